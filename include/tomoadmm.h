@@ -1,0 +1,191 @@
+/*
+ * tomoadmm.h -- C ABI of the MI355X (gfx950) library for decentralized ADMM
+ * tomographic reconstruction with quantized exchange.
+ *
+ * Method: "Distributed Tomographic Reconstruction with Quantization"
+ * (arXiv 2410.06106).  The library computes, on one GPU, the per-node work of
+ * the paper's decentralized ADMM: the local u-update (Alg. 2), the segment
+ * x-update (Alg. 3) or the averaging x-update (Eq. 9), the quantizer Q of the
+ * exchanged segments (Alg. 5 and the JPEG-style codec), the concatenation
+ * (Eq. 23) and the dual update (Eq. 24).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every array argument is a DEVICE pointer owned by the caller (for example
+ *   the storage of a torch tensor).  The library never frees caller memory.
+ * - Images are float32 [n][n], row-major.  Pixel (r, c) has its centre at
+ *   x = c - (n-1)/2, y = r - (n-1)/2 in pixel units; y grows with the row index.
+ * - Sinograms are float32 [n_ang][n_bins], row-major; bin b is centred at
+ *   t = b - (n_bins-1)/2.  Angles are float64 radians; the ray (theta, t) is the
+ *   line x cos(theta) + y sin(theta) = t (Section 2.1, Eq. 1).
+ * - System matrix (Eq. 2-4, Joseph linear-interpolation discretisation):
+ *     P[(theta,b),(r,c)] = max(0, 1 - |t_b - t_rc| / c_theta) / c_theta,
+ *     t_rc = x_c cos(theta) + y_r sin(theta), c_theta = max(|cos|, |sin|).
+ * - `stream` is a hipStream_t (NULL = the legacy default stream).  Every call
+ *   only enqueues work on that stream and returns; nothing blocks the host
+ *   except the first use of a new node list (see admm_local_update).
+ * - Return value: TOMO_OK, or an error code.  Argument errors (TOMO_EINVAL) are
+ *   detected on the host before anything is enqueued.  A failed kernel launch
+ *   returns TOMO_EDEVICE.  tomo_last_error() describes the latest failure of a
+ *   context in words.  No C++ exception crosses this interface.
+ * - A context owns reusable device workspace.  Calls made with one context must
+ *   be issued from one host thread and ordered on one stream at a time.
+ */
+#ifndef TOMOADMM_H
+#define TOMOADMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tomo_ctx tomo_ctx;
+
+enum {
+  TOMO_OK = 0,
+  TOMO_EINVAL = 1,        /* bad argument, checked on the host                 */
+  TOMO_ENOMEM = 2,        /* device workspace could not be allocated            */
+  TOMO_EDEVICE = 3,       /* HIP runtime or kernel launch failure               */
+  TOMO_EUNSUPPORTED = 4   /* valid request this build does not handle           */
+};
+
+/* Create a context bound to HIP device `device`.  *ctx receives the handle. */
+int tomo_create(tomo_ctx** ctx, int device);
+/* Release the context and its workspace (waits for its pending work). */
+int tomo_destroy(tomo_ctx* ctx);
+/* Static text for a status code. */
+const char* tomo_status_string(int status);
+/* Text of the latest error recorded on `ctx` ("" if none). */
+const char* tomo_last_error(const tomo_ctx* ctx);
+
+typedef struct {
+  int32_t n;       /* image side: the image is n x n pixels (1 <= n <= 4096) */
+  int32_t n_bins;  /* detector bins per angle (n_bins >= 1)                  */
+} tomo_geom;
+
+/*
+ * Forward projection d = P u (Eq. 2-4) over `n_ang` angles.
+ *   angles: float64 [n_ang];  image: float32 [n][n];  sino: float32 [n_ang][n_bins]
+ * sino is overwritten.  image and sino must not overlap.  n_ang == 0 is a no-op.
+ */
+int tomo_project(tomo_ctx* ctx, tomo_geom g, const double* angles, int32_t n_ang,
+                 const float* image, float* sino, void* stream);
+
+/*
+ * Matched backprojection, the exact transpose of tomo_project:
+ *   image = alpha * P^T sino + beta * image
+ * (image is not read when beta == 0).  Same layouts as tomo_project.
+ */
+int tomo_backproject(tomo_ctx* ctx, tomo_geom g, const double* angles, int32_t n_ang,
+                     const float* sino, float* image, float alpha, float beta, void* stream);
+
+/*
+ * One node of the decentralized problem (Eq. 6-7): its angles and data d_m,
+ * its local image u_m and dual variable lambda_m, the slice-wide consensus image
+ * x, and the segment x[m] it owns (rows seg_row0 .. seg_row0+seg_rows-1 of x,
+ * Eq. 13/17).  Nodes of one slice share `x` and must be adjacent in a node list.
+ */
+typedef struct {
+  tomo_geom g;
+  const double* angles;   /* float64 [n_ang]                                   */
+  int32_t n_ang;          /* >= 1                                              */
+  int32_t slice;          /* slice id; equal ids <=> same x                     */
+  const float* d;         /* float32 [n_ang][n_bins]  node data d_m             */
+  float* u;               /* float32 [n][n]  u_m, updated in place              */
+  float* lam;             /* float32 [n][n]  lambda_m, updated in place         */
+  float* x;               /* float32 [n][n]  consensus image of the slice       */
+  int32_t seg_row0;       /* first row of the owned segment                     */
+  int32_t seg_rows;       /* rows in the owned segment (>= 1)                   */
+  float rho;              /* penalty (> 0)                                      */
+  float eta1;             /* step of Alg. 2                                     */
+  float eta2;             /* step of Alg. 3                                     */
+  int32_t reserved;       /* must be 0 (keeps the struct free of padding)       */
+} tomo_node;
+
+/*
+ * Alg. 2 for every listed node: E1 steps of
+ *   u_m <- u_m - eta1 * ( P_m^T (P_m u_m - d_m) + rho (u_m - x) + lambda_m )
+ * starting from the current u_m (zero it before the first outer iteration).
+ * n_nodes > 1 runs all nodes in one launch per step.  The first call with a
+ * given node list (compared by value) builds a plan: it allocates workspace and
+ * copies descriptors to the device synchronously, so capture a stream into a
+ * graph only after one uncaptured call with the same list.
+ */
+int admm_local_update(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, int32_t e1,
+                      void* stream);
+
+enum { TOMO_XUPDATE_SEGMENT = 0, TOMO_XUPDATE_AVERAGE = 1 };
+enum { TOMO_QUANT_NONE = 0, TOMO_QUANT_KMEANS = 1, TOMO_QUANT_DCT = 2 };
+
+typedef struct {
+  int32_t kind;      /* TOMO_QUANT_*                                             */
+  int32_t levels;    /* K-means clusters, 1..256                                 */
+  int32_t max_iter;  /* K-means Lloyd iteration cap (>= 0)                       */
+  int32_t quality;   /* DCT quality factor, 1..100                               */
+} tomo_quant;
+
+/* Optional per-node message buffers (device pointers, each may be NULL). */
+typedef struct {
+  uint8_t* labels;     /* K-means: uint8 [seg_rows*n] cluster index per value    */
+  float* centroids;    /* K-means: float32 [levels]                              */
+  int32_t* iters;      /* K-means: int32 [1] Lloyd iterations run                */
+  int16_t* coeffs;     /* DCT: int16 [seg_rows][n] quantized coefficients        */
+  float* lohi;         /* DCT: float32 [2] level-map range                       */
+} tomo_msg;
+
+/*
+ * Consensus, exchange and dual steps of one outer iteration, for every listed
+ * node (all nodes of each listed slice must be present):
+ *   mode TOMO_XUPDATE_SEGMENT: node m runs Alg. 3 on its own segment, E2 steps
+ *     x[m] <- x[m] - eta2 * rho * (x[m] - u_m[m] - lambda_m[m]/rho), from x^k[m];
+ *   mode TOMO_XUPDATE_AVERAGE: x = mean_m (u_m + lambda_m/rho) (Eq. 9, E2 unused);
+ * then each segment is replaced by Q(segment) in place (Eq. 23), and finally
+ *   lambda_m <- lambda_m + rho (u_m - x)   for every node (Eq. 24).
+ * q == NULL means no quantization.  msg == NULL or an array of n_nodes entries.
+ * K-means requires seg_rows*n <= 2^22 values per segment; DCT requires seg_rows
+ * and n to be multiples of 8.
+ */
+int admm_consensus(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, int32_t mode,
+                   int32_t e2, const tomo_quant* q, const tomo_msg* msg, void* stream);
+
+/*
+ * Scalar K-means quantizer (Alg. 5) of a float32 vector a[n], bit-exact:
+ *  lo,hi = min,max (NaN/Inf -> TOMO_EINVAL is NOT detectable on the host: the
+ *  kernel then writes iters = -1 and leaves the outputs unspecified);
+ *  centres start at lo + (hi-lo)(2j+1)/(2k) (float64, no FMA, rounded to float32);
+ *  values enter the centroid sums as int64 fixed point round(a * 2^S),
+ *  S = 40 - e (n <= 2^22), e the binary exponent of max(|lo|,|hi|);
+ *  label = lowest j minimising |a - c_j| in float32; Lloyd iterations until the
+ *  labels repeat or max_iter.  hi == lo: labels 0, centres lo, iters 0.
+ * Outputs: labels uint8 [n], centroids float32 [k], a_hat float32 [n] (nullable,
+ * may alias a), iters int32 [1] (nullable).  1 <= k <= 256, 1 <= n <= 2^22.
+ */
+int quantize_kmeans(tomo_ctx* ctx, const float* a, int64_t n, int32_t k, int32_t max_iter,
+                    uint8_t* labels, float* centroids, float* a_hat, int32_t* iters, void* stream);
+
+/*
+ * JPEG-style quantizer of a float32 matrix a[rows][cols] with leading dimension
+ * ld (elements): per-matrix level map v = (a-lo)*255/(hi-lo) - 128, orthonormal
+ * 8x8 DCT-II per block, codes = round-half-even(F / Qs) with Qs the ITU-T T.81
+ * Table K.1 luminance table scaled to `quality` (scale 5000/q below 50, else
+ * 200-2q; step = clamp(floor((T*scale+50)/100), 1, 255)), dequantize, inverse
+ * DCT, unmap.  rows, cols multiples of 8.  Outputs: a_hat float32 [rows][ld]
+ * (may alias a), coeffs int16 [rows][cols] (nullable), lohi float32 [2]
+ * (nullable).  hi == lo: a_hat = a, coeffs 0.
+ */
+int quantize_dct(tomo_ctx* ctx, const float* a, int32_t rows, int32_t cols, int32_t ld,
+                 int32_t quality, int16_t* coeffs, float* a_hat, float* lohi, void* stream);
+
+/*
+ * Sum of squared differences sum_i (a_i - b_i)^2 accumulated in float64 into
+ * out[0] (overwritten).  Used for RMSE (Eq. 25) and relative-change traces.
+ */
+int tomo_sqdiff(tomo_ctx* ctx, const float* a, const float* b, int64_t n, double* out,
+                void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TOMOADMM_H */

@@ -1,0 +1,507 @@
+// C ABI of the tomoadmm library: argument checks, workspace and plans, launches.
+#include <algorithm>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "../../include/tomoadmm.h"
+
+namespace tomo {
+template <class Src> __global__ void k_project(Src);
+template <class Src> __global__ void k_backproject(Src);
+__global__ void k_seg_none(const SegJob*, int, int);
+__global__ void k_seg_kmeans(const SegJob*, int, int, int, int, uint8_t*, long long);
+__global__ void k_seg_dct(const SegJob*, int, int, int);
+__global__ void k_kmeans(const float*, long long, int, int, uint8_t*, float*, float*, int32_t*);
+__global__ void k_dct(const float*, int, int, int, int, int16_t*, float*, float*);
+__global__ void k_avg(Many<AvgJob>, const NodeRef*);
+__global__ void k_dual(Many<NodeRef>);
+__global__ void k_sqdiff(const float*, const float*, long long, double*);
+}  // namespace tomo
+
+using namespace tomo;
+
+static_assert(sizeof(tomo_node) == 80, "tomo_node must have no padding (plans compare it bytewise)");
+static_assert(sizeof(tomo_msg) == 40, "tomo_msg must have no padding");
+
+namespace {
+
+constexpr int kTargetProjWGs = 1024;   // workgroups wanted per projector launch
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~DevBuf() { if (p) (void)hipFree(p); }
+  bool ensure(size_t want) {
+    if (want <= bytes) return true;
+    if (p) { (void)hipFree(p); p = nullptr; bytes = 0; }
+    if (hipMalloc(&p, want) != hipSuccess) { p = nullptr; return false; }
+    bytes = want;
+    return true;
+  }
+};
+
+// Projector decomposition of one job: angle chunks x regions.
+struct ProjShape {
+  int n_achunk, reg_h, reg_w, n_rr, n_rc;
+  int wgs() const { return n_achunk * n_rr * n_rc; }
+  int regions() const { return n_rr * n_rc; }
+};
+
+ProjShape base_shape(int n, int n_ang) {
+  ProjShape s;
+  s.n_achunk = (n_ang + PA - 1) / PA;
+  s.reg_h = s.reg_w = std::min(n, PREG);
+  s.n_rr = s.n_rc = (n + s.reg_h - 1) / s.reg_h;
+  return s;
+}
+
+// Halve regions of every job (rows first) until the launch has enough
+// workgroups, keeping regions at least 64 pixels on a side.
+void split_for_parallelism(std::vector<ProjShape>& shapes, const std::vector<int>& ns) {
+  for (int round = 0; round < 8; ++round) {
+    long total = 0;
+    for (auto& s : shapes) total += s.wgs();
+    if (total >= kTargetProjWGs) return;
+    bool changed = false;
+    for (size_t i = 0; i < shapes.size(); ++i) {
+      ProjShape& s = shapes[i];
+      int n = ns[i];
+      if (s.regions() >= 64) continue;
+      if (s.reg_h >= s.reg_w && s.reg_h >= 128) {
+        s.reg_h /= 2; s.n_rr = (n + s.reg_h - 1) / s.reg_h; changed = true;
+      } else if (s.reg_w >= 128) {
+        s.reg_w /= 2; s.n_rc = (n + s.reg_w - 1) / s.reg_w; changed = true;
+      }
+    }
+    if (!changed) return;
+  }
+}
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  auto pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
+  return pa < pb + nb && pb < pa + na;
+}
+
+struct LocalPlan {
+  std::vector<tomo_node> key;
+  DevBuf pjobs, bjobs, resid, partial, tickets;
+  int n_p = 0, p_wgs = 0, n_b = 0, b_wgs = 0;
+};
+
+struct ConsPlan {
+  std::vector<tomo_node> key;
+  std::vector<tomo_msg> msg_key;
+  DevBuf seg, avg, noderefs, labels;
+  int n_seg = 0, n_avg = 0, avg_wgs = 0, dual_wgs = 0;
+  long long label_stride = 0;
+};
+
+bool same_nodes(const std::vector<tomo_node>& k, const tomo_node* nodes, int n) {
+  return (int)k.size() == n && std::memcmp(k.data(), nodes, sizeof(tomo_node) * n) == 0;
+}
+
+}  // namespace
+
+struct tomo_ctx {
+  int device = 0;
+  std::string err;
+  DevBuf partial, tickets;                       // standalone projector workspace
+  std::vector<std::unique_ptr<LocalPlan>> lplans;
+  std::vector<std::unique_ptr<ConsPlan>> cplans;
+  int fail(int code, const std::string& msg) { err = msg; return code; }
+};
+
+namespace {
+
+int launch_status(tomo_ctx* ctx, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return ctx->fail(TOMO_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  return TOMO_OK;
+}
+
+int set_device(tomo_ctx* ctx) {
+  if (hipSetDevice(ctx->device) != hipSuccess) return ctx->fail(TOMO_EDEVICE, "hipSetDevice failed");
+  return TOMO_OK;
+}
+
+int check_geom(tomo_ctx* ctx, tomo_geom g) {
+  if (g.n < 1 || g.n_bins < 1) return ctx->fail(TOMO_EINVAL, "geometry needs n >= 1 and n_bins >= 1");
+  // the projector's finalizer holds at most 64 regions of <= 512 x 512 pixels
+  if (g.n > 8 * PREG || (long long)g.n_bins > (1 << 24))
+    return ctx->fail(TOMO_EUNSUPPORTED, "image side above 4096 or more than 2^24 bins");
+  return TOMO_OK;
+}
+
+ProjJob make_proj_job(const float* img, const double* ang, const float* d, float* out, int n, int nb,
+                      int n_ang, const ProjShape& s) {
+  ProjJob j{};
+  j.img = img; j.ang = ang; j.d = d; j.out = out;
+  j.n = n; j.nb = nb; j.n_ang = n_ang;
+  j.n_achunk = s.n_achunk;
+  j.reg_h = s.reg_h; j.reg_w = s.reg_w; j.n_rr = s.n_rr; j.n_rc = s.n_rc;
+  j.scale = 1.f;
+  return j;
+}
+
+BPJob make_bp_job(const float* sino, const double* ang, float* img, int n, int nb, int n_ang) {
+  BPJob j{};
+  j.sino = sino; j.ang = ang; j.img = img;
+  j.n = n; j.nb = nb; j.n_ang = n_ang;
+  j.tiles_x = (n + BT - 1) / BT;
+  return j;
+}
+
+int check_nodes(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes) {
+  if (!nodes || n_nodes < 1) return ctx->fail(TOMO_EINVAL, "empty node list");
+  for (int i = 0; i < n_nodes; ++i) {
+    const tomo_node& N = nodes[i];
+    if (int rc = check_geom(ctx, N.g)) return rc;
+    if (N.n_ang < 1) return ctx->fail(TOMO_EINVAL, "node without angles");
+    if (!N.angles || !N.d || !N.u || !N.lam || !N.x) return ctx->fail(TOMO_EINVAL, "null node pointer");
+    if (N.seg_row0 < 0 || N.seg_rows < 1 || N.seg_row0 + N.seg_rows > N.g.n)
+      return ctx->fail(TOMO_EINVAL, "segment outside the image");
+    if (!(N.rho > 0.f)) return ctx->fail(TOMO_EINVAL, "rho must be positive");
+    size_t img = (size_t)N.g.n * N.g.n * sizeof(float);
+    if (overlaps(N.u, img, N.lam, img) || overlaps(N.u, img, N.x, img) || overlaps(N.lam, img, N.x, img))
+      return ctx->fail(TOMO_EINVAL, "u, lambda and x must not overlap");
+    if (i > 0 && nodes[i - 1].slice == N.slice) {
+      if (nodes[i - 1].x != N.x || nodes[i - 1].g.n != N.g.n)
+        return ctx->fail(TOMO_EINVAL, "nodes of one slice must share x and n");
+    }
+  }
+  std::vector<int32_t> starts;   // first slice id of every run of equal ids
+  for (int i = 0; i < n_nodes; ++i)
+    if (i == 0 || nodes[i - 1].slice != nodes[i].slice) starts.push_back(nodes[i].slice);
+  std::sort(starts.begin(), starts.end());
+  if (std::adjacent_find(starts.begin(), starts.end()) != starts.end())
+    return ctx->fail(TOMO_EINVAL, "nodes of one slice must be adjacent");
+  return TOMO_OK;
+}
+
+LocalPlan* find_local_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes) {
+  for (auto& p : ctx->lplans)
+    if (same_nodes(p->key, nodes, n_nodes)) return p.get();
+  return nullptr;
+}
+
+LocalPlan* get_local_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, int& rc) {
+  rc = TOMO_OK;
+  if (LocalPlan* p = find_local_plan(ctx, nodes, n_nodes)) return p;
+  auto plan = std::make_unique<LocalPlan>();
+  plan->key.assign(nodes, nodes + n_nodes);
+  std::vector<ProjShape> shapes;
+  std::vector<int> ns;
+  size_t resid_elems = 0, part_elems = 0, tick_elems = 0;
+  for (int i = 0; i < n_nodes; ++i) {
+    shapes.push_back(base_shape(nodes[i].g.n, nodes[i].n_ang));
+    ns.push_back(nodes[i].g.n);
+  }
+  split_for_parallelism(shapes, ns);
+  std::vector<size_t> roff(n_nodes), poff(n_nodes), toff(n_nodes);
+  for (int i = 0; i < n_nodes; ++i) {
+    roff[i] = resid_elems;
+    resid_elems += (size_t)nodes[i].n_ang * nodes[i].g.n_bins;
+    poff[i] = part_elems;
+    if (shapes[i].regions() > 1) part_elems += (size_t)shapes[i].wgs() * PA * PACC;
+    toff[i] = tick_elems;
+    tick_elems += shapes[i].n_achunk;
+  }
+  if (!plan->resid.ensure(resid_elems * 4) || !plan->partial.ensure(std::max<size_t>(part_elems, 1) * 4) ||
+      !plan->tickets.ensure(tick_elems * 4)) {
+    rc = ctx->fail(TOMO_ENOMEM, "plan workspace allocation failed");
+    return nullptr;
+  }
+  if (hipMemset(plan->tickets.p, 0, tick_elems * 4) != hipSuccess) {
+    rc = ctx->fail(TOMO_EDEVICE, "hipMemset failed");
+    return nullptr;
+  }
+  std::vector<ProjJob> pj;
+  std::vector<BPJob> bj;
+  int pw = 0, bw = 0;
+  float* R = static_cast<float*>(plan->resid.p);
+  float* PP = static_cast<float*>(plan->partial.p);
+  unsigned* T = static_cast<unsigned*>(plan->tickets.p);
+  for (int i = 0; i < n_nodes; ++i) {
+    const tomo_node& N = nodes[i];
+    ProjJob j = make_proj_job(N.u, N.angles, N.d, R + roff[i], N.g.n, N.g.n_bins, N.n_ang, shapes[i]);
+    j.partial = PP + poff[i];
+    j.ticket = T + toff[i];
+    j.wg_begin = pw;
+    pw += shapes[i].wgs();
+    pj.push_back(j);
+    BPJob b = make_bp_job(R + roff[i], N.angles, N.u, N.g.n, N.g.n_bins, N.n_ang);
+    b.mode = BP_ADMM;
+    b.x = N.x;
+    b.lam = N.lam;
+    b.rho = N.rho;
+    b.eta1 = N.eta1;
+    b.wg_begin = bw;
+    bw += b.tiles_x * b.tiles_x;
+    bj.push_back(b);
+  }
+  if (!plan->pjobs.ensure(pj.size() * sizeof(ProjJob)) || !plan->bjobs.ensure(bj.size() * sizeof(BPJob))) {
+    rc = ctx->fail(TOMO_ENOMEM, "plan descriptor allocation failed");
+    return nullptr;
+  }
+  if (hipMemcpy(plan->pjobs.p, pj.data(), pj.size() * sizeof(ProjJob), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(plan->bjobs.p, bj.data(), bj.size() * sizeof(BPJob), hipMemcpyHostToDevice) != hipSuccess) {
+    rc = ctx->fail(TOMO_EDEVICE, "descriptor upload failed");
+    return nullptr;
+  }
+  plan->n_p = (int)pj.size();
+  plan->p_wgs = pw;
+  plan->n_b = (int)bj.size();
+  plan->b_wgs = bw;
+  ctx->lplans.push_back(std::move(plan));
+  return ctx->lplans.back().get();
+}
+
+bool same_msg(const std::vector<tomo_msg>& k, const tomo_msg* msg, int n) {
+  if (!msg) return k.empty();
+  return (int)k.size() == n && std::memcmp(k.data(), msg, sizeof(tomo_msg) * n) == 0;
+}
+
+ConsPlan* get_cons_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, const tomo_msg* msg, int& rc) {
+  rc = TOMO_OK;
+  for (auto& p : ctx->cplans)
+    if (same_nodes(p->key, nodes, n_nodes) && same_msg(p->msg_key, msg, n_nodes)) return p.get();
+  auto plan = std::make_unique<ConsPlan>();
+  plan->key.assign(nodes, nodes + n_nodes);
+  if (msg) plan->msg_key.assign(msg, msg + n_nodes);
+  std::vector<SegJob> seg;
+  std::vector<AvgJob> avg;
+  std::vector<NodeRef> refs;
+  long long max_seg = 0;
+  int aw = 0, dw = 0;
+  for (int i = 0; i < n_nodes; ++i) {
+    const tomo_node& N = nodes[i];
+    SegJob s{};
+    s.x = N.x; s.u = N.u; s.lam = N.lam;
+    s.n = N.g.n; s.row0 = N.seg_row0; s.rows = N.seg_rows;
+    s.rho = N.rho; s.eta2 = N.eta2;
+    if (msg) {
+      s.labels = msg[i].labels; s.centroids = msg[i].centroids; s.iters = msg[i].iters;
+      s.coeffs = msg[i].coeffs; s.lohi = msg[i].lohi;
+    }
+    seg.push_back(s);
+    max_seg = std::max(max_seg, (long long)N.seg_rows * N.g.n);
+    NodeRef r{};
+    r.u = N.u; r.lam = N.lam; r.x = N.x; r.n = N.g.n; r.rho = N.rho;
+    r.wg_begin = dw;
+    dw += (int)(((long long)N.g.n * N.g.n + 255) / 256);
+    refs.push_back(r);
+    if (i == 0 || nodes[i - 1].slice != N.slice) {
+      AvgJob a{};
+      a.x = N.x; a.node0 = i; a.n_nodes = 0; a.n = N.g.n; a.wg_begin = aw;
+      aw += (int)(((long long)N.g.n * N.g.n + 255) / 256);
+      avg.push_back(a);
+    }
+    avg.back().n_nodes++;
+  }
+  plan->label_stride = (max_seg + 255) / 256 * 256;
+  if (!plan->seg.ensure(seg.size() * sizeof(SegJob)) || !plan->avg.ensure(avg.size() * sizeof(AvgJob)) ||
+      !plan->noderefs.ensure(refs.size() * sizeof(NodeRef)) ||
+      !plan->labels.ensure((size_t)plan->label_stride * n_nodes)) {
+    rc = ctx->fail(TOMO_ENOMEM, "consensus plan allocation failed");
+    return nullptr;
+  }
+  if (hipMemcpy(plan->seg.p, seg.data(), seg.size() * sizeof(SegJob), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(plan->avg.p, avg.data(), avg.size() * sizeof(AvgJob), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(plan->noderefs.p, refs.data(), refs.size() * sizeof(NodeRef), hipMemcpyHostToDevice) != hipSuccess) {
+    rc = ctx->fail(TOMO_EDEVICE, "descriptor upload failed");
+    return nullptr;
+  }
+  plan->n_seg = (int)seg.size();
+  plan->n_avg = (int)avg.size();
+  plan->avg_wgs = aw;
+  plan->dual_wgs = dw;
+  ctx->cplans.push_back(std::move(plan));
+  return ctx->cplans.back().get();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* tomo_status_string(int status) {
+  switch (status) {
+    case TOMO_OK: return "ok";
+    case TOMO_EINVAL: return "invalid argument";
+    case TOMO_ENOMEM: return "out of device memory";
+    case TOMO_EDEVICE: return "device error";
+    case TOMO_EUNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+const char* tomo_last_error(const tomo_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int tomo_create(tomo_ctx** out, int device) {
+  if (!out) return TOMO_EINVAL;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return TOMO_EDEVICE;
+  if (hipSetDevice(device) != hipSuccess) return TOMO_EDEVICE;
+  tomo_ctx* c = new (std::nothrow) tomo_ctx();
+  if (!c) return TOMO_ENOMEM;
+  c->device = device;
+  *out = c;
+  return TOMO_OK;
+}
+
+int tomo_destroy(tomo_ctx* ctx) {
+  if (!ctx) return TOMO_EINVAL;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  delete ctx;
+  return TOMO_OK;
+}
+
+int tomo_project(tomo_ctx* ctx, tomo_geom g, const double* angles, int32_t n_ang, const float* image,
+                 float* sino, void* stream) {
+  if (!ctx) return TOMO_EINVAL;
+  if (int rc = check_geom(ctx, g)) return rc;
+  if (n_ang < 0) return ctx->fail(TOMO_EINVAL, "n_ang < 0");
+  if (n_ang == 0) return TOMO_OK;
+  if (!angles || !image || !sino) return ctx->fail(TOMO_EINVAL, "null pointer");
+  if (overlaps(image, (size_t)g.n * g.n * 4, sino, (size_t)n_ang * g.n_bins * 4))
+    return ctx->fail(TOMO_EINVAL, "image and sino overlap");
+  if (int rc = set_device(ctx)) return rc;
+  std::vector<ProjShape> sh{base_shape(g.n, n_ang)};
+  split_for_parallelism(sh, {g.n});
+  ProjJob j = make_proj_job(image, angles, nullptr, sino, g.n, g.n_bins, n_ang, sh[0]);
+  if (sh[0].regions() > 1) {
+    if (!ctx->partial.ensure((size_t)sh[0].wgs() * PA * PACC * 4)) return ctx->fail(TOMO_ENOMEM, "workspace");
+    size_t had = ctx->tickets.bytes;
+    if (!ctx->tickets.ensure((size_t)sh[0].n_achunk * 4)) return ctx->fail(TOMO_ENOMEM, "workspace");
+    if (ctx->tickets.bytes != had && hipMemset(ctx->tickets.p, 0, ctx->tickets.bytes) != hipSuccess)
+      return ctx->fail(TOMO_EDEVICE, "hipMemset failed");
+    j.partial = static_cast<float*>(ctx->partial.p);
+    j.ticket = static_cast<unsigned*>(ctx->tickets.p);
+  }
+  hipLaunchKernelGGL(k_project<Single<ProjJob>>, dim3(sh[0].wgs()), dim3(PTHREADS), 0,
+                     (hipStream_t)stream, Single<ProjJob>{j});
+  return launch_status(ctx, "tomo_project");
+}
+
+int tomo_backproject(tomo_ctx* ctx, tomo_geom g, const double* angles, int32_t n_ang, const float* sino,
+                     float* image, float alpha, float beta, void* stream) {
+  if (!ctx) return TOMO_EINVAL;
+  if (int rc = check_geom(ctx, g)) return rc;
+  if (n_ang < 0) return ctx->fail(TOMO_EINVAL, "n_ang < 0");
+  if (!image || (n_ang > 0 && (!angles || !sino))) return ctx->fail(TOMO_EINVAL, "null pointer");
+  if (n_ang > 0 && overlaps(image, (size_t)g.n * g.n * 4, sino, (size_t)n_ang * g.n_bins * 4))
+    return ctx->fail(TOMO_EINVAL, "image and sino overlap");
+  if (int rc = set_device(ctx)) return rc;
+  BPJob j = make_bp_job(sino, angles, image, g.n, g.n_bins, n_ang);
+  j.mode = BP_PLAIN;
+  j.alpha = alpha;
+  j.beta = beta;
+  hipLaunchKernelGGL(k_backproject<Single<BPJob>>, dim3(j.tiles_x * j.tiles_x), dim3(BTHREADS), 0,
+                     (hipStream_t)stream, Single<BPJob>{j});
+  return launch_status(ctx, "tomo_backproject");
+}
+
+int admm_local_update(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, int32_t e1, void* stream) {
+  if (!ctx) return TOMO_EINVAL;
+  if (e1 < 0) return ctx->fail(TOMO_EINVAL, "E1 < 0");
+  if (!nodes || n_nodes < 1) return ctx->fail(TOMO_EINVAL, "empty node list");
+  if (int rc = set_device(ctx)) return rc;
+  int rc = TOMO_OK;
+  LocalPlan* plan = find_local_plan(ctx, nodes, n_nodes);
+  if (!plan) {
+    if (int rc2 = check_nodes(ctx, nodes, n_nodes)) return rc2;
+    plan = get_local_plan(ctx, nodes, n_nodes, rc);
+  }
+  if (!plan) return rc;
+  Many<ProjJob> ps{static_cast<const ProjJob*>(plan->pjobs.p), plan->n_p};
+  Many<BPJob> bs{static_cast<const BPJob*>(plan->bjobs.p), plan->n_b};
+  for (int e = 0; e < e1; ++e) {
+    hipLaunchKernelGGL(k_project<Many<ProjJob>>, dim3(plan->p_wgs), dim3(PTHREADS), 0, (hipStream_t)stream, ps);
+    hipLaunchKernelGGL(k_backproject<Many<BPJob>>, dim3(plan->b_wgs), dim3(BTHREADS), 0, (hipStream_t)stream, bs);
+  }
+  return launch_status(ctx, "admm_local_update");
+}
+
+int admm_consensus(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, int32_t mode, int32_t e2,
+                   const tomo_quant* q, const tomo_msg* msg, void* stream) {
+  if (!ctx) return TOMO_EINVAL;
+  if (mode != TOMO_XUPDATE_SEGMENT && mode != TOMO_XUPDATE_AVERAGE) return ctx->fail(TOMO_EINVAL, "bad mode");
+  if (e2 < 0) return ctx->fail(TOMO_EINVAL, "E2 < 0");
+  if (int rc = check_nodes(ctx, nodes, n_nodes)) return rc;
+  int kind = q ? q->kind : TOMO_QUANT_NONE;
+  if (kind < TOMO_QUANT_NONE || kind > TOMO_QUANT_DCT) return ctx->fail(TOMO_EINVAL, "bad quantizer");
+  for (int i = 0; i < n_nodes; ++i) {
+    long long segn = (long long)nodes[i].seg_rows * nodes[i].g.n;
+    if (kind == TOMO_QUANT_KMEANS && (q->levels < 1 || q->levels > 256 || q->max_iter < 0 || segn > (1ll << 31)))
+      return ctx->fail(TOMO_EINVAL, "bad K-means parameters");
+    if (kind == TOMO_QUANT_DCT && (q->quality < 1 || q->quality > 100 || nodes[i].seg_rows % 8 || nodes[i].g.n % 8))
+      return ctx->fail(TOMO_EINVAL, "bad DCT parameters (quality 1..100, segment sides multiples of 8)");
+  }
+  if (int rc = set_device(ctx)) return rc;
+  int rc = TOMO_OK;
+  ConsPlan* plan = get_cons_plan(ctx, nodes, n_nodes, msg, rc);
+  if (!plan) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const SegJob* seg = static_cast<const SegJob*>(plan->seg.p);
+  const NodeRef* refs = static_cast<const NodeRef*>(plan->noderefs.p);
+  const int do_x = mode == TOMO_XUPDATE_SEGMENT;
+  if (mode == TOMO_XUPDATE_AVERAGE) {
+    Many<AvgJob> as{static_cast<const AvgJob*>(plan->avg.p), plan->n_avg};
+    hipLaunchKernelGGL(k_avg, dim3(plan->avg_wgs), dim3(256), 0, s, as, refs);
+  }
+  if (kind == TOMO_QUANT_KMEANS) {
+    hipLaunchKernelGGL(k_seg_kmeans, dim3(plan->n_seg), dim3(1024), 0, s, seg, do_x, e2, q->levels, q->max_iter,
+                       static_cast<uint8_t*>(plan->labels.p), plan->label_stride);
+  } else if (kind == TOMO_QUANT_DCT) {
+    hipLaunchKernelGGL(k_seg_dct, dim3(plan->n_seg), dim3(256), 0, s, seg, do_x, e2, q->quality);
+  } else if (do_x) {
+    hipLaunchKernelGGL(k_seg_none, dim3(plan->n_seg), dim3(256), 0, s, seg, do_x, e2);
+  }
+  Many<NodeRef> ds{refs, n_nodes};
+  hipLaunchKernelGGL(k_dual, dim3(plan->dual_wgs), dim3(256), 0, s, ds);
+  return launch_status(ctx, "admm_consensus");
+}
+
+int quantize_kmeans(tomo_ctx* ctx, const float* a, int64_t n, int32_t k, int32_t max_iter, uint8_t* labels,
+                    float* centroids, float* a_hat, int32_t* iters, void* stream) {
+  if (!ctx) return TOMO_EINVAL;
+  if (n < 1 || n > (1ll << 31)) return ctx->fail(TOMO_EINVAL, "n must lie in [1, 2^31]");
+  if (k < 1 || k > 256 || max_iter < 0) return ctx->fail(TOMO_EINVAL, "k must lie in [1, 256], max_iter >= 0");
+  if (!a || !labels || !centroids) return ctx->fail(TOMO_EINVAL, "null pointer");
+  if (a_hat && a_hat != a && overlaps(a, (size_t)n * 4, a_hat, (size_t)n * 4))
+    return ctx->fail(TOMO_EINVAL, "a_hat partially overlaps a");
+  if (int rc = set_device(ctx)) return rc;
+  hipLaunchKernelGGL(k_kmeans, dim3(1), dim3(1024), 0, (hipStream_t)stream, a, (long long)n, k, max_iter, labels,
+                     centroids, a_hat, iters);
+  return launch_status(ctx, "quantize_kmeans");
+}
+
+int quantize_dct(tomo_ctx* ctx, const float* a, int32_t rows, int32_t cols, int32_t ld, int32_t quality,
+                 int16_t* coeffs, float* a_hat, float* lohi, void* stream) {
+  if (!ctx) return TOMO_EINVAL;
+  if (rows < 8 || cols < 8 || rows % 8 || cols % 8 || ld < cols)
+    return ctx->fail(TOMO_EINVAL, "rows, cols must be positive multiples of 8 and ld >= cols");
+  if (quality < 1 || quality > 100) return ctx->fail(TOMO_EINVAL, "quality must lie in [1, 100]");
+  if (!a || !a_hat) return ctx->fail(TOMO_EINVAL, "null pointer");
+  if (a_hat != a && overlaps(a, (size_t)rows * ld * 4, a_hat, (size_t)rows * ld * 4))
+    return ctx->fail(TOMO_EINVAL, "a_hat partially overlaps a");
+  if (int rc = set_device(ctx)) return rc;
+  hipLaunchKernelGGL(k_dct, dim3(1), dim3(256), 0, (hipStream_t)stream, a, rows, cols, ld, quality, coeffs, a_hat,
+                     lohi);
+  return launch_status(ctx, "quantize_dct");
+}
+
+int tomo_sqdiff(tomo_ctx* ctx, const float* a, const float* b, int64_t n, double* out, void* stream) {
+  if (!ctx) return TOMO_EINVAL;
+  if (n < 0 || !a || !b || !out) return ctx->fail(TOMO_EINVAL, "bad arguments");
+  if (int rc = set_device(ctx)) return rc;
+  hipLaunchKernelGGL(k_sqdiff, dim3(1), dim3(1024), 0, (hipStream_t)stream, a, b, (long long)n, out);
+  return launch_status(ctx, "tomo_sqdiff");
+}
+
+}  // extern "C"

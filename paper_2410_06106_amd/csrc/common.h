@@ -1,0 +1,128 @@
+// Shared device-side definitions of the tomoadmm HIP library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tomo {
+
+// ---------------------------------------------------------------------------
+// Work descriptors.  A launch processes one descriptor passed by value
+// (Single) or many descriptors in device memory (Many); a descriptor owns the
+// contiguous range of workgroup ids [wg_begin, wg_begin + its WG count).
+// ---------------------------------------------------------------------------
+template <class Job>
+struct Single {
+  Job job;
+  __device__ __forceinline__ Job get(int bid, int& lid) const {
+    lid = bid;
+    return job;
+  }
+};
+
+template <class Job>
+struct Many {
+  const Job* jobs;
+  int n_jobs;
+  __device__ __forceinline__ Job get(int bid, int& lid) const {
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {  // last job with wg_begin <= bid (uniform across the WG)
+      int mid = (lo + hi + 1) >> 1;
+      if (jobs[mid].wg_begin <= bid) lo = mid; else hi = mid - 1;
+    }
+    Job j = jobs[lo];
+    lid = bid - j.wg_begin;
+    return j;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Forward projector: one job = one image and one set of angles.
+// Decomposition: angle chunks of PA angles x rectangular image regions.
+// Each (chunk, region) workgroup writes partial ray sums; the last workgroup of
+// a chunk (ticket counter) adds the regions' partials in region order.
+// ---------------------------------------------------------------------------
+constexpr int PA = 4;          // angles per workgroup
+constexpr int PACC = 768;      // ray accumulators per angle and region
+constexpr int PREG = 512;      // max region side
+constexpr int PTHREADS = 256;
+
+struct ProjJob {
+  const float* img;     // [n][n]
+  const double* ang;    // [n_ang]
+  const float* d;       // [n_ang][nb] or null: out = scale * P img - d
+  float* out;           // [n_ang][nb]
+  float* partial;       // [n_achunk][G][PA][PACC]
+  unsigned* ticket;     // [n_achunk], zero between launches
+  int n, nb, n_ang;
+  int n_achunk;
+  int reg_h, reg_w;     // region size (<= PREG)
+  int n_rr, n_rc;       // regions down / across
+  int wg_begin;
+  float scale;
+};
+
+// ---------------------------------------------------------------------------
+// Backprojector: one job = one image tile grid and one set of angles.
+// ---------------------------------------------------------------------------
+constexpr int BT = 32;          // tile side in pixels
+constexpr int BW = 48;          // staged bins per (tile, angle)
+constexpr int BAC = 64;         // angles per staged chunk
+constexpr int BTHREADS = 256;   // 4 pixels per thread
+
+enum { BP_PLAIN = 0, BP_ADMM = 1 };
+
+struct BPJob {
+  const float* sino;    // [n_ang][nb]
+  const double* ang;    // [n_ang]
+  float* img;           // output image (plain) or u (ADMM)
+  const float* x;       // ADMM: consensus image
+  const float* lam;     // ADMM: dual variable
+  int n, nb, n_ang;
+  int tiles_x;          // tiles per row
+  int wg_begin;
+  int mode;
+  float alpha, beta;    // plain: img = alpha * P^T sino + beta * img
+  float rho, eta1;      // ADMM:  u -= eta1 * (P^T sino + rho (u - x) + lam)
+};
+
+// ---------------------------------------------------------------------------
+// Consensus / quantization: one job = one segment of one node.
+// ---------------------------------------------------------------------------
+struct SegJob {
+  float* x;             // slice consensus image [n][n]
+  const float* u;       // this node's u (SEG mode)
+  const float* lam;     // this node's lambda (SEG mode)
+  int n, row0, rows;
+  float rho, eta2;
+  // AVG mode: the slice's nodes are nodes[node0 .. node0 + n_nodes)
+  int node0, n_nodes;
+  // message outputs (nullable)
+  uint8_t* labels;
+  float* centroids;
+  int32_t* iters;
+  int16_t* coeffs;
+  float* lohi;
+};
+
+struct NodeRef {        // u, lambda of one node (AVG gather, dual update)
+  float* u;
+  float* lam;
+  const float* x;
+  int n;
+  float rho;
+  int wg_begin;
+};
+
+struct AvgJob {         // x = mean over nodes[node0 .. node0+n_nodes) of u + lambda/rho
+  float* x;
+  int node0, n_nodes, n;
+  int wg_begin;
+};
+
+__device__ __forceinline__ float wave_sum(float v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+}  // namespace tomo

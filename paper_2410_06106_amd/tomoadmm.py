@@ -1,0 +1,256 @@
+"""Thin Python binding of the tomoadmm C ABI (include/tomoadmm.h).
+
+Argument marshalling only: every function checks dtype, device, shape and
+contiguity of the torch tensors it is given, passes their device pointers and
+torch's current HIP stream to the C function of the same name, and raises
+TomoError on a non-zero status.  All arithmetic happens in the HIP library.
+The library must have been built in-tree (``python -m
+paper_2410_06106_amd.buildlib``); importing this module fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtomoadmm.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2410_06106_amd.buildlib`")
+_lib = ctypes.CDLL(LIB_PATH)
+
+TOMO_XUPDATE_SEGMENT, TOMO_XUPDATE_AVERAGE = 0, 1
+TOMO_QUANT_NONE, TOMO_QUANT_KMEANS, TOMO_QUANT_DCT = 0, 1, 2
+EXPORTED = ("tomo_create", "tomo_destroy", "tomo_status_string", "tomo_last_error", "tomo_project",
+            "tomo_backproject", "admm_local_update", "admm_consensus", "quantize_kmeans",
+            "quantize_dct", "tomo_sqdiff")
+
+
+class TomoError(RuntimeError):
+    pass
+
+
+class tomo_geom(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("n_bins", ctypes.c_int32)]
+
+
+class tomo_node(ctypes.Structure):
+    _fields_ = [("g", tomo_geom), ("angles", ctypes.c_void_p), ("n_ang", ctypes.c_int32),
+                ("slice", ctypes.c_int32), ("d", ctypes.c_void_p), ("u", ctypes.c_void_p),
+                ("lam", ctypes.c_void_p), ("x", ctypes.c_void_p), ("seg_row0", ctypes.c_int32),
+                ("seg_rows", ctypes.c_int32), ("rho", ctypes.c_float), ("eta1", ctypes.c_float),
+                ("eta2", ctypes.c_float), ("reserved", ctypes.c_int32)]
+
+
+class tomo_quant(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("levels", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+                ("quality", ctypes.c_int32)]
+
+
+class tomo_msg(ctypes.Structure):
+    _fields_ = [("labels", ctypes.c_void_p), ("centroids", ctypes.c_void_p), ("iters", ctypes.c_void_p),
+                ("coeffs", ctypes.c_void_p), ("lohi", ctypes.c_void_p)]
+
+
+assert ctypes.sizeof(tomo_node) == 80 and ctypes.sizeof(tomo_msg) == 40
+
+_P = ctypes.c_void_p
+_lib.tomo_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int]
+_lib.tomo_destroy.argtypes = [_P]
+_lib.tomo_status_string.argtypes = [ctypes.c_int]
+_lib.tomo_status_string.restype = ctypes.c_char_p
+_lib.tomo_last_error.argtypes = [_P]
+_lib.tomo_last_error.restype = ctypes.c_char_p
+_lib.tomo_project.argtypes = [_P, tomo_geom, _P, ctypes.c_int32, _P, _P, _P]
+_lib.tomo_backproject.argtypes = [_P, tomo_geom, _P, ctypes.c_int32, _P, _P, ctypes.c_float,
+                                  ctypes.c_float, _P]
+_lib.admm_local_update.argtypes = [_P, ctypes.POINTER(tomo_node), ctypes.c_int32, ctypes.c_int32, _P]
+_lib.admm_consensus.argtypes = [_P, ctypes.POINTER(tomo_node), ctypes.c_int32, ctypes.c_int32,
+                                ctypes.c_int32, ctypes.POINTER(tomo_quant), ctypes.POINTER(tomo_msg), _P]
+_lib.quantize_kmeans.argtypes = [_P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P]
+_lib.quantize_dct.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                              _P, _P, _P, _P]
+_lib.tomo_sqdiff.argtypes = [_P, _P, _P, ctypes.c_int64, _P, _P]
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(t, dtype, name, shape=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must live on the GPU")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _opt(t, dtype, name, shape=None):
+    return ctypes.c_void_p(None) if t is None else _dev(t, dtype, name, shape)
+
+
+class Context:
+    """A tomo_ctx bound to one HIP device (torch's current device by default)."""
+
+    def __init__(self, device: int | None = None):
+        if device is None:
+            device = torch.cuda.current_device()
+        h = ctypes.c_void_p()
+        rc = _lib.tomo_create(ctypes.byref(h), int(device))
+        if rc != 0:
+            raise TomoError(f"tomo_create: {_lib.tomo_status_string(rc).decode()}")
+        self.handle = h
+        self.device = device
+
+    def check(self, rc: int, what: str):
+        if rc != 0:
+            msg = _lib.tomo_last_error(self.handle).decode()
+            raise TomoError(f"{what}: {_lib.tomo_status_string(rc).decode()}: {msg}")
+
+    def close(self):
+        if self.handle:
+            _lib.tomo_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default_ctx: dict[int, Context] = {}
+
+
+def default_context(device: int | None = None) -> Context:
+    if device is None:
+        device = torch.cuda.current_device()
+    if device not in _default_ctx:
+        _default_ctx[device] = Context(device)
+    return _default_ctx[device]
+
+
+def tomo_project(ctx: Context, angles, image, n_bins: int, out=None, stream=None):
+    n = image.shape[-1]
+    n_ang = angles.numel()
+    if out is None:
+        out = torch.empty((n_ang, n_bins), dtype=torch.float32, device=image.device)
+    g = tomo_geom(n, n_bins)
+    rc = _lib.tomo_project(ctx.handle, g, _dev(angles, torch.float64, "angles", (n_ang,)), n_ang,
+                           _dev(image, torch.float32, "image", (n, n)),
+                           _dev(out, torch.float32, "sino", (n_ang, n_bins)), _stream(stream))
+    ctx.check(rc, "tomo_project")
+    return out
+
+
+def tomo_backproject(ctx: Context, angles, sino, n: int, out=None, alpha: float = 1.0, beta: float = 0.0,
+                     stream=None):
+    n_ang, n_bins = sino.shape
+    if out is None:
+        out = torch.empty((n, n), dtype=torch.float32, device=sino.device)
+        beta = 0.0
+    g = tomo_geom(n, n_bins)
+    rc = _lib.tomo_backproject(ctx.handle, g, _dev(angles, torch.float64, "angles", (n_ang,)), n_ang,
+                               _dev(sino, torch.float32, "sino", (n_ang, n_bins)),
+                               _dev(out, torch.float32, "image", (n, n)), float(alpha), float(beta),
+                               _stream(stream))
+    ctx.check(rc, "tomo_backproject")
+    return out
+
+
+def admm_local_update(ctx: Context, nodes, e1: int, stream=None):
+    """``nodes`` is a ctypes array of tomo_node (see make_nodes)."""
+    rc = _lib.admm_local_update(ctx.handle, nodes, len(nodes), int(e1), _stream(stream))
+    ctx.check(rc, "admm_local_update")
+
+
+def admm_consensus(ctx: Context, nodes, mode: int, e2: int, quant: tomo_quant | None = None, msgs=None,
+                   stream=None):
+    q = ctypes.byref(quant) if quant is not None else None
+    rc = _lib.admm_consensus(ctx.handle, nodes, len(nodes), int(mode), int(e2), q, msgs, _stream(stream))
+    ctx.check(rc, "admm_consensus")
+
+
+def quantize_kmeans(ctx: Context, a, k: int, max_iter: int = 30, labels=None, centroids=None, a_hat=None,
+                    iters=None, stream=None):
+    a = a.reshape(-1)
+    n = a.numel()
+    if labels is None:
+        labels = torch.empty(n, dtype=torch.uint8, device=a.device)
+    if centroids is None:
+        centroids = torch.empty(k, dtype=torch.float32, device=a.device)
+    rc = _lib.quantize_kmeans(ctx.handle, _dev(a, torch.float32, "a"), n, int(k), int(max_iter),
+                              _dev(labels, torch.uint8, "labels", (n,)),
+                              _dev(centroids, torch.float32, "centroids", (k,)),
+                              _opt(a_hat, torch.float32, "a_hat", (n,)), _opt(iters, torch.int32, "iters", (1,)),
+                              _stream(stream))
+    ctx.check(rc, "quantize_kmeans")
+    return labels, centroids
+
+
+def quantize_dct(ctx: Context, a, quality: int, coeffs=None, a_hat=None, lohi=None, stream=None):
+    rows, cols = a.shape
+    if a_hat is None:
+        a_hat = torch.empty_like(a)
+    rc = _lib.quantize_dct(ctx.handle, _dev(a, torch.float32, "a"), rows, cols, cols, int(quality),
+                           _opt(coeffs, torch.int16, "coeffs", (rows, cols)),
+                           _dev(a_hat, torch.float32, "a_hat", (rows, cols)),
+                           _opt(lohi, torch.float32, "lohi", (2,)), _stream(stream))
+    ctx.check(rc, "quantize_dct")
+    return a_hat
+
+
+def tomo_sqdiff(ctx: Context, a, b, out=None, stream=None):
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=a.device)
+    n = a.numel()
+    if b.numel() != n:
+        raise ValueError("a and b differ in size")
+    rc = _lib.tomo_sqdiff(ctx.handle, _dev(a, torch.float32, "a"), _dev(b, torch.float32, "b"), n,
+                          _dev(out, torch.float64, "out", (1,)), _stream(stream))
+    ctx.check(rc, "tomo_sqdiff")
+    return out
+
+
+def make_nodes(entries):
+    """Build a ctypes tomo_node array from dicts with keys n, n_bins, angles, slice,
+    d, u, lam, x, seg_row0, seg_rows, rho, eta1, eta2 (tensors are checked)."""
+    arr = (tomo_node * len(entries))()
+    for i, e in enumerate(entries):
+        n, nb = int(e["n"]), int(e["n_bins"])
+        n_ang = e["angles"].numel()
+        arr[i].g = tomo_geom(n, nb)
+        arr[i].angles = _dev(e["angles"], torch.float64, "angles", (n_ang,)).value
+        arr[i].n_ang = n_ang
+        arr[i].slice = int(e.get("slice", 0))
+        arr[i].d = _dev(e["d"], torch.float32, "d", (n_ang, nb)).value
+        arr[i].u = _dev(e["u"], torch.float32, "u", (n, n)).value
+        arr[i].lam = _dev(e["lam"], torch.float32, "lam", (n, n)).value
+        arr[i].x = _dev(e["x"], torch.float32, "x", (n, n)).value
+        arr[i].seg_row0 = int(e["seg_row0"])
+        arr[i].seg_rows = int(e["seg_rows"])
+        arr[i].rho = float(e["rho"])
+        arr[i].eta1 = float(e["eta1"])
+        arr[i].eta2 = float(e["eta2"])
+        arr[i].reserved = 0
+    return arr
+
+
+def make_msgs(entries):
+    """ctypes tomo_msg array from dicts with optional labels, centroids, iters, coeffs, lohi."""
+    arr = (tomo_msg * len(entries))()
+    for i, e in enumerate(entries):
+        for key, dt in (("labels", torch.uint8), ("centroids", torch.float32), ("iters", torch.int32),
+                        ("coeffs", torch.int16), ("lohi", torch.float32)):
+            t = e.get(key)
+            setattr(arr[i], key, None if t is None else _dev(t, dt, key).value)
+    return arr

@@ -1,0 +1,141 @@
+"""End-to-end GPU parity of decentralized ADMM (Alg. 4) against the oracle, and
+equivalence of the plain per-node launch loop, the batched launch and its
+HIP-graph replay."""
+import numpy as np
+import pytest
+import torch
+
+import synthdata
+from gpu_common import log, rel_l2, require_gpu, to_dev
+from oracle import admm as oadmm
+from oracle import joseph, stepsize
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mods():
+    require_gpu()
+    from paper_2410_06106_amd import admm, tomoadmm
+    return tomoadmm, admm
+
+
+@pytest.fixture(scope="module")
+def ctx(mods):
+    return mods[0].Context(0)
+
+
+def _oracle_inputs(w, slice_idx=0):
+    truth = synthdata.phantom(w, slice_idx)
+    th = synthdata.angles(w.n_angles)
+    clean = joseph.project(truth, th, w.n_bins)
+    d = synthdata.add_gaussian_noise(clean, w.noise_level, synthdata.sinogram_seed(w, slice_idx))
+    parts = synthdata.partition_angles(w.n_angles, w.n_nodes, w.split)
+    v0 = np.random.default_rng(0).standard_normal((w.n, w.n))
+    L = max(stepsize.normal_operator_norm(th[p], w.n, w.n_bins, v0) for p in parts)
+    return truth, th, d, parts, L
+
+
+def _run_both(T, A, ctx, w, mode, quant, iters, c):
+    truth, th, d, parts, L = _oracle_inputs(w)
+    rho = 1.0
+    eta1 = float(np.float32(c / (L + rho)))
+    prob = oadmm.Problem(w.n, w.n_bins, [th[p] for p in parts], [d[p].astype(np.float64) for p in parts],
+                         synthdata.segment_rows(w.n, w.n_nodes), truth.astype(np.float64))
+    oq = oadmm.Quantizer(quant, w.levels, 30, 50)
+    x_o, _, _, tr_o = oadmm.run(prob, iters, rho, eta1, w.inner_iters, w.eta2, w.x_iters,
+                                mode=mode, quant=oq, cast32=True)
+    s = A.make_slice(ctx, w, d_host=d, truth_host=truth)
+    s.eta1 = eta1
+    q = None if quant == "none" else T.tomo_quant(T.TOMO_QUANT_KMEANS, w.levels, 30, 50)
+    run = A.DADMM(ctx, [s], rho=rho, eta2=w.eta2, e1=w.inner_iters, e2=w.x_iters,
+                  mode=T.TOMO_XUPDATE_SEGMENT if mode == "seg" else T.TOMO_XUPDATE_AVERAGE, quant=q)
+    rm = []
+    for _ in range(iters):
+        run.step()
+        rm.append(run.rmse())
+    return np.array(rm), np.array(tr_o.rmse), s.x.cpu().numpy(), x_o
+
+
+@pytest.mark.parametrize("mode", ["avg", "seg"])
+def test_tiny_workload_without_quantizer(mods, ctx, mode):
+    T, A = mods
+    w = synthdata.WORKLOADS["tiny"]
+    log(f"case tiny mode={mode} quant=none")
+    rm_g, rm_o, x_g, x_o = _run_both(T, A, ctx, w, mode, "none", 50, 1.0 if mode == "avg" else 0.1)
+    log(f"  rmse gpu {rm_g[-1]:.6g} oracle {rm_o[-1]:.6g} x rel {rel_l2(x_g, x_o):.3g}")
+    assert np.all(np.abs(rm_g - rm_o) <= 1e-4 * rm_o)
+    assert rel_l2(x_g, x_o) <= 1e-4
+
+
+def test_tiny_workload_kmeans16(mods, ctx):
+    """The tiny workload as specified: SEG x-update, 50 iterations, K-means with
+    16 levels on every exchanged segment."""
+    T, A = mods
+    w = synthdata.WORKLOADS["tiny"]
+    log("case tiny mode=seg quant=kmeans16")
+    rm_g, rm_o, x_g, x_o = _run_both(T, A, ctx, w, "seg", "kmeans", w.outer_iters, 0.1)
+    log(f"  rmse gpu {rm_g[-1]:.6g} oracle {rm_o[-1]:.6g} x rel {rel_l2(x_g, x_o):.3g}")
+    assert abs(rm_g[-1] - rm_o[-1]) <= 1e-4 * rm_o[-1]
+
+
+def _slices(T, A, ctx, n_slices=3):
+    out = []
+    for i in range(n_slices):
+        base = synthdata.WORKLOADS["tiny"]
+        w = synthdata.Workload(f"t{i}", 0, [48, 64, 40][i], [60, 90, 50][i], [69, 91, 57][i], [2, 4, 5][i],
+                               "interleaved", 5, "gaussian", 0.01, 5)
+        s = A.make_slice(ctx, w, slice_idx=i)
+        s.eta1 = A.step_size(ctx, s, 1.0, 0.5)
+        out.append(s)
+    return out
+
+
+def _snapshot(slices):
+    return [[t.clone() for t in s.u + s.lam + [s.x]] for s in slices]
+
+
+def _restore(slices, snap):
+    for s, sn in zip(slices, snap):
+        for t, v in zip(s.u + s.lam + [s.x], sn):
+            t.copy_(v)
+
+
+def test_batched_equals_plain_loop(mods, ctx):
+    T, A = mods
+    slices = _slices(T, A, ctx)
+    q = T.tomo_quant(T.TOMO_QUANT_KMEANS, 16, 30, 50)
+    run = A.DADMM(ctx, slices, quant=q)
+    for _ in range(4):
+        run.step_plain()
+    plain = [s.x.cpu().numpy().copy() for s in slices]
+    for s in slices:
+        s.zero()
+    for _ in range(4):
+        run.step()
+    for s, p in zip(slices, plain):
+        assert rel_l2(s.x.cpu().numpy(), p) <= 1e-5
+
+
+def test_graph_replay_matches_eager(mods, ctx):
+    T, A = mods
+    slices = _slices(T, A, ctx)
+    q = T.tomo_quant(T.TOMO_QUANT_KMEANS, 16, 30, 50)
+    run = A.DADMM(ctx, slices, quant=q)
+    s0 = _snapshot(slices)
+    eager = []
+    for _ in range(3):
+        run.step()
+        torch.cuda.synchronize()
+        eager.append([s.x.cpu().clone() for s in slices])
+    _restore(slices, s0)
+    torch.cuda.synchronize()
+    g = run.capture(1)
+    _restore(slices, s0)
+    torch.cuda.synchronize()
+    for k in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        _ = torch.ones(8, device="cuda").sum().item()     # unrelated eager work between replays
+        for s, e in zip(slices, eager[k]):
+            assert torch.equal(s.x.cpu(), e), f"replay {k} differs from eager"

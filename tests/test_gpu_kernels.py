@@ -1,0 +1,309 @@
+"""GPU parity of every kernel against the oracle, through the C ABI.
+
+Tolerances: projections and backprojections rel-L2 <= 1e-5 (float32 on the GPU
+against the float64 oracle); K-means labels and centroids bit-exact on identical
+float32 inputs; DCT codes equal except for off-by-one codes at rounding ties of
+the float64 coefficients (checked to lie within the float32 error bound), and the
+decoded segment within 1e-5 rel-L2 outside blocks that hold such a tie.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import log, rel_l2, require_gpu, to_dev
+from oracle import admm as oadmm
+from oracle import dct as odct
+from oracle import joseph
+from oracle.kmeans import kmeans_quantize
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def T():
+    require_gpu()
+    from paper_2410_06106_amd import tomoadmm
+    return tomoadmm
+
+
+@pytest.fixture(scope="module")
+def ctx(T):
+    return T.Context(0)
+
+
+def _angles(kind, k, rng):
+    if kind == "uniform":
+        return np.pi * np.arange(k) / k
+    if kind == "special":
+        return np.array([0.0, np.pi / 4, np.pi / 2, 3 * np.pi / 4, np.pi - 1e-9, 1e-9, np.pi / 4 + 1e-12])
+    return rng.uniform(0, np.pi, k)
+
+
+PROJ_CASES = [  # (n, n_bins, angle kind, n_angles)
+    (1, 1, "special", 0), (7, 11, "special", 0), (8, 8, "random", 9), (64, 91, "uniform", 90),
+    (100, 143, "random", 13), (129, 150, "uniform", 30), (513, 727, "random", 6),
+    (300, 200, "random", 5),   # detector narrower than the image
+]
+
+
+@pytest.mark.parametrize("n,nb,kind,k", PROJ_CASES)
+def test_project_and_backproject_match_oracle(T, ctx, n, nb, kind, k):
+    log(f"case project n={n} nb={nb} kind={kind} k={k}")
+    rng = np.random.default_rng(n * 7 + nb)
+    th = _angles(kind, k, rng)
+    img = rng.random((n, n)).astype(np.float32)
+    sino = rng.standard_normal((th.size, nb)).astype(np.float32)
+    ref_p = joseph.project(img, th, nb)
+    ref_b = joseph.backproject(sino, th, n)
+    ang = to_dev(th, torch.float64)
+    got_p = T.tomo_project(ctx, ang, to_dev(img), nb).cpu().numpy()
+    got_b = T.tomo_backproject(ctx, ang, to_dev(sino), n).cpu().numpy()
+    assert rel_l2(got_p, ref_p) <= 1e-5
+    assert rel_l2(got_b, ref_b) <= 1e-5
+    # alpha / beta epilogue
+    base = rng.standard_normal((n, n)).astype(np.float32)
+    out = to_dev(base)
+    T.tomo_backproject(ctx, ang, to_dev(sino), n, out=out, alpha=-0.5, beta=2.0)
+    assert rel_l2(out.cpu().numpy(), -0.5 * ref_b + 2.0 * base) <= 1e-5
+
+
+def test_adjoint_identity_on_gpu(T, ctx):
+    rng = np.random.default_rng(5)
+    n, nb, k = 200, 290, 37
+    th = rng.uniform(0, np.pi, k)
+    ang = to_dev(th, torch.float64)
+    x = rng.standard_normal((n, n)).astype(np.float32)
+    y = rng.standard_normal((k, nb)).astype(np.float32)
+    Ax = T.tomo_project(ctx, ang, to_dev(x), nb).cpu().numpy().astype(np.float64)
+    Aty = T.tomo_backproject(ctx, ang, to_dev(y), n).cpu().numpy().astype(np.float64)
+    lhs, rhs = np.sum(Ax * y), np.sum(x * Aty)
+    assert abs(lhs - rhs) <= 1e-5 * np.linalg.norm(Ax) * np.linalg.norm(y)
+
+
+def test_projector_full_size_sampled_angles(T, ctx):
+    """The 2048^2, 2897-bin shape of the large workload, on a sample of its
+    1800 angles (each angle's projection is independent of the others)."""
+    rng = np.random.default_rng(9)
+    n, nb = 2048, 2897
+    th_all = np.pi * np.arange(1800) / 1800
+    pick = np.sort(rng.choice(1800, 6, replace=False))
+    img = rng.random((n, n)).astype(np.float32)
+    ang = to_dev(th_all, torch.float64)
+    got = T.tomo_project(ctx, ang, to_dev(img), nb).cpu().numpy()
+    ref = joseph.project(img, th_all[pick], nb)
+    assert rel_l2(got[pick], ref) <= 1e-5
+    sino = rng.standard_normal((pick.size, nb)).astype(np.float32)
+    got_b = T.tomo_backproject(ctx, to_dev(th_all[pick], torch.float64), to_dev(sino), n).cpu().numpy()
+    assert rel_l2(got_b, joseph.backproject(sino, th_all[pick], n)) <= 1e-5
+
+
+def test_projector_is_deterministic(T, ctx):
+    rng = np.random.default_rng(2)
+    n, nb = 700, 990
+    ang = to_dev(rng.uniform(0, np.pi, 40), torch.float64)
+    img = to_dev(rng.random((n, n)).astype(np.float32))
+    a = T.tomo_project(ctx, ang, img, nb).cpu()
+    for _ in range(3):
+        assert torch.equal(a, T.tomo_project(ctx, ang, img, nb).cpu())
+
+
+KM_CASES = [  # (n, k, distribution)
+    (1, 4, "normal"), (7, 3, "normal"), (1000, 16, "normal"), (1024, 16, "uniform"),
+    (16384, 8, "normal"), (5000, 3, "three"), (4097, 1, "uniform"), (3000, 256, "normal"),
+    (65536, 16, "mixture"), (100003, 8, "ties"), (64, 5, "const"),
+]
+
+
+def _km_input(n, dist, rng):
+    if dist == "normal":
+        return rng.standard_normal(n).astype(np.float32)
+    if dist == "uniform":
+        return rng.uniform(-3, 5, n).astype(np.float32)
+    if dist == "three":
+        return np.array([0.0, 0.35, 1.0], np.float32)[rng.integers(0, 3, n)]
+    if dist == "mixture":
+        return np.concatenate([rng.normal(m, 0.05, n // 4) for m in (0, 0.3, 0.7, 1.0)]).astype(np.float32)
+    if dist == "ties":
+        return (rng.integers(0, 50, n) / 7.0).astype(np.float32)
+    if dist == "const":
+        return np.full(n, 0.625, np.float32)
+    raise ValueError(dist)
+
+
+@pytest.mark.parametrize("n,k,dist", KM_CASES)
+def test_kmeans_bit_exact(T, ctx, n, k, dist):
+    log(f"case kmeans n={n} k={k} dist={dist}")
+    rng = np.random.default_rng(n + k)
+    a = _km_input(n, dist, rng)
+    ref = kmeans_quantize(a, k, 30)
+    a_d = to_dev(a)
+    a_hat = torch.empty_like(a_d)
+    iters = torch.zeros(1, dtype=torch.int32, device="cuda")
+    labels, cent = T.quantize_kmeans(ctx, a_d, k, 30, a_hat=a_hat, iters=iters)
+    np.testing.assert_array_equal(labels.cpu().numpy(), ref.labels)
+    np.testing.assert_array_equal(cent.cpu().numpy().view(np.uint32), ref.centroids.view(np.uint32))
+    np.testing.assert_array_equal(a_hat.cpu().numpy(), ref.a_hat)
+    assert int(iters.item()) == ref.iters
+
+
+def test_kmeans_in_place_and_nonfinite(T, ctx):
+    rng = np.random.default_rng(3)
+    a = rng.standard_normal(2000).astype(np.float32)
+    ref = kmeans_quantize(a, 4)
+    a_d = to_dev(a)
+    T.quantize_kmeans(ctx, a_d, 4, 30, a_hat=a_d)
+    np.testing.assert_array_equal(a_d.cpu().numpy(), ref.a_hat)
+    b = a.copy()
+    b[17] = np.inf
+    iters = torch.zeros(1, dtype=torch.int32, device="cuda")
+    T.quantize_kmeans(ctx, to_dev(b), 4, 30, iters=iters)
+    assert int(iters.item()) == -1
+    with pytest.raises(T.TomoError):
+        T.quantize_kmeans(ctx, to_dev(a), 0)
+
+
+DCT_CASES = [(8, 8, 50), (32, 64, 25), (32, 64, 90), (24, 40, 50), (32, 2048, 50), (128, 128, 75), (16, 16, 100)]
+
+
+@pytest.mark.parametrize("rows,cols,q", DCT_CASES)
+def test_dct_codec(T, ctx, rows, cols, q):
+    log(f"case dct rows={rows} cols={cols} q={q}")
+    rng = np.random.default_rng(rows * cols + q)
+    yy, xx = np.mgrid[0:rows, 0:cols]
+    a = (np.sin(xx / 9.0) * np.cos(yy / 5.0) + 0.1 * rng.standard_normal((rows, cols))).astype(np.float32)
+    ref = odct.dct_quantize(a, q)
+    coeffs = torch.empty((rows, cols), dtype=torch.int16, device="cuda")
+    lohi = torch.empty(2, dtype=torch.float32, device="cuda")
+    a_hat = T.quantize_dct(ctx, to_dev(a), q, coeffs=coeffs, lohi=lohi).cpu().numpy()
+    got = coeffs.cpu().numpy().astype(np.int64)
+    want = ref.coeffs.astype(np.int64)
+    qs = np.tile(odct.quant_steps(q), (rows // 8, cols // 8))
+    diff = got != want
+    # any differing code is off by one at a rounding tie of the float64 coefficient
+    assert np.all(np.abs(got - want)[diff] == 1)
+    frac = np.abs(ref.F / qs - np.floor(ref.F / qs) - 0.5)
+    assert np.all(frac[diff] <= 2e-3 / qs[diff] + 1e-6), frac[diff]
+    assert diff.mean() <= 1e-3
+    np.testing.assert_allclose(lohi.cpu().numpy(), [a.min(), a.max()])
+    blk = diff.reshape(rows // 8, 8, cols // 8, 8).any(axis=(1, 3))
+    clean = ~np.repeat(np.repeat(blk, 8, 0), 8, 1)
+    assert rel_l2(a_hat[clean], ref.a_hat[clean]) <= 1e-5
+
+
+def test_dct_rejects_bad_shapes(T, ctx):
+    with pytest.raises(T.TomoError):
+        T.quantize_dct(ctx, to_dev(np.zeros((12, 16), np.float32)), 50)
+    with pytest.raises(T.TomoError):
+        T.quantize_dct(ctx, to_dev(np.zeros((16, 16), np.float32)), 0)
+    a = np.full((16, 16), 1.5, np.float32)
+    np.testing.assert_array_equal(T.quantize_dct(ctx, to_dev(a), 50).cpu().numpy(), a)
+
+
+def _nodes_problem(n, nb, k, m_nodes, seed):
+    rng = np.random.default_rng(seed)
+    th = np.pi * np.arange(k) / k
+    parts = [np.arange(m, k, m_nodes) for m in range(m_nodes)]
+    truth = rng.random((n, n))
+    d = [joseph.project(truth, th[p], nb) + 0.1 * rng.standard_normal((p.size, nb)) for p in parts]
+    return rng, th, parts, d
+
+
+def test_local_update_matches_oracle(T, ctx):
+    n, nb, k, M = 64, 91, 90, 4
+    rng, th, parts, d = _nodes_problem(n, nb, k, M, 1)
+    x = rng.random((n, n)).astype(np.float32)
+    us = [rng.random((n, n)).astype(np.float32) for _ in range(M)]
+    lams = [(0.1 * rng.standard_normal((n, n))).astype(np.float32) for _ in range(M)]
+    rho, eta1, e1 = 1.0, 1e-4, 5
+    X = to_dev(x)
+    U = [to_dev(u) for u in us]
+    Lm = [to_dev(l) for l in lams]
+    ents = [dict(n=n, n_bins=nb, angles=to_dev(th[p], torch.float64), slice=0, d=to_dev(d[m].astype(np.float32)),
+                 u=U[m], lam=Lm[m], x=X, seg_row0=16 * m, seg_rows=16, rho=rho, eta1=eta1, eta2=0.2)
+            for m, p in enumerate(parts)]
+    nodes = T.make_nodes(ents)
+    T.admm_local_update(ctx, nodes, e1)
+    for m, p in enumerate(parts):
+        ref = oadmm.local_update(us[m], x, lams[m], d[m].astype(np.float32), th[p], rho, eta1, e1)
+        assert rel_l2(U[m].cpu().numpy(), ref) <= 1e-5
+
+
+@pytest.mark.parametrize("mode", ["seg", "avg"])
+def test_consensus_without_quantizer_matches_oracle(T, ctx, mode):
+    n, M = 48, 3
+    rng = np.random.default_rng(11)
+    x = rng.random((n, n)).astype(np.float32)
+    us = [rng.random((n, n)).astype(np.float32) for _ in range(M)]
+    lams = [(0.1 * rng.standard_normal((n, n))).astype(np.float32) for _ in range(M)]
+    rho, eta2, e2 = 0.7, 0.2, 10
+    segs = [(0, 16), (16, 16), (32, 16)]
+    X = to_dev(x)
+    U = [to_dev(u) for u in us]
+    L = [to_dev(l) for l in lams]
+    dummy_d = to_dev(np.zeros((1, 8), np.float32))
+    ents = [dict(n=n, n_bins=8, angles=to_dev(np.zeros(1), torch.float64), slice=0, d=dummy_d, u=U[m],
+                 lam=L[m], x=X, seg_row0=segs[m][0], seg_rows=segs[m][1], rho=rho, eta1=0.0, eta2=eta2)
+            for m in range(M)]
+    nodes = T.make_nodes(ents)
+    T.admm_consensus(ctx, nodes, T.TOMO_XUPDATE_SEGMENT if mode == "seg" else T.TOMO_XUPDATE_AVERAGE, e2)
+    if mode == "seg":
+        xr = x.astype(np.float64).copy()
+        for m, (r0, nr) in enumerate(segs):
+            sl = slice(r0, r0 + nr)
+            xr[sl] = oadmm.x_update_segment(x[sl], us[m][sl], lams[m][sl], rho, eta2, e2)
+    else:
+        xr = oadmm.x_update_average([u.astype(np.float64) for u in us], [l.astype(np.float64) for l in lams], rho)
+    assert rel_l2(X.cpu().numpy(), xr) <= 1e-6
+    for m in range(M):
+        lr = oadmm.dual_update(lams[m].astype(np.float64), us[m], xr, rho)
+        assert rel_l2(L[m].cpu().numpy(), lr) <= 1e-5
+
+
+def test_consensus_with_kmeans_matches_oracle_bit_exact(T, ctx):
+    """SEG update then K-means on each segment: identical float32 x-updates feed
+    both quantizers, so labels and centroids must agree exactly."""
+    n, M, k = 64, 4, 16
+    rng = np.random.default_rng(12)
+    x = rng.random((n, n)).astype(np.float32)
+    us = [rng.random((n, n)).astype(np.float32) for _ in range(M)]
+    lams = [np.zeros((n, n), np.float32) for _ in range(M)]
+    X = to_dev(x)
+    U = [to_dev(u) for u in us]
+    L = [to_dev(l) for l in lams]
+    dummy_d = to_dev(np.zeros((1, 8), np.float32))
+    labels = [torch.empty(16 * n, dtype=torch.uint8, device="cuda") for _ in range(M)]
+    cents = [torch.empty(k, dtype=torch.float32, device="cuda") for _ in range(M)]
+    ents = [dict(n=n, n_bins=8, angles=to_dev(np.zeros(1), torch.float64), slice=0, d=dummy_d, u=U[m],
+                 lam=L[m], x=X, seg_row0=16 * m, seg_rows=16, rho=1.0, eta1=0.0, eta2=1.0) for m in range(M)]
+    nodes = T.make_nodes(ents)
+    msgs = T.make_msgs([dict(labels=labels[m], centroids=cents[m]) for m in range(M)])
+    q = T.tomo_quant(T.TOMO_QUANT_KMEANS, k, 30, 50)
+    # eta2 * rho = 1 with E2 = 1 makes the segment update exactly u + lambda/rho = u
+    T.admm_consensus(ctx, nodes, T.TOMO_XUPDATE_SEGMENT, 1, q, msgs)
+    for m in range(M):
+        ref = kmeans_quantize(us[m][16 * m:16 * m + 16].reshape(-1), k, 30)
+        np.testing.assert_array_equal(labels[m].cpu().numpy(), ref.labels)
+        np.testing.assert_array_equal(cents[m].cpu().numpy(), ref.centroids)
+        np.testing.assert_array_equal(X.cpu().numpy()[16 * m:16 * m + 16].reshape(-1), ref.a_hat)
+
+
+def test_sqdiff(T, ctx):
+    rng = np.random.default_rng(0)
+    a = rng.standard_normal(100001).astype(np.float32)
+    b = rng.standard_normal(100001).astype(np.float32)
+    got = float(T.tomo_sqdiff(ctx, to_dev(a), to_dev(b)).item())
+    ref = float(np.sum((a.astype(np.float64) - b) ** 2))
+    assert abs(got - ref) <= 1e-12 * ref
+
+
+def test_argument_errors_are_reported(T, ctx):
+    img = to_dev(np.zeros((8, 8), np.float32))
+    ang = to_dev(np.zeros(3), torch.float64)
+    with pytest.raises(T.TomoError):
+        T.tomo_project(ctx, ang, img, 0)
+    sino = torch.zeros(64, dtype=torch.float32, device="cuda")
+    with pytest.raises(T.TomoError):   # image and sino overlap
+        T._lib and T.tomo_project(ctx, to_dev(np.zeros(1), torch.float64), sino[:64].view(8, 8), 8,
+                                  out=sino[8:16].view(1, 8))
