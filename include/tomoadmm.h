@@ -115,6 +115,16 @@ typedef struct {
 int admm_local_update(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, int32_t e1,
                       void* stream);
 
+/*
+ * One launch of one half of an Alg. 2 step for every listed node (same plan as
+ * admm_local_update), for timing and profiling the two kernels separately:
+ *   phase 0: r_m = P_m u_m - d_m   into the plan's residual buffers;
+ *   phase 1: u_m <- u_m - eta1 (P_m^T r_m + rho (u_m - x) + lambda_m).
+ * admm_local_update with E1 = 1 is phase 0 followed by phase 1.
+ */
+int admm_local_phase(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, int32_t phase,
+                     void* stream);
+
 enum { TOMO_XUPDATE_SEGMENT = 0, TOMO_XUPDATE_AVERAGE = 1 };
 enum { TOMO_QUANT_NONE = 0, TOMO_QUANT_KMEANS = 1, TOMO_QUANT_DCT = 2 };
 

@@ -29,7 +29,7 @@ static_assert(sizeof(tomo_msg) == 40, "tomo_msg must have no padding");
 
 namespace {
 
-constexpr int kTargetProjWGs = 1024;   // workgroups wanted per projector launch
+constexpr int kJobWGs = 64;   // projector workgroups wanted per job
 
 struct DevBuf {
   void* p = nullptr;
@@ -59,25 +59,18 @@ ProjShape base_shape(int n, int n_ang) {
   return s;
 }
 
-// Halve regions of every job (rows first) until the launch has enough
-// workgroups, keeping regions at least 64 pixels on a side.
-void split_for_parallelism(std::vector<ProjShape>& shapes, const std::vector<int>& ns) {
-  for (int round = 0; round < 8; ++round) {
-    long total = 0;
-    for (auto& s : shapes) total += s.wgs();
-    if (total >= kTargetProjWGs) return;
-    bool changed = false;
-    for (size_t i = 0; i < shapes.size(); ++i) {
-      ProjShape& s = shapes[i];
-      int n = ns[i];
-      if (s.regions() >= 64) continue;
-      if (s.reg_h >= s.reg_w && s.reg_h >= 128) {
-        s.reg_h /= 2; s.n_rr = (n + s.reg_h - 1) / s.reg_h; changed = true;
-      } else if (s.reg_w >= 128) {
-        s.reg_w /= 2; s.n_rc = (n + s.reg_w - 1) / s.reg_w; changed = true;
-      }
+// Halve the regions of a job (rows first, sides >= 64) until the job alone
+// spans kJobWGs workgroups.  The decomposition depends on the job only, so a
+// node gives bit-identical results whether it is launched alone or batched.
+void split_for_parallelism(ProjShape& s, int n) {
+  while (s.wgs() < kJobWGs && s.regions() < 64) {
+    if (s.reg_h >= s.reg_w && s.reg_h >= 128) {
+      s.reg_h /= 2; s.n_rr = (n + s.reg_h - 1) / s.reg_h;
+    } else if (s.reg_w >= 128) {
+      s.reg_w /= 2; s.n_rc = (n + s.reg_w - 1) / s.reg_w;
+    } else {
+      break;
     }
-    if (!changed) return;
   }
 }
 
@@ -194,13 +187,11 @@ LocalPlan* get_local_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, in
   auto plan = std::make_unique<LocalPlan>();
   plan->key.assign(nodes, nodes + n_nodes);
   std::vector<ProjShape> shapes;
-  std::vector<int> ns;
   size_t resid_elems = 0, part_elems = 0, tick_elems = 0;
   for (int i = 0; i < n_nodes; ++i) {
     shapes.push_back(base_shape(nodes[i].g.n, nodes[i].n_ang));
-    ns.push_back(nodes[i].g.n);
+    split_for_parallelism(shapes.back(), nodes[i].g.n);
   }
-  split_for_parallelism(shapes, ns);
   std::vector<size_t> roff(n_nodes), poff(n_nodes), toff(n_nodes);
   for (int i = 0; i < n_nodes; ++i) {
     roff[i] = resid_elems;
@@ -372,7 +363,7 @@ int tomo_project(tomo_ctx* ctx, tomo_geom g, const double* angles, int32_t n_ang
     return ctx->fail(TOMO_EINVAL, "image and sino overlap");
   if (int rc = set_device(ctx)) return rc;
   std::vector<ProjShape> sh{base_shape(g.n, n_ang)};
-  split_for_parallelism(sh, {g.n});
+  split_for_parallelism(sh[0], g.n);
   ProjJob j = make_proj_job(image, angles, nullptr, sino, g.n, g.n_bins, n_ang, sh[0]);
   if (sh[0].regions() > 1) {
     if (!ctx->partial.ensure((size_t)sh[0].wgs() * PA * PACC * 4)) return ctx->fail(TOMO_ENOMEM, "workspace");
@@ -425,6 +416,28 @@ int admm_local_update(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, in
     hipLaunchKernelGGL(k_backproject<Many<BPJob>>, dim3(plan->b_wgs), dim3(BTHREADS), 0, (hipStream_t)stream, bs);
   }
   return launch_status(ctx, "admm_local_update");
+}
+
+int admm_local_phase(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, int32_t phase, void* stream) {
+  if (!ctx) return TOMO_EINVAL;
+  if (phase != 0 && phase != 1) return ctx->fail(TOMO_EINVAL, "phase must be 0 or 1");
+  if (!nodes || n_nodes < 1) return ctx->fail(TOMO_EINVAL, "empty node list");
+  if (int rc = set_device(ctx)) return rc;
+  int rc = TOMO_OK;
+  LocalPlan* plan = find_local_plan(ctx, nodes, n_nodes);
+  if (!plan) {
+    if (int rc2 = check_nodes(ctx, nodes, n_nodes)) return rc2;
+    plan = get_local_plan(ctx, nodes, n_nodes, rc);
+  }
+  if (!plan) return rc;
+  if (phase == 0) {
+    Many<ProjJob> ps{static_cast<const ProjJob*>(plan->pjobs.p), plan->n_p};
+    hipLaunchKernelGGL(k_project<Many<ProjJob>>, dim3(plan->p_wgs), dim3(PTHREADS), 0, (hipStream_t)stream, ps);
+  } else {
+    Many<BPJob> bs{static_cast<const BPJob*>(plan->bjobs.p), plan->n_b};
+    hipLaunchKernelGGL(k_backproject<Many<BPJob>>, dim3(plan->b_wgs), dim3(BTHREADS), 0, (hipStream_t)stream, bs);
+  }
+  return launch_status(ctx, "admm_local_phase");
 }
 
 int admm_consensus(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, int32_t mode, int32_t e2,

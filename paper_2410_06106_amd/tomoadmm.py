@@ -24,8 +24,8 @@ _lib = ctypes.CDLL(LIB_PATH)
 TOMO_XUPDATE_SEGMENT, TOMO_XUPDATE_AVERAGE = 0, 1
 TOMO_QUANT_NONE, TOMO_QUANT_KMEANS, TOMO_QUANT_DCT = 0, 1, 2
 EXPORTED = ("tomo_create", "tomo_destroy", "tomo_status_string", "tomo_last_error", "tomo_project",
-            "tomo_backproject", "admm_local_update", "admm_consensus", "quantize_kmeans",
-            "quantize_dct", "tomo_sqdiff")
+            "tomo_backproject", "admm_local_update", "admm_local_phase", "admm_consensus",
+            "quantize_kmeans", "quantize_dct", "tomo_sqdiff")
 
 
 class TomoError(RuntimeError):
@@ -67,6 +67,7 @@ _lib.tomo_project.argtypes = [_P, tomo_geom, _P, ctypes.c_int32, _P, _P, _P]
 _lib.tomo_backproject.argtypes = [_P, tomo_geom, _P, ctypes.c_int32, _P, _P, ctypes.c_float,
                                   ctypes.c_float, _P]
 _lib.admm_local_update.argtypes = [_P, ctypes.POINTER(tomo_node), ctypes.c_int32, ctypes.c_int32, _P]
+_lib.admm_local_phase.argtypes = [_P, ctypes.POINTER(tomo_node), ctypes.c_int32, ctypes.c_int32, _P]
 _lib.admm_consensus.argtypes = [_P, ctypes.POINTER(tomo_node), ctypes.c_int32, ctypes.c_int32,
                                 ctypes.c_int32, ctypes.POINTER(tomo_quant), ctypes.POINTER(tomo_msg), _P]
 _lib.quantize_kmeans.argtypes = [_P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P]
@@ -171,6 +172,11 @@ def admm_local_update(ctx: Context, nodes, e1: int, stream=None):
     """``nodes`` is a ctypes array of tomo_node (see make_nodes)."""
     rc = _lib.admm_local_update(ctx.handle, nodes, len(nodes), int(e1), _stream(stream))
     ctx.check(rc, "admm_local_update")
+
+
+def admm_local_phase(ctx: Context, nodes, phase: int, stream=None):
+    rc = _lib.admm_local_phase(ctx.handle, nodes, len(nodes), int(phase), _stream(stream))
+    ctx.check(rc, "admm_local_phase")
 
 
 def admm_consensus(ctx: Context, nodes, mode: int, e2: int, quant: tomo_quant | None = None, msgs=None,

