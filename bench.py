@@ -116,8 +116,11 @@ def main():
     rho, c_seg = w.rho, 0.1
     s.eta1 = A.step_size(ctx, s, rho, c_seg)
     q = T.tomo_quant(T.TOMO_QUANT_KMEANS, w.levels, 30, 50)
+    km_iters = torch.zeros((w.n_nodes, 1), dtype=torch.int32, device="cuda")
+    km_cent = torch.zeros((w.n_nodes, w.levels), dtype=torch.float32, device="cuda")
+    msgs = T.make_msgs([dict(iters=km_iters[m], centroids=km_cent[m]) for m in range(w.n_nodes)])
     run = A.DADMM(ctx, [s], rho=rho, eta2=w.eta2, e1=w.inner_iters, e2=w.x_iters,
-                  mode=T.TOMO_XUPDATE_SEGMENT, quant=q)
+                  mode=T.TOMO_XUPDATE_SEGMENT, quant=q, msgs=msgs)
     updates_per_step = 2 * w.inner_iters * w.n_angles * w.n * w.n
 
     # --- equal-RMSE check: plain per-node loop vs batched graph, same iterations
@@ -162,6 +165,7 @@ def main():
     ms_per_step = max(gpu_ms, wall * 1e3) / args.steps
     value = updates_per_step / (ms_per_step * 1e-3)
     rmse_final = run.rmse()
+    lloyd = km_iters.cpu().numpy().reshape(-1)
     log(f"batched graph: {ms_per_step:.3f} ms/iteration, {value:.4g} updates/s, rmse {rmse_final:.6g}")
 
     # --- dominant kernels: average launch duration with HIP events on the launch stream
@@ -213,6 +217,8 @@ def main():
         "equal_rmse": {"iterations": n_eq, "plain": rmse_plain, "batched": rmse_batched,
                        "bit_identical": identical},
         "rmse_after_timed_steps": rmse_final,
+        "kmeans_lloyd_iters_last_step": {"mean": float(lloyd.mean()), "max": int(lloyd.max()),
+                                          "min": int(lloyd.min())},
         "kernels_us": {k: v * 1e3 for k, v in kern.items()},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,

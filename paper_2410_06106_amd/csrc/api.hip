@@ -13,9 +13,8 @@ namespace tomo {
 template <class Src> __global__ void k_project(Src);
 template <class Src> __global__ void k_backproject(Src);
 __global__ void k_seg_none(const SegJob*, int, int);
-__global__ void k_seg_kmeans(const SegJob*, int, int, int, int, uint8_t*, long long);
+template <bool REG> __global__ void k_kmeans_grid(const KMJob*, KMJob, int, int, int, int, KMSlot*, KMSync*);
 __global__ void k_seg_dct(const SegJob*, int, int, int);
-__global__ void k_kmeans(const float*, long long, int, int, uint8_t*, float*, float*, int32_t*);
 __global__ void k_dct(const float*, int, int, int, int, int16_t*, float*, float*);
 __global__ void k_avg(Many<AvgJob>, const NodeRef*);
 __global__ void k_dual(Many<NodeRef>);
@@ -88,10 +87,22 @@ struct LocalPlan {
 struct ConsPlan {
   std::vector<tomo_node> key;
   std::vector<tomo_msg> msg_key;
-  DevBuf seg, avg, noderefs, labels;
+  DevBuf seg, avg, noderefs, labels, kmjobs, kmslots, kmsync;
   int n_seg = 0, n_avg = 0, avg_wgs = 0, dual_wgs = 0;
+  int km_G = 1;
+  bool km_reg = true;
   long long label_stride = 0;
 };
+
+constexpr int kKmRegElems = 256 * 16;   // values a K-means workgroup keeps in registers
+
+// Workgroups per K-means segment: spread segments over the CUs (all of a
+// segment's workgroups must be resident together) with >= 1024 values each.
+int kmeans_groups(int n_cu, int n_seg, long long max_n) {
+  long long want = (max_n + 1023) / 1024;
+  long long fit = n_cu / std::max(1, n_seg);
+  return (int)std::max(1ll, std::min(want, fit));
+}
 
 bool same_nodes(const std::vector<tomo_node>& k, const tomo_node* nodes, int n) {
   return (int)k.size() == n && std::memcmp(k.data(), nodes, sizeof(tomo_node) * n) == 0;
@@ -101,8 +112,10 @@ bool same_nodes(const std::vector<tomo_node>& k, const tomo_node* nodes, int n) 
 
 struct tomo_ctx {
   int device = 0;
+  int n_cu = 1;
   std::string err;
   DevBuf partial, tickets;                       // standalone projector workspace
+  DevBuf km_slots, km_sync;                      // standalone K-means workspace
   std::vector<std::unique_ptr<LocalPlan>> lplans;
   std::vector<std::unique_ptr<ConsPlan>> cplans;
   int fail(int code, const std::string& msg) { err = msg; return code; }
@@ -294,10 +307,40 @@ ConsPlan* get_cons_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, cons
     avg.back().n_nodes++;
   }
   plan->label_stride = (max_seg + 255) / 256 * 256;
+  plan->km_G = kmeans_groups(ctx->n_cu, n_nodes, max_seg);
+  plan->km_reg = (max_seg + plan->km_G - 1) / plan->km_G <= kKmRegElems;
+  std::vector<KMJob> km;
+  for (int i = 0; i < n_nodes; ++i) {
+    const tomo_node& N = nodes[i];
+    size_t off = (size_t)N.seg_row0 * N.g.n;
+    KMJob j{};
+    j.src = N.x + off;
+    j.x = N.x + off;
+    j.a_hat = N.x + off;
+    j.u = N.u + off;
+    j.lam = N.lam + off;
+    j.n = (long long)N.seg_rows * N.g.n;
+    j.rho = N.rho;
+    j.eta2 = N.eta2;
+    j.labels = (msg && msg[i].labels) ? msg[i].labels : nullptr;   // scratch filled in below
+    j.cent = msg ? msg[i].centroids : nullptr;
+    j.iters = msg ? msg[i].iters : nullptr;
+    km.push_back(j);
+  }
+  const size_t n_slots = (size_t)n_nodes * plan->km_G * 2;
   if (!plan->seg.ensure(seg.size() * sizeof(SegJob)) || !plan->avg.ensure(avg.size() * sizeof(AvgJob)) ||
       !plan->noderefs.ensure(refs.size() * sizeof(NodeRef)) ||
-      !plan->labels.ensure((size_t)plan->label_stride * n_nodes)) {
+      !plan->labels.ensure((size_t)plan->label_stride * n_nodes) ||
+      !plan->kmjobs.ensure(km.size() * sizeof(KMJob)) || !plan->kmslots.ensure(n_slots * sizeof(KMSlot)) ||
+      !plan->kmsync.ensure((size_t)n_nodes * sizeof(KMSync))) {
     rc = ctx->fail(TOMO_ENOMEM, "consensus plan allocation failed");
+    return nullptr;
+  }
+  for (int i = 0; i < n_nodes; ++i)
+    if (!km[i].labels) km[i].labels = static_cast<uint8_t*>(plan->labels.p) + (size_t)i * plan->label_stride;
+  if (hipMemset(plan->kmsync.p, 0, (size_t)n_nodes * sizeof(KMSync)) != hipSuccess ||
+      hipMemcpy(plan->kmjobs.p, km.data(), km.size() * sizeof(KMJob), hipMemcpyHostToDevice) != hipSuccess) {
+    rc = ctx->fail(TOMO_EDEVICE, "K-means plan upload failed");
     return nullptr;
   }
   if (hipMemcpy(plan->seg.p, seg.data(), seg.size() * sizeof(SegJob), hipMemcpyHostToDevice) != hipSuccess ||
@@ -340,6 +383,8 @@ int tomo_create(tomo_ctx** out, int device) {
   tomo_ctx* c = new (std::nothrow) tomo_ctx();
   if (!c) return TOMO_ENOMEM;
   c->device = device;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->n_cu = std::max(1, prop.multiProcessorCount);
   *out = c;
   return TOMO_OK;
 }
@@ -468,8 +513,18 @@ int admm_consensus(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, int32
     hipLaunchKernelGGL(k_avg, dim3(plan->avg_wgs), dim3(256), 0, s, as, refs);
   }
   if (kind == TOMO_QUANT_KMEANS) {
-    hipLaunchKernelGGL(k_seg_kmeans, dim3(plan->n_seg), dim3(1024), 0, s, seg, do_x, e2, q->levels, q->max_iter,
-                       static_cast<uint8_t*>(plan->labels.p), plan->label_stride);
+    // the x-update (SEG) runs inside the K-means kernel; AVG already wrote x
+    const KMJob* kj = static_cast<const KMJob*>(plan->kmjobs.p);
+    KMSlot* sl = static_cast<KMSlot*>(plan->kmslots.p);
+    KMSync* sy = static_cast<KMSync*>(plan->kmsync.p);
+    const int ex = do_x ? e2 : 0;
+    dim3 grid(plan->n_seg * plan->km_G);
+    if (plan->km_reg)
+      hipLaunchKernelGGL(k_kmeans_grid<true>, grid, dim3(256), 0, s, kj, KMJob{}, plan->km_G, q->levels,
+                         q->max_iter, ex, sl, sy);
+    else
+      hipLaunchKernelGGL(k_kmeans_grid<false>, grid, dim3(256), 0, s, kj, KMJob{}, plan->km_G, q->levels,
+                         q->max_iter, ex, sl, sy);
   } else if (kind == TOMO_QUANT_DCT) {
     hipLaunchKernelGGL(k_seg_dct, dim3(plan->n_seg), dim3(256), 0, s, seg, do_x, e2, q->quality);
   } else if (do_x) {
@@ -489,8 +544,29 @@ int quantize_kmeans(tomo_ctx* ctx, const float* a, int64_t n, int32_t k, int32_t
   if (a_hat && a_hat != a && overlaps(a, (size_t)n * 4, a_hat, (size_t)n * 4))
     return ctx->fail(TOMO_EINVAL, "a_hat partially overlaps a");
   if (int rc = set_device(ctx)) return rc;
-  hipLaunchKernelGGL(k_kmeans, dim3(1), dim3(1024), 0, (hipStream_t)stream, a, (long long)n, k, max_iter, labels,
-                     centroids, a_hat, iters);
+  const int G = kmeans_groups(ctx->n_cu, 1, n);
+  const bool reg = (n + G - 1) / G <= kKmRegElems;
+  if (!ctx->km_slots.ensure((size_t)G * 2 * sizeof(KMSlot))) return ctx->fail(TOMO_ENOMEM, "workspace");
+  size_t had = ctx->km_sync.bytes;
+  if (!ctx->km_sync.ensure(sizeof(KMSync))) return ctx->fail(TOMO_ENOMEM, "workspace");
+  if (ctx->km_sync.bytes != had && hipMemset(ctx->km_sync.p, 0, sizeof(KMSync)) != hipSuccess)
+    return ctx->fail(TOMO_EDEVICE, "hipMemset failed");
+  KMJob j{};
+  j.src = a;
+  j.a_hat = a_hat;
+  j.labels = labels;
+  j.cent = centroids;
+  j.iters = iters;
+  j.n = n;
+  j.rho = 1.f;
+  KMSlot* sl = static_cast<KMSlot*>(ctx->km_slots.p);
+  KMSync* sy = static_cast<KMSync*>(ctx->km_sync.p);
+  if (reg)
+    hipLaunchKernelGGL(k_kmeans_grid<true>, dim3(G), dim3(256), 0, (hipStream_t)stream, nullptr, j, G, k,
+                       max_iter, 0, sl, sy);
+  else
+    hipLaunchKernelGGL(k_kmeans_grid<false>, dim3(G), dim3(256), 0, (hipStream_t)stream, nullptr, j, G, k,
+                       max_iter, 0, sl, sy);
   return launch_status(ctx, "quantize_kmeans");
 }
 

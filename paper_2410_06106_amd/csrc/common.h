@@ -120,6 +120,33 @@ struct AvgJob {         // x = mean over nodes[node0 .. node0+n_nodes) of u + la
   int wg_begin;
 };
 
+// K-means over segments: one job per segment (see kmeans.hip)
+constexpr int KM_MAX_K = 256;
+
+struct KMJob {
+  const float* src;     // values (the segment of x in the consensus step)
+  float* x;             // where the x-updated values are stored (consensus)
+  float* a_hat;         // quantized values (nullable, may equal src)
+  const float* u;       // Alg. 3 inputs, or null for no x-update
+  const float* lam;
+  uint8_t* labels;      // [n] (required when the slice of a workgroup exceeds its registers)
+  float* cent;          // [k] (nullable)
+  int32_t* iters;       // [1] (nullable)
+  long long n;
+  float rho, eta2;
+};
+
+struct KMSlot {         // statistics one workgroup publishes for its segment
+  long long sum[KM_MAX_K];
+  unsigned cnt[KM_MAX_K];
+  float mn, mx;
+  int changed, bad;
+};
+
+struct KMSync {         // per-segment barrier counters, zero between launches
+  unsigned arrive, leave;
+};
+
 __device__ __forceinline__ float wave_sum(float v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;

@@ -1,11 +1,11 @@
 // Consensus, exchange and dual steps of decentralized ADMM (gfx950):
 //   Alg. 3   segment x-update, E2 gradient steps on rho/2 ||u - x + lambda/rho||^2
 //   Eq. 9    averaging x-update x = mean_m (u_m + lambda_m / rho)
-//   Alg. 5   scalar K-means quantizer of a segment (bit-exact fixed-point sums)
 //   JPEG-style quantizer: 8x8 DCT-II on MFMA, table quantization, inverse DCT
 //   Eq. 24   dual update lambda_m += rho (u_m - x)
-// One workgroup owns one segment for the x-update and the quantizer, so a
-// segment's statistics (min/max, cluster sums) never leave the workgroup.
+// One workgroup owns one segment for the x-update and the DCT quantizer, so a
+// segment's level-map range never leaves the workgroup.  (The K-means quantizer
+// lives in kmeans.hip.)
 #include "common.h"
 
 namespace tomo {
@@ -50,117 +50,6 @@ __device__ void segment_xupdate(const SegJob& S, int e2) {
     S.x[base + i] = xv;
   }
   __syncthreads();
-}
-
-// ---------------------------------------------------------------------------
-// Alg. 5: scalar K-means with a fully specified arithmetic (see the header)
-// ---------------------------------------------------------------------------
-constexpr int KM_THREADS = 1024;
-constexpr int KM_WAVES = KM_THREADS / 64;
-
-struct KMShared {
-  unsigned long long sum[KM_WAVES][256];
-  unsigned cnt[KM_WAVES][256];
-  float cent[256];
-  float red[2 * KM_WAVES];
-  int redb[KM_WAVES];
-  int changed;
-};
-
-__device__ __forceinline__ int km_assign(float v, const float* cent, int k) {
-  float best = fabsf(v - cent[0]);
-  int bj = 0;
-  for (int j = 1; j < k; ++j) {
-    float d = fabsf(v - cent[j]);
-    if (d < best) { best = d; bj = j; }
-  }
-  return bj;
-}
-
-__device__ __forceinline__ long long km_fixed(float v, int S) {
-  return (long long)rint(ldexp((double)v, S));
-}
-
-// values a[0..n) (stride 1); labels (required) ; a_hat may alias a
-__device__ void kmeans_wg(const float* a, long long n, int k, int max_iter, uint8_t* labels,
-                          float* cent_out, float* a_hat, int32_t* iters_out, KMShared& sh) {
-#pragma clang fp contract(off)
-  const int tid = threadIdx.x;
-  const int w = tid >> 6, l = tid & 63;
-  float lo = INFINITY, hi = -INFINITY;
-  int bad = 0;
-  for (long long i = tid; i < n; i += KM_THREADS) {
-    float v = a[i];
-    bad |= !isfinite(v);
-    lo = fminf(lo, v);
-    hi = fmaxf(hi, v);
-  }
-  wg_minmax<KM_THREADS>(lo, hi, bad, sh.red, sh.redb);
-  if (bad || hi == lo) {
-    // non-finite input: iters = -1; constant input: one cluster at lo, iters = 0
-    for (long long i = tid; i < n; i += KM_THREADS) {
-      labels[i] = 0;
-      if (a_hat && a_hat != a) a_hat[i] = a[i];
-    }
-    if (cent_out) for (int j = tid; j < k; j += KM_THREADS) cent_out[j] = bad ? 0.f : lo;
-    if (iters_out && tid == 0) *iters_out = bad ? -1 : 0;
-    return;
-  }
-  int e;
-  frexp(fmax(fabs((double)lo), fabs((double)hi)), &e);
-  int S;
-  if (n <= (1ll << 22)) {
-    S = 40 - e;
-  } else {
-    int lg = 64 - __clzll((unsigned long long)(n - 1));   // ceil(log2 n)
-    S = 62 - lg - e;
-  }
-  if (tid < k) {
-    double lo64 = lo, hi64 = hi;
-    double t = (hi64 - lo64) * (double)(2 * tid + 1);
-    t = t / (double)(2 * k);
-    sh.cent[tid] = (float)(lo64 + t);
-  }
-  __syncthreads();
-  for (long long i = tid; i < n; i += KM_THREADS) labels[i] = (uint8_t)km_assign(a[i], sh.cent, k);
-
-  int it = 0;
-  for (int t = 1; t <= max_iter; ++t) {
-    for (int j = l; j < k; j += 64) { sh.sum[w][j] = 0ull; sh.cnt[w][j] = 0u; }
-    if (tid == 0) sh.changed = 0;
-    __syncthreads();
-    for (long long i = tid; i < n; i += KM_THREADS) {
-      int lab = labels[i];
-      atomicAdd(&sh.sum[w][lab], (unsigned long long)km_fixed(a[i], S));
-      atomicAdd(&sh.cnt[w][lab], 1u);
-    }
-    __syncthreads();
-    if (tid < k) {
-      long long q = 0;
-      unsigned long long c = 0;
-      for (int ww = 0; ww < KM_WAVES; ++ww) {
-        q += (long long)sh.sum[ww][tid];
-        c += sh.cnt[ww][tid];
-      }
-      if (c > 0) sh.cent[tid] = (float)(ldexp((double)q, -S) / (double)c);
-    }
-    __syncthreads();
-    int ch = 0;
-    for (long long i = tid; i < n; i += KM_THREADS) {
-      int nl = km_assign(a[i], sh.cent, k);
-      if (nl != labels[i]) { ch = 1; labels[i] = (uint8_t)nl; }
-    }
-    if (ch) sh.changed = 1;
-    __syncthreads();
-    it = t;
-    if (!sh.changed) break;
-    __syncthreads();
-  }
-  for (long long i = tid; i < n; i += KM_THREADS) {
-    if (a_hat) a_hat[i] = sh.cent[labels[i]];
-  }
-  if (cent_out) for (int j = tid; j < k; j += KM_THREADS) cent_out[j] = sh.cent[j];
-  if (iters_out && tid == 0) *iters_out = it;
 }
 
 // ---------------------------------------------------------------------------
@@ -282,17 +171,6 @@ __global__ __launch_bounds__(256) void k_seg_none(const SegJob* jobs, int do_x, 
   if (do_x) segment_xupdate<256>(S, e2);
 }
 
-__global__ __launch_bounds__(KM_THREADS) void k_seg_kmeans(const SegJob* jobs, int do_x, int e2, int k,
-                                                          int max_iter, uint8_t* scratch_labels,
-                                                          long long scratch_stride) {
-  __shared__ KMShared sh;
-  const SegJob S = jobs[blockIdx.x];
-  if (do_x) segment_xupdate<KM_THREADS>(S, e2);
-  float* seg = S.x + (size_t)S.row0 * S.n;
-  uint8_t* lab = S.labels ? S.labels : scratch_labels + blockIdx.x * scratch_stride;
-  kmeans_wg(seg, (long long)S.rows * S.n, k, max_iter, lab, S.centroids, seg, S.iters, sh);
-}
-
 __global__ __launch_bounds__(DCT_THREADS) void k_seg_dct(const SegJob* jobs, int do_x, int e2,
                                                          int quality) {
   __shared__ DCTShared sh;
@@ -300,13 +178,6 @@ __global__ __launch_bounds__(DCT_THREADS) void k_seg_dct(const SegJob* jobs, int
   if (do_x) segment_xupdate<DCT_THREADS>(S, e2);
   float* seg = S.x + (size_t)S.row0 * S.n;
   dct_wg(seg, S.rows, S.n, S.n, quality, S.coeffs, seg, S.lohi, sh);
-}
-
-__global__ __launch_bounds__(KM_THREADS) void k_kmeans(const float* a, long long n, int k,
-                                                      int max_iter, uint8_t* labels, float* cent,
-                                                      float* a_hat, int32_t* iters) {
-  __shared__ KMShared sh;
-  kmeans_wg(a, n, k, max_iter, labels, cent, a_hat, iters, sh);
 }
 
 __global__ __launch_bounds__(DCT_THREADS) void k_dct(const float* a, int rows, int cols, int ld,

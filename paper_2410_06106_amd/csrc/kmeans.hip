@@ -1,0 +1,309 @@
+// Scalar K-means quantizer (Alg. 5) of exchanged segments, for gfx950.
+//
+// Arithmetic is fixed so that results are bit-exact and independent of the
+// launch shape: centres start at lo + (hi - lo)(2j + 1)/(2k) (float64, no
+// contraction); values enter the centroid sums as int64 fixed point
+// round(a * 2^S) (S = 40 - e for n <= 2^22, else 62 - ceil(log2 n) - e, e the
+// binary exponent of max(|lo|, |hi|)), so every sum is exact in any order;
+// label = lowest j minimising |a - c_j| in float32; a centre becomes
+// f32(f64(sum) * 2^-S / f64(count)); Lloyd iterations stop when no label
+// changes or after max_iter.
+//
+// One segment is spread over G workgroups (G * segments <= number of CUs, so
+// all of them are resident together).  Each iteration a workgroup publishes the
+// cluster sums of its slice of the segment to a double-buffered slot and meets
+// the others at a per-segment barrier; every workgroup then adds the G slots in
+// the same order and derives identical centres.  The barrier spins a bounded
+// number of times: if the workgroups of a segment ever fail to be co-resident
+// the kernel reports iters = -2 instead of hanging.  With G = 1 no barrier is
+// needed.  The optional Alg. 3 x-update of the segment is applied on load.
+#include "common.h"
+
+namespace tomo {
+
+namespace {
+
+constexpr int KT = 256;                 // threads per workgroup
+constexpr int KWAVES = KT / 64;
+constexpr int KVPT = 16;                // values per thread kept in registers
+constexpr unsigned kSpinLimit = 1u << 20;
+
+__device__ __forceinline__ int km_assign(float v, const float* cent, int k) {
+  float best = fabsf(v - cent[0]);
+  int bj = 0;
+  for (int j = 1; j < k; ++j) {
+    float d = fabsf(v - cent[j]);
+    if (d < best) { best = d; bj = j; }
+  }
+  return bj;
+}
+
+__device__ __forceinline__ long long km_fixed(float v, int S) {
+  return (long long)rint(ldexp((double)v, S));
+}
+
+__device__ __forceinline__ float km_xupdate(float xv, float uv, float lv, float rho, float irho, float eta2,
+                                            int e2) {
+  for (int e = 0; e < e2; ++e) {
+    float delta = rho * (xv - uv - lv * irho);
+    xv = xv - eta2 * delta;
+  }
+  return xv;
+}
+
+struct KMLocal {
+  unsigned long long sum[KWAVES][KM_MAX_K];
+  unsigned cnt[KWAVES][KM_MAX_K];
+  float cent[KM_MAX_K];
+  float red[2 * KWAVES];
+  int redb[KWAVES];
+  int flag;
+  int ok;
+};
+
+// Monotonic per-segment barrier: the b-th barrier of a launch completes when
+// the arrival counter reaches b * G.  Returns false after kSpinLimit polls.
+__device__ bool seg_barrier(KMSync* sy, int G, unsigned b, KMLocal& sh) {
+  if (G == 1) {
+    __syncthreads();
+    return true;
+  }
+  __threadfence();          // every wave's slot stores are visible device-wide
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomicAdd(&sy->arrive, 1u);
+    const unsigned target = b * (unsigned)G;
+    unsigned spins = 0;
+    int ok = 1;
+    while (__hip_atomic_load(&sy->arrive, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(2);
+      if (++spins > kSpinLimit) { ok = 0; break; }
+    }
+    sh.ok = ok;
+  }
+  __syncthreads();
+  __threadfence();
+  return sh.ok != 0;
+}
+
+__device__ void seg_leave(KMSync* sy, int G) {
+  __syncthreads();
+  if (G == 1 || threadIdx.x != 0) return;
+  __threadfence();
+  if (atomicAdd(&sy->leave, 1u) == (unsigned)(G - 1)) {   // last one out resets the barrier
+    atomicExch(&sy->arrive, 0u);
+    atomicExch(&sy->leave, 0u);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T coherent_load(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace
+
+template <bool REG>
+__global__ __launch_bounds__(KT) void k_kmeans_grid(const KMJob* jobs, KMJob single, int G, int k, int max_iter,
+                                                    int e2, KMSlot* slots, KMSync* syncs) {
+#pragma clang fp contract(off)
+  __shared__ KMLocal sh;
+  const int seg = blockIdx.x / G, g = blockIdx.x - seg * G;
+  const KMJob J = jobs ? jobs[seg] : single;
+  if (threadIdx.x == 0) sh.flag = 0;
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const long long chunk = (J.n + G - 1) / G;
+  const long long i0 = min(J.n, (long long)g * chunk), i1 = min(J.n, i0 + chunk);
+  KMSync* sy = syncs + seg;
+  KMSlot* my = slots + ((size_t)seg * G + g) * 2;
+  const KMSlot* all = slots + (size_t)seg * G * 2;
+  unsigned bar = 0;
+  const bool do_x = J.u != nullptr;
+  const float irho = 1.f / J.rho;
+
+  // values of this workgroup's slice (after the optional x-update)
+  float v[REG ? KVPT : 1];
+  float lo = INFINITY, hi = -INFINITY;
+  int bad = 0;
+  if (REG) {
+#pragma unroll
+    for (int e = 0; e < KVPT; ++e) {
+      long long i = i0 + tid + (long long)e * KT;
+      float a = 0.f;
+      if (i < i1) {
+        a = J.src[i];
+        if (do_x) {
+          a = km_xupdate(a, J.u[i], J.lam[i], J.rho, irho, J.eta2, e2);
+          J.x[i] = a;
+        }
+        bad |= !isfinite(a);
+        lo = fminf(lo, a);
+        hi = fmaxf(hi, a);
+      }
+      v[e] = a;
+    }
+  } else {
+    for (long long i = i0 + tid; i < i1; i += KT) {
+      float a = J.src[i];
+      if (do_x) {
+        a = km_xupdate(a, J.u[i], J.lam[i], J.rho, irho, J.eta2, e2);
+        J.x[i] = a;
+      }
+      bad |= !isfinite(a);
+      lo = fminf(lo, a);
+      hi = fmaxf(hi, a);
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = fminf(lo, __shfl_xor(lo, o, 64));
+    hi = fmaxf(hi, __shfl_xor(hi, o, 64));
+    bad |= __shfl_xor(bad, o, 64);
+  }
+  if (l == 0) { sh.red[2 * w] = lo; sh.red[2 * w + 1] = hi; sh.redb[w] = bad; }
+  __syncthreads();
+  if (tid == 0) {
+    float a = sh.red[0], b = sh.red[1];
+    int c = sh.redb[0];
+    for (int i = 1; i < KWAVES; ++i) { a = fminf(a, sh.red[2 * i]); b = fmaxf(b, sh.red[2 * i + 1]); c |= sh.redb[i]; }
+    my[0].mn = a; my[0].mx = b; my[0].bad = c;
+  }
+  bool ok = seg_barrier(sy, G, ++bar, sh);
+  lo = INFINITY; hi = -INFINITY; bad = 0;
+  for (int q = 0; q < G; ++q) {
+    lo = fminf(lo, coherent_load(&all[2 * q].mn));
+    hi = fmaxf(hi, coherent_load(&all[2 * q].mx));
+    bad |= coherent_load(&all[2 * q].bad);
+  }
+  if (!ok || bad || hi == lo) {
+    // constant slice: one cluster at lo; non-finite input or lost barrier: flagged
+    const int code = !ok ? -2 : (bad ? -1 : 0);
+    for (long long i = i0 + tid; i < i1; i += KT) {
+      if (J.labels) J.labels[i] = 0;
+      if (J.a_hat && J.a_hat != J.src) J.a_hat[i] = J.src[i];
+    }
+    if (g == 0) {
+      if (J.cent) for (int j = tid; j < k; j += KT) J.cent[j] = code == 0 ? lo : 0.f;
+      if (J.iters && tid == 0) *J.iters = code;
+    }
+    seg_leave(sy, G);
+    return;
+  }
+  int e;
+  frexp(fmax(fabs((double)lo), fabs((double)hi)), &e);
+  int S;
+  if (J.n <= (1ll << 22)) {
+    S = 40 - e;
+  } else {
+    int lg = 64 - __clzll((unsigned long long)(J.n - 1));   // ceil(log2 n)
+    S = 62 - lg - e;
+  }
+  if (tid < k) {
+    double lo64 = lo, hi64 = hi;
+    double t = (hi64 - lo64) * (double)(2 * tid + 1);
+    t = t / (double)(2 * k);
+    sh.cent[tid] = (float)(lo64 + t);
+  }
+  __syncthreads();
+
+  uint8_t lab[REG ? KVPT : 1];
+  if (REG) {
+#pragma unroll
+    for (int e2i = 0; e2i < KVPT; ++e2i) lab[e2i] = (uint8_t)km_assign(v[e2i], sh.cent, k);
+  } else {
+    for (long long i = i0 + tid; i < i1; i += KT) J.labels[i] = (uint8_t)km_assign(J.src[i], sh.cent, k);
+  }
+
+  int changed = 1, it = 0;
+  for (int t = 1; t <= max_iter; ++t) {
+    // cluster sums of the current labels
+    for (int j = l; j < k; j += 64) { sh.sum[w][j] = 0ull; sh.cnt[w][j] = 0u; }
+    __syncthreads();
+    if (REG) {
+#pragma unroll
+      for (int q = 0; q < KVPT; ++q) {
+        long long i = i0 + tid + (long long)q * KT;
+        if (i < i1) {
+          atomicAdd(&sh.sum[w][lab[q]], (unsigned long long)km_fixed(v[q], S));
+          atomicAdd(&sh.cnt[w][lab[q]], 1u);
+        }
+      }
+    } else {
+      for (long long i = i0 + tid; i < i1; i += KT) {
+        int lb = J.labels[i];
+        atomicAdd(&sh.sum[w][lb], (unsigned long long)km_fixed(J.src[i], S));
+        atomicAdd(&sh.cnt[w][lb], 1u);
+      }
+    }
+    if (changed) sh.flag = 1;   // published with this iteration's sums
+    __syncthreads();
+    KMSlot* slot = my + (t & 1);
+    for (int j = tid; j < k; j += KT) {
+      long long q = 0;
+      unsigned c = 0;
+      for (int ww = 0; ww < KWAVES; ++ww) { q += (long long)sh.sum[ww][j]; c += sh.cnt[ww][j]; }
+      slot->sum[j] = q;
+      slot->cnt[j] = c;
+    }
+    if (tid == 0) { slot->changed = sh.flag; sh.flag = 0; }
+    ok = seg_barrier(sy, G, ++bar, sh);
+    if (!ok) break;
+    // did any slice change its labels in the previous reassignment?
+    int any = 0;
+    for (int q = 0; q < G; ++q) any |= coherent_load(&all[2 * q + (t & 1)].changed);
+    if (t > 1 && !any) break;          // labels of iteration t-1 are final
+    it = t;
+    if (tid < k) {
+      long long q = 0;
+      unsigned long long c = 0;
+      for (int gg = 0; gg < G; ++gg) {
+        q += coherent_load(&all[2 * gg + (t & 1)].sum[tid]);
+        c += coherent_load(&all[2 * gg + (t & 1)].cnt[tid]);
+      }
+      if (c > 0) sh.cent[tid] = (float)(ldexp((double)q, -S) / (double)c);
+    }
+    __syncthreads();
+    changed = 0;
+    if (REG) {
+#pragma unroll
+      for (int q = 0; q < KVPT; ++q) {
+        long long i = i0 + tid + (long long)q * KT;
+        int nl = km_assign(v[q], sh.cent, k);
+        if (i < i1 && nl != lab[q]) changed = 1;
+        lab[q] = (uint8_t)nl;
+      }
+    } else {
+      for (long long i = i0 + tid; i < i1; i += KT) {
+        int nl = km_assign(J.src[i], sh.cent, k);
+        if (nl != J.labels[i]) { changed = 1; J.labels[i] = (uint8_t)nl; }
+      }
+    }
+    __syncthreads();
+  }
+  if (!ok) {
+    if (g == 0 && J.iters && tid == 0) *J.iters = -2;
+    seg_leave(sy, G);
+    return;
+  }
+  if (REG) {
+#pragma unroll
+    for (int q = 0; q < KVPT; ++q) {
+      long long i = i0 + tid + (long long)q * KT;
+      if (i < i1) {
+        if (J.labels) J.labels[i] = lab[q];
+        if (J.a_hat) J.a_hat[i] = sh.cent[lab[q]];
+      }
+    }
+  } else if (J.a_hat) {
+    for (long long i = i0 + tid; i < i1; i += KT) J.a_hat[i] = sh.cent[J.labels[i]];
+  }
+  if (g == 0) {
+    if (J.cent) for (int j = tid; j < k; j += KT) J.cent[j] = sh.cent[j];
+    if (J.iters && tid == 0) *J.iters = it;
+  }
+  seg_leave(sy, G);
+}
+
+template __global__ void k_kmeans_grid<true>(const KMJob*, KMJob, int, int, int, int, KMSlot*, KMSync*);
+template __global__ void k_kmeans_grid<false>(const KMJob*, KMJob, int, int, int, int, KMSlot*, KMSync*);
+
+}  // namespace tomo

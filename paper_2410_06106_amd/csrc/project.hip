@@ -26,6 +26,7 @@ struct AngleParam {
   double xi0;     // interpolation coordinate of ray j = 0 at driving index 0 (LDS units)
   double beta;    // d(xi)/dj
   double gamma;   // d(xi)/d(driving index)
+  double ibeta;   // 1 / beta
   float scale;    // path length per step: 1/|cos| or 1/|sin|
   int cls;        // 0 row-driven, 1 column-driven, -1 inactive
   int bbase;      // detector bin of ray j = 0 for this region
@@ -67,6 +68,7 @@ __global__ __launch_bounds__(PTHREADS) void k_project(Src src) {
   const int a0 = achunk * PA;
   const int na = min(PA, J.n_ang - a0);
   const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   const double h = 0.5 * (J.n - 1), hb = 0.5 * (J.nb - 1);
 
   int gr0, gc0, gh, gw;
@@ -75,7 +77,7 @@ __global__ __launch_bounds__(PTHREADS) void k_project(Src src) {
   if (tid < PA) {
     AngleParam p;
     p.cls = -1;
-    p.xi0 = p.beta = p.gamma = 0.0;
+    p.xi0 = p.beta = p.gamma = p.ibeta = 0.0;
     p.scale = 0.f;
     p.bbase = 0;
     if (tid < na) {
@@ -85,12 +87,14 @@ __global__ __launch_bounds__(PTHREADS) void k_project(Src src) {
       if (fabs(cs) >= fabs(sn)) {   // walk rows, interpolate across columns
         p.cls = 0;
         p.beta = 1.0 / cs;
+        p.ibeta = cs;
         p.gamma = -sn / cs;
         p.xi0 = (p.bbase - hb - (gr0 - h) * sn) / cs + h - gc0 + PPAD;
         p.scale = (float)(1.0 / fabs(cs));
       } else {                      // walk columns, interpolate across rows
         p.cls = 1;
         p.beta = 1.0 / sn;
+        p.ibeta = sn;
         p.gamma = -cs / sn;
         p.xi0 = (p.bbase - hb - (gc0 - h) * cs) / sn + h - gr0 + PPAD;
         p.scale = (float)(1.0 / fabs(sn));
@@ -100,6 +104,10 @@ __global__ __launch_bounds__(PTHREADS) void k_project(Src src) {
   }
   for (int i = tid; i < PA * PACC; i += PTHREADS) acc[i] = 0.f;
   __syncthreads();
+
+  // vectorised staging needs 16-byte aligned rows and region corners
+  const bool vec4 = ((J.n & 3) == 0) && ((gc0 & 3) == 0) &&
+                    ((reinterpret_cast<uintptr_t>(J.img) & 15) == 0);
 
   for (int cls = 0; cls < 2; ++cls) {
     bool any = false;
@@ -113,55 +121,95 @@ __global__ __launch_bounds__(PTHREADS) void k_project(Src src) {
 
     for (int db = 0; db < D; db += PR) {
       __syncthreads();
-      // stage R driving lines of the region (zero beyond D)
+      // stage PR driving lines of the region (lines beyond D stay zero)
+      const int nl = min(PR, D - db);
       if (cls == 0) {
-        for (int idx = tid; idx < PR * W; idx += PTHREADS) {
-          int i = idx / W, k = idx - i * W;
-          float v = 0.f;
-          if (db + i < D) v = J.img[(size_t)(gr0 + db + i) * J.n + gc0 + k];
-          band[i * PLS + PPAD + k] = v;
+        if (vec4) {
+          const int W4 = W >> 2;        // W is a multiple of 4 when vec4 holds
+          for (int i = tid >> 6; i < PR; i += PTHREADS / 64) {
+            float* dst = band + i * PLS + PPAD;
+            if (i < nl) {
+              const float4* src4 = reinterpret_cast<const float4*>(J.img + (size_t)(gr0 + db + i) * J.n + gc0);
+              for (int k = lane; k < W4; k += 64) {
+                float4 v = src4[k];
+                dst[4 * k] = v.x; dst[4 * k + 1] = v.y; dst[4 * k + 2] = v.z; dst[4 * k + 3] = v.w;
+              }
+            } else {
+              for (int k = lane; k < W; k += 64) dst[k] = 0.f;
+            }
+          }
+        } else {
+          for (int i = 0; i < PR; ++i) {
+            float* dst = band + i * PLS + PPAD;
+            const float* srow = J.img + (size_t)(gr0 + db + i) * J.n + gc0;
+            for (int k = tid; k < W; k += PTHREADS) dst[k] = i < nl ? srow[k] : 0.f;
+          }
         }
       } else {
-        for (int idx = tid; idx < PR * W; idx += PTHREADS) {
-          int k = idx / PR, i = idx - k * PR;
-          float v = 0.f;
-          if (db + i < D) v = J.img[(size_t)(gr0 + k) * J.n + gc0 + db + i];
-          band[i * PLS + PPAD + k] = v;
+        if (vec4) {
+          // thread -> (image row k, 4 adjacent band columns), written transposed
+          const int q = tid & 3;
+          for (int k = tid >> 2; k < W; k += PTHREADS / 4) {
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            const int c = db + 4 * q;
+            if (c < D) v = *reinterpret_cast<const float4*>(J.img + (size_t)(gr0 + k) * J.n + gc0 + c);
+            // columns beyond D inside a partial group are masked individually
+            band[(4 * q + 0) * PLS + PPAD + k] = (c + 0 < D) ? v.x : 0.f;
+            band[(4 * q + 1) * PLS + PPAD + k] = (c + 1 < D) ? v.y : 0.f;
+            band[(4 * q + 2) * PLS + PPAD + k] = (c + 2 < D) ? v.z : 0.f;
+            band[(4 * q + 3) * PLS + PPAD + k] = (c + 3 < D) ? v.w : 0.f;
+          }
+        } else {
+          for (int k = tid >> 4; k < W; k += PTHREADS / 16) {
+            const int i = tid & 15;
+            float v = (i < nl) ? J.img[(size_t)(gr0 + k) * J.n + gc0 + db + i] : 0.f;
+            band[i * PLS + PPAD + k] = v;
+          }
         }
       }
       __syncthreads();
 
-      // rays of each angle of this class that meet the band
-      int jlo[PA], cnt[PA], pre[PA + 1];
-      pre[0] = 0;
+      // rays of each angle of this class that meet the band (wave-uniform values)
+      int jlo[PA], jhi[PA], nch[PA];
+      double xib[PA];
+      int tot = 0;
 #pragma unroll
       for (int a = 0; a < PA; ++a) {
         jlo[a] = 0;
-        cnt[a] = 0;
+        jhi[a] = -1;
+        nch[a] = 0;
+        xib[a] = 0.0;
         if (a < na && prm[a].cls == cls) {
-          const AngleParam p = prm[a];
-          double e0 = p.xi0 + db * p.gamma, e1 = p.xi0 + (db + PR - 1) * p.gamma;
+          const double x0 = prm[a].xi0, gm = prm[a].gamma, ib = prm[a].ibeta;
+          double e0 = x0 + db * gm, e1 = x0 + (db + PR - 1) * gm;
           double emin = fmin(e0, e1), emax = fmax(e0, e1);
-          double lo = (PPAD - 1 - emax) / p.beta, hi = (PPAD + W - emin) / p.beta;
+          double lo = (PPAD - 1 - emax) * ib, hi = (PPAD + W - emin) * ib;
           if (lo > hi) { double t = lo; lo = hi; hi = t; }
-          int jl = max((int)floor(lo), max(0, -p.bbase));
-          int jh = min((int)ceil(hi), min(PACC - 1, J.nb - 1 - p.bbase));
+          const int bb = prm[a].bbase;
+          int jl = max((int)floor(lo), max(0, -bb));
+          int jh = min((int)ceil(hi), min(PACC - 1, J.nb - 1 - bb));
           jlo[a] = jl;
-          cnt[a] = max(0, jh - jl + 1);
+          jhi[a] = jh;
+          nch[a] = jh >= jl ? ((jh - jl + 1 + 63) >> 6) : 0;
+          xib[a] = e0;
         }
-        pre[a + 1] = pre[a] + cnt[a];
+        tot += nch[a];
       }
-      const int total = pre[PA];
-      for (int pidx = tid; pidx < total; pidx += PTHREADS) {
-        int a = 0;
+      // each wave takes chunks of 64 consecutive rays of one angle
+      for (int ch = wave; ch < tot; ch += PTHREADS / 64) {
+        int a = 0, base = 0;
 #pragma unroll
-        for (int q = 1; q < PA; ++q) a += (pidx >= pre[q]) ? 1 : 0;
-        int pa = 0, ja = 0;
+        for (int q = 0; q < PA - 1; ++q) {
+          if (ch >= base + nch[a]) { base += nch[a]; ++a; }
+        }
+        int ja = 0, jb = -1;
+        double xa = 0.0;
 #pragma unroll
-        for (int q = 0; q < PA; ++q) if (q == a) { pa = pre[q]; ja = jlo[q]; }
-        const int j = ja + (pidx - pa);
+        for (int q = 0; q < PA; ++q) if (q == a) { ja = jlo[q]; jb = jhi[q]; xa = xib[q]; }
+        const int j = ja + ((ch - base) << 6) + lane;
         const AngleParam& p = prm[a];
-        const float xi = (float)(p.xi0 + j * p.beta + db * p.gamma);
+        if (j > jb) continue;
+        const float xi = (float)(xa + (double)j * p.beta);
         const float g = (float)p.gamma;
         float s0 = 0.f, s1 = 0.f;
 #pragma unroll
