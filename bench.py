@@ -56,7 +56,7 @@ def _traffic(kernel: str):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(w, sample_nodes=2):
+def cpu_baseline(w, sample_nodes=8):
     """The oracle's Alg. 2 local update (E1 steps of P and P^T) on a sample of
     the workload's nodes, timed on the host; returns ray-voxel updates/s."""
     import numpy as np
@@ -190,10 +190,10 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        log("cpu baseline: oracle local update on 2 of 16 nodes ...")
+        log("cpu baseline: oracle local update on 8 of 16 nodes ...")
         v_cpu, dt = cpu_baseline(w)
         cpu = {"value": v_cpu, "unit": "updates/s", "cores": 1, "kind": "oracle",
-               "sample": f"Alg. 2 local update (E1={w.inner_iters}: P and P^T) of nodes 0-1 of {w.n_nodes}, "
+               "sample": f"Alg. 2 local update (E1={w.inner_iters}: P and P^T) of nodes 0-7 of {w.n_nodes}, "
                          f"{w.n}^2, {w.n_angles // w.n_nodes} angles each, float64 NumPy, {dt:.1f} s"}
 
     out = {

@@ -61,12 +61,15 @@ ProjShape base_shape(int n, int n_ang) {
 // Halve the regions of a job (rows first, sides >= 64) until the job alone
 // spans kJobWGs workgroups.  The decomposition depends on the job only, so a
 // node gives bit-identical results whether it is launched alone or batched.
+// Region sides stay multiples of 16 so that rows of a region start on
+// 16-byte boundaries whenever the image side is a multiple of 4.
 void split_for_parallelism(ProjShape& s, int n) {
+  auto half = [](int r) { return ((r / 2) + 15) & ~15; };
   while (s.wgs() < kJobWGs && s.regions() < 64) {
     if (s.reg_h >= s.reg_w && s.reg_h >= 128) {
-      s.reg_h /= 2; s.n_rr = (n + s.reg_h - 1) / s.reg_h;
+      s.reg_h = half(s.reg_h); s.n_rr = (n + s.reg_h - 1) / s.reg_h;
     } else if (s.reg_w >= 128) {
-      s.reg_w /= 2; s.n_rc = (n + s.reg_w - 1) / s.reg_w;
+      s.reg_w = half(s.reg_w); s.n_rc = (n + s.reg_w - 1) / s.reg_w;
     } else {
       break;
     }

@@ -106,7 +106,7 @@ __global__ __launch_bounds__(PTHREADS) void k_project(Src src) {
   __syncthreads();
 
   // vectorised staging needs 16-byte aligned rows and region corners
-  const bool vec4 = ((J.n & 3) == 0) && ((gc0 & 3) == 0) &&
+  const bool vec4 = ((J.n & 3) == 0) && ((gc0 & 3) == 0) && ((gw & 3) == 0) &&
                     ((reinterpret_cast<uintptr_t>(J.img) & 15) == 0);
 
   for (int cls = 0; cls < 2; ++cls) {
