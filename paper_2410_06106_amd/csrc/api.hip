@@ -28,7 +28,8 @@ static_assert(sizeof(tomo_msg) == 40, "tomo_msg must have no padding");
 
 namespace {
 
-constexpr int kJobWGs = 64;   // projector workgroups wanted per job
+constexpr int kJobWGs = 64;      // projector workgroups wanted per job
+constexpr int kMaxRegions = PMAXREG;  // regions per projector job (finalizer table size)
 
 struct DevBuf {
   void* p = nullptr;
@@ -65,14 +66,17 @@ ProjShape base_shape(int n, int n_ang) {
 // 16-byte boundaries whenever the image side is a multiple of 4.
 void split_for_parallelism(ProjShape& s, int n) {
   auto half = [](int r) { return ((r / 2) + 15) & ~15; };
-  while (s.wgs() < kJobWGs && s.regions() < 64) {
-    if (s.reg_h >= s.reg_w && s.reg_h >= 128) {
-      s.reg_h = half(s.reg_h); s.n_rr = (n + s.reg_h - 1) / s.reg_h;
-    } else if (s.reg_w >= 128) {
-      s.reg_w = half(s.reg_w); s.n_rc = (n + s.reg_w - 1) / s.reg_w;
+  while (s.wgs() < kJobWGs) {
+    ProjShape c = s;
+    if (c.reg_h >= c.reg_w && c.reg_h >= 128) {
+      c.reg_h = half(c.reg_h); c.n_rr = (n + c.reg_h - 1) / c.reg_h;
+    } else if (c.reg_w >= 128) {
+      c.reg_w = half(c.reg_w); c.n_rc = (n + c.reg_w - 1) / c.reg_w;
     } else {
       break;
     }
+    if (c.regions() > kMaxRegions) break;
+    s = c;
   }
 }
 
@@ -139,8 +143,8 @@ int set_device(tomo_ctx* ctx) {
 
 int check_geom(tomo_ctx* ctx, tomo_geom g) {
   if (g.n < 1 || g.n_bins < 1) return ctx->fail(TOMO_EINVAL, "geometry needs n >= 1 and n_bins >= 1");
-  // the projector's finalizer holds at most 64 regions of <= 512 x 512 pixels
-  if (g.n > 8 * PREG || (long long)g.n_bins > (1 << 24))
+  // the projector's finalizer holds at most PMAXREG regions of <= PREG x PREG pixels
+  if (g.n > 16 * PREG || (long long)g.n_bins > (1 << 24))
     return ctx->fail(TOMO_EUNSUPPORTED, "image side above 4096 or more than 2^24 bins");
   return TOMO_OK;
 }

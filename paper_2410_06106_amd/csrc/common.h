@@ -43,8 +43,9 @@ struct Many {
 // a chunk (ticket counter) adds the regions' partials in region order.
 // ---------------------------------------------------------------------------
 constexpr int PA = 4;          // angles per workgroup
-constexpr int PACC = 768;      // ray accumulators per angle and region
-constexpr int PREG = 512;      // max region side
+constexpr int PREG = 256;      // max region side
+constexpr int PACC = 384;      // ray accumulators per angle and region (>= PREG * sqrt(2) + 3)
+constexpr int PMAXREG = 256;   // max regions per job
 constexpr int PTHREADS = 256;
 
 struct ProjJob {

@@ -96,10 +96,6 @@ __device__ void seg_leave(KMSync* sy, int G) {
   }
 }
 
-template <typename T>
-__device__ __forceinline__ T coherent_load(const T* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 }  // namespace
 
@@ -170,9 +166,9 @@ __global__ __launch_bounds__(KT) void k_kmeans_grid(const KMJob* jobs, KMJob sin
   bool ok = seg_barrier(sy, G, ++bar, sh);
   lo = INFINITY; hi = -INFINITY; bad = 0;
   for (int q = 0; q < G; ++q) {
-    lo = fminf(lo, coherent_load(&all[2 * q].mn));
-    hi = fmaxf(hi, coherent_load(&all[2 * q].mx));
-    bad |= coherent_load(&all[2 * q].bad);
+    lo = fminf(lo, all[2 * q].mn);
+    hi = fmaxf(hi, all[2 * q].mx);
+    bad |= all[2 * q].bad;
   }
   if (!ok || bad || hi == lo) {
     // constant slice: one cluster at lo; non-finite input or lost barrier: flagged
@@ -249,15 +245,15 @@ __global__ __launch_bounds__(KT) void k_kmeans_grid(const KMJob* jobs, KMJob sin
     if (!ok) break;
     // did any slice change its labels in the previous reassignment?
     int any = 0;
-    for (int q = 0; q < G; ++q) any |= coherent_load(&all[2 * q + (t & 1)].changed);
+    for (int q = 0; q < G; ++q) any |= all[2 * q + (t & 1)].changed;
     if (t > 1 && !any) break;          // labels of iteration t-1 are final
     it = t;
     if (tid < k) {
       long long q = 0;
       unsigned long long c = 0;
       for (int gg = 0; gg < G; ++gg) {
-        q += coherent_load(&all[2 * gg + (t & 1)].sum[tid]);
-        c += coherent_load(&all[2 * gg + (t & 1)].cnt[tid]);
+        q += all[2 * gg + (t & 1)].sum[tid];
+        c += all[2 * gg + (t & 1)].cnt[tid];
       }
       if (c > 0) sh.cent[tid] = (float)(ldexp((double)q, -S) / (double)c);
     }

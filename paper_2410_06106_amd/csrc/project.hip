@@ -58,7 +58,7 @@ __global__ __launch_bounds__(PTHREADS) void k_project(Src src) {
   __shared__ float acc[PA * PACC];
   __shared__ AngleParam prm[PA];
   __shared__ int s_last;
-  __shared__ int fin_bbase[64 * PA];
+  __shared__ int fin_bbase[PMAXREG * PA];
 
   int lid;
   const ProjJob J = src.get(blockIdx.x, lid);
