@@ -11,6 +11,7 @@
 
 namespace tomo {
 template <class Src> __global__ void k_project(Src);
+template <class Src> __global__ void k_project_reduce(Src);
 template <class Src> __global__ void k_backproject(Src);
 __global__ void k_seg_none(const SegJob*, int, int);
 template <bool REG> __global__ void k_kmeans_grid(const KMJob*, KMJob, int, int, int, int, KMSlot*, KMSync*);
@@ -87,8 +88,8 @@ bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
 
 struct LocalPlan {
   std::vector<tomo_node> key;
-  DevBuf pjobs, bjobs, resid, partial, tickets;
-  int n_p = 0, p_wgs = 0, n_b = 0, b_wgs = 0;
+  DevBuf pjobs, rjobs, bjobs, resid, partial;
+  int n_p = 0, p_wgs = 0, n_r = 0, r_wgs = 0, n_b = 0, b_wgs = 0;
 };
 
 struct ConsPlan {
@@ -121,7 +122,7 @@ struct tomo_ctx {
   int device = 0;
   int n_cu = 1;
   std::string err;
-  DevBuf partial, tickets;                       // standalone projector workspace
+  DevBuf partial;                                // standalone projector workspace
   DevBuf km_slots, km_sync;                      // standalone K-means workspace
   std::vector<std::unique_ptr<LocalPlan>> lplans;
   std::vector<std::unique_ptr<ConsPlan>> cplans;
@@ -207,43 +208,40 @@ LocalPlan* get_local_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, in
   auto plan = std::make_unique<LocalPlan>();
   plan->key.assign(nodes, nodes + n_nodes);
   std::vector<ProjShape> shapes;
-  size_t resid_elems = 0, part_elems = 0, tick_elems = 0;
+  size_t resid_elems = 0, part_elems = 0;
   for (int i = 0; i < n_nodes; ++i) {
     shapes.push_back(base_shape(nodes[i].g.n, nodes[i].n_ang));
     split_for_parallelism(shapes.back(), nodes[i].g.n);
   }
-  std::vector<size_t> roff(n_nodes), poff(n_nodes), toff(n_nodes);
+  std::vector<size_t> roff(n_nodes), poff(n_nodes);
   for (int i = 0; i < n_nodes; ++i) {
     roff[i] = resid_elems;
     resid_elems += (size_t)nodes[i].n_ang * nodes[i].g.n_bins;
     poff[i] = part_elems;
     if (shapes[i].regions() > 1) part_elems += (size_t)shapes[i].wgs() * PA * PACC;
-    toff[i] = tick_elems;
-    tick_elems += shapes[i].n_achunk;
   }
-  if (!plan->resid.ensure(resid_elems * 4) || !plan->partial.ensure(std::max<size_t>(part_elems, 1) * 4) ||
-      !plan->tickets.ensure(tick_elems * 4)) {
+  if (!plan->resid.ensure(resid_elems * 4) || !plan->partial.ensure(std::max<size_t>(part_elems, 1) * 4)) {
     rc = ctx->fail(TOMO_ENOMEM, "plan workspace allocation failed");
     return nullptr;
   }
-  if (hipMemset(plan->tickets.p, 0, tick_elems * 4) != hipSuccess) {
-    rc = ctx->fail(TOMO_EDEVICE, "hipMemset failed");
-    return nullptr;
-  }
-  std::vector<ProjJob> pj;
+  std::vector<ProjJob> pj, rj;
   std::vector<BPJob> bj;
-  int pw = 0, bw = 0;
+  int pw = 0, rw = 0, bw = 0;
   float* R = static_cast<float*>(plan->resid.p);
   float* PP = static_cast<float*>(plan->partial.p);
-  unsigned* T = static_cast<unsigned*>(plan->tickets.p);
   for (int i = 0; i < n_nodes; ++i) {
     const tomo_node& N = nodes[i];
     ProjJob j = make_proj_job(N.u, N.angles, N.d, R + roff[i], N.g.n, N.g.n_bins, N.n_ang, shapes[i]);
     j.partial = PP + poff[i];
-    j.ticket = T + toff[i];
     j.wg_begin = pw;
     pw += shapes[i].wgs();
     pj.push_back(j);
+    if (shapes[i].regions() > 1) {     // reduction launch: one workgroup per angle chunk
+      ProjJob r = j;
+      r.wg_begin = rw;
+      rw += shapes[i].n_achunk;
+      rj.push_back(r);
+    }
     BPJob b = make_bp_job(R + roff[i], N.angles, N.u, N.g.n, N.g.n_bins, N.n_ang);
     b.mode = BP_ADMM;
     b.x = N.x;
@@ -254,21 +252,38 @@ LocalPlan* get_local_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, in
     bw += b.tiles_x * b.tiles_x;
     bj.push_back(b);
   }
-  if (!plan->pjobs.ensure(pj.size() * sizeof(ProjJob)) || !plan->bjobs.ensure(bj.size() * sizeof(BPJob))) {
+  if (!plan->pjobs.ensure(pj.size() * sizeof(ProjJob)) || !plan->bjobs.ensure(bj.size() * sizeof(BPJob)) ||
+      !plan->rjobs.ensure(std::max<size_t>(rj.size(), 1) * sizeof(ProjJob))) {
     rc = ctx->fail(TOMO_ENOMEM, "plan descriptor allocation failed");
     return nullptr;
   }
   if (hipMemcpy(plan->pjobs.p, pj.data(), pj.size() * sizeof(ProjJob), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(plan->bjobs.p, bj.data(), bj.size() * sizeof(BPJob), hipMemcpyHostToDevice) != hipSuccess) {
+      hipMemcpy(plan->bjobs.p, bj.data(), bj.size() * sizeof(BPJob), hipMemcpyHostToDevice) != hipSuccess ||
+      (!rj.empty() &&
+       hipMemcpy(plan->rjobs.p, rj.data(), rj.size() * sizeof(ProjJob), hipMemcpyHostToDevice) != hipSuccess)) {
     rc = ctx->fail(TOMO_EDEVICE, "descriptor upload failed");
     return nullptr;
   }
+  plan->n_r = (int)rj.size();
+  plan->r_wgs = rw;
   plan->n_p = (int)pj.size();
   plan->p_wgs = pw;
   plan->n_b = (int)bj.size();
   plan->b_wgs = bw;
   ctx->lplans.push_back(std::move(plan));
   return ctx->lplans.back().get();
+}
+
+// Residual r = P u - d of every node of a plan: the region pass, then (for
+// nodes split into several regions) the reduction pass.
+void launch_projection(const LocalPlan* plan, void* stream) {
+  Many<ProjJob> ps{static_cast<const ProjJob*>(plan->pjobs.p), plan->n_p};
+  hipLaunchKernelGGL(k_project<Many<ProjJob>>, dim3(plan->p_wgs), dim3(PTHREADS), 0, (hipStream_t)stream, ps);
+  if (plan->n_r > 0) {
+    Many<ProjJob> rs{static_cast<const ProjJob*>(plan->rjobs.p), plan->n_r};
+    hipLaunchKernelGGL(k_project_reduce<Many<ProjJob>>, dim3(plan->r_wgs), dim3(PTHREADS), 0, (hipStream_t)stream,
+                       rs);
+  }
 }
 
 bool same_msg(const std::vector<tomo_msg>& k, const tomo_msg* msg, int n) {
@@ -419,15 +434,13 @@ int tomo_project(tomo_ctx* ctx, tomo_geom g, const double* angles, int32_t n_ang
   ProjJob j = make_proj_job(image, angles, nullptr, sino, g.n, g.n_bins, n_ang, sh[0]);
   if (sh[0].regions() > 1) {
     if (!ctx->partial.ensure((size_t)sh[0].wgs() * PA * PACC * 4)) return ctx->fail(TOMO_ENOMEM, "workspace");
-    size_t had = ctx->tickets.bytes;
-    if (!ctx->tickets.ensure((size_t)sh[0].n_achunk * 4)) return ctx->fail(TOMO_ENOMEM, "workspace");
-    if (ctx->tickets.bytes != had && hipMemset(ctx->tickets.p, 0, ctx->tickets.bytes) != hipSuccess)
-      return ctx->fail(TOMO_EDEVICE, "hipMemset failed");
     j.partial = static_cast<float*>(ctx->partial.p);
-    j.ticket = static_cast<unsigned*>(ctx->tickets.p);
   }
   hipLaunchKernelGGL(k_project<Single<ProjJob>>, dim3(sh[0].wgs()), dim3(PTHREADS), 0,
                      (hipStream_t)stream, Single<ProjJob>{j});
+  if (sh[0].regions() > 1)
+    hipLaunchKernelGGL(k_project_reduce<Single<ProjJob>>, dim3(sh[0].n_achunk), dim3(PTHREADS), 0,
+                       (hipStream_t)stream, Single<ProjJob>{j});
   return launch_status(ctx, "tomo_project");
 }
 
@@ -461,10 +474,9 @@ int admm_local_update(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, in
     plan = get_local_plan(ctx, nodes, n_nodes, rc);
   }
   if (!plan) return rc;
-  Many<ProjJob> ps{static_cast<const ProjJob*>(plan->pjobs.p), plan->n_p};
   Many<BPJob> bs{static_cast<const BPJob*>(plan->bjobs.p), plan->n_b};
   for (int e = 0; e < e1; ++e) {
-    hipLaunchKernelGGL(k_project<Many<ProjJob>>, dim3(plan->p_wgs), dim3(PTHREADS), 0, (hipStream_t)stream, ps);
+    launch_projection(plan, stream);
     hipLaunchKernelGGL(k_backproject<Many<BPJob>>, dim3(plan->b_wgs), dim3(BTHREADS), 0, (hipStream_t)stream, bs);
   }
   return launch_status(ctx, "admm_local_update");
@@ -483,8 +495,7 @@ int admm_local_phase(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, int
   }
   if (!plan) return rc;
   if (phase == 0) {
-    Many<ProjJob> ps{static_cast<const ProjJob*>(plan->pjobs.p), plan->n_p};
-    hipLaunchKernelGGL(k_project<Many<ProjJob>>, dim3(plan->p_wgs), dim3(PTHREADS), 0, (hipStream_t)stream, ps);
+    launch_projection(plan, stream);
   } else {
     Many<BPJob> bs{static_cast<const BPJob*>(plan->bjobs.p), plan->n_b};
     hipLaunchKernelGGL(k_backproject<Many<BPJob>>, dim3(plan->b_wgs), dim3(BTHREADS), 0, (hipStream_t)stream, bs);

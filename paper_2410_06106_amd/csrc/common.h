@@ -39,8 +39,8 @@ struct Many {
 // ---------------------------------------------------------------------------
 // Forward projector: one job = one image and one set of angles.
 // Decomposition: angle chunks of PA angles x rectangular image regions.
-// Each (chunk, region) workgroup writes partial ray sums; the last workgroup of
-// a chunk (ticket counter) adds the regions' partials in region order.
+// Each (chunk, region) workgroup writes partial ray sums; with more than one
+// region a reduction launch (one workgroup per chunk) adds them in order.
 // ---------------------------------------------------------------------------
 constexpr int PA = 4;          // angles per workgroup
 constexpr int PREG = 256;      // max region side
@@ -54,12 +54,11 @@ struct ProjJob {
   const float* d;       // [n_ang][nb] or null: out = scale * P img - d
   float* out;           // [n_ang][nb]
   float* partial;       // [n_achunk][G][PA][PACC]
-  unsigned* ticket;     // [n_achunk], zero between launches
   int n, nb, n_ang;
   int n_achunk;
   int reg_h, reg_w;     // region size (<= PREG)
   int n_rr, n_rc;       // regions down / across
-  int wg_begin;
+  int wg_begin;         // first workgroup of this job in its launch
   float scale;
 };
 

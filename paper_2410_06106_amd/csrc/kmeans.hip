@@ -63,26 +63,30 @@ struct KMLocal {
 
 // Monotonic per-segment barrier: the b-th barrier of a launch completes when
 // the arrival counter reaches b * G.  Returns false after kSpinLimit polls.
+// Device-scope cache maintenance is expensive on this chip (a release writes
+// back, an acquire invalidates the L2 of the XCD), so each workgroup performs
+// exactly one release (before arriving) and one acquire (after the counter has
+// reached the target); the polling itself uses relaxed loads.
 __device__ bool seg_barrier(KMSync* sy, int G, unsigned b, KMLocal& sh) {
   if (G == 1) {
     __syncthreads();
     return true;
   }
-  __threadfence();          // every wave's slot stores are visible device-wide
+  __builtin_amdgcn_s_waitcnt(0);   // this wave's slot stores have completed
   __syncthreads();
   if (threadIdx.x == 0) {
-    atomicAdd(&sy->arrive, 1u);
+    __hip_atomic_fetch_add(&sy->arrive, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     const unsigned target = b * (unsigned)G;
     unsigned spins = 0;
     int ok = 1;
-    while (__hip_atomic_load(&sy->arrive, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (__hip_atomic_load(&sy->arrive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       __builtin_amdgcn_s_sleep(2);
       if (++spins > kSpinLimit) { ok = 0; break; }
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     sh.ok = ok;
   }
   __syncthreads();
-  __threadfence();
   return sh.ok != 0;
 }
 

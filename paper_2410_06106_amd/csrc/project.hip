@@ -9,9 +9,9 @@
 // staged band serves all PA angles.  LDS pads of R+3 zero samples on both sides
 // of a band row mean the inner loop needs no bounds checks; pixels outside the
 // region count as zero, so the region's partial ray sums add up exactly to the
-// full projection.  The last workgroup of an angle chunk (ticket counter) adds
-// the partials of all regions in region order: no atomics on data, results are
-// bit-reproducible.
+// full projection.  When a job has several regions, a second small launch adds
+// the regions' partials in region order: no atomics and no cross-workgroup
+// handshakes inside a launch, results are bit-reproducible.
 #include "common.h"
 
 namespace tomo {
@@ -57,8 +57,6 @@ __global__ __launch_bounds__(PTHREADS) void k_project(Src src) {
   __shared__ float band[PR * PLS];
   __shared__ float acc[PA * PACC];
   __shared__ AngleParam prm[PA];
-  __shared__ int s_last;
-  __shared__ int fin_bbase[PMAXREG * PA];
 
   int lid;
   const ProjJob J = src.get(blockIdx.x, lid);
@@ -240,20 +238,27 @@ __global__ __launch_bounds__(PTHREADS) void k_project(Src src) {
     return;
   }
 
-  // partial sums of this region, pre-scaled by the path length per step
+  // partial sums of this region, pre-scaled by the path length per step; a
+  // separate launch (k_project_reduce) adds the regions in region order
   float* part = J.partial + ((size_t)achunk * G + region) * (PA * PACC);
   for (int i = tid; i < PA * PACC; i += PTHREADS) {
     int a = i / PACC;
     part[i] = a < na ? acc[i] * prm[a].scale : 0.f;
   }
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) s_last = (atomicAdd(&J.ticket[achunk], 1u) == (unsigned)(G - 1));
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
+}
 
-  // last region of this angle chunk: add all regions' partials in order
+// Sum of the regions' partial ray sums of one angle chunk (one workgroup per
+// chunk of a job with more than one region): out = scale * sum - d.
+template <class Src>
+__global__ __launch_bounds__(PTHREADS) void k_project_reduce(Src src) {
+  __shared__ int fin_bbase[PMAXREG * PA];
+  int achunk;
+  const ProjJob J = src.get(blockIdx.x, achunk);
+  const int G = J.n_rr * J.n_rc;
+  const int a0 = achunk * PA;
+  const int na = min(PA, J.n_ang - a0);
+  const int tid = threadIdx.x;
+  const double h = 0.5 * (J.n - 1), hb = 0.5 * (J.nb - 1);
   for (int i = tid; i < G * PA; i += PTHREADS) {
     int g = i / PA, a = i - g * PA;
     int bb = 0;
@@ -278,10 +283,11 @@ __global__ __launch_bounds__(PTHREADS) void k_project(Src src) {
     size_t o = (size_t)(a0 + a) * J.nb + b;
     J.out[o] = J.d ? s - J.d[o] : s;
   }
-  if (tid == 0) J.ticket[achunk] = 0u;
 }
 
 template __global__ void k_project<Single<ProjJob>>(Single<ProjJob>);
 template __global__ void k_project<Many<ProjJob>>(Many<ProjJob>);
+template __global__ void k_project_reduce<Single<ProjJob>>(Single<ProjJob>);
+template __global__ void k_project_reduce<Many<ProjJob>>(Many<ProjJob>);
 
 }  // namespace tomo
