@@ -52,6 +52,10 @@ struct ProjShape {
   int regions() const { return n_rr * n_rc; }
 };
 
+int reduce_wgs(const ProjShape& s, int n_bins) {
+  return s.n_achunk * ((n_bins + PTHREADS - 1) / PTHREADS);
+}
+
 ProjShape base_shape(int n, int n_ang) {
   ProjShape s;
   s.n_achunk = (n_ang + PA - 1) / PA;
@@ -236,10 +240,10 @@ LocalPlan* get_local_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, in
     j.wg_begin = pw;
     pw += shapes[i].wgs();
     pj.push_back(j);
-    if (shapes[i].regions() > 1) {     // reduction launch: one workgroup per angle chunk
+    if (shapes[i].regions() > 1) {     // reduction launch: angle chunks x bin blocks
       ProjJob r = j;
       r.wg_begin = rw;
-      rw += shapes[i].n_achunk;
+      rw += reduce_wgs(shapes[i], N.g.n_bins);
       rj.push_back(r);
     }
     BPJob b = make_bp_job(R + roff[i], N.angles, N.u, N.g.n, N.g.n_bins, N.n_ang);
@@ -439,7 +443,7 @@ int tomo_project(tomo_ctx* ctx, tomo_geom g, const double* angles, int32_t n_ang
   hipLaunchKernelGGL(k_project<Single<ProjJob>>, dim3(sh[0].wgs()), dim3(PTHREADS), 0,
                      (hipStream_t)stream, Single<ProjJob>{j});
   if (sh[0].regions() > 1)
-    hipLaunchKernelGGL(k_project_reduce<Single<ProjJob>>, dim3(sh[0].n_achunk), dim3(PTHREADS), 0,
+    hipLaunchKernelGGL(k_project_reduce<Single<ProjJob>>, dim3(reduce_wgs(sh[0], g.n_bins)), dim3(PTHREADS), 0,
                        (hipStream_t)stream, Single<ProjJob>{j});
   return launch_status(ctx, "tomo_project");
 }

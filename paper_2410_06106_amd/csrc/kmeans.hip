@@ -63,10 +63,12 @@ struct KMLocal {
 
 // Monotonic per-segment barrier: the b-th barrier of a launch completes when
 // the arrival counter reaches b * G.  Returns false after kSpinLimit polls.
-// Device-scope cache maintenance is expensive on this chip (a release writes
-// back, an acquire invalidates the L2 of the XCD), so each workgroup performs
-// exactly one release (before arriving) and one acquire (after the counter has
-// reached the target); the polling itself uses relaxed loads.
+// Cross-workgroup data of a segment (the statistic slots and the barrier
+// counter) is only ever accessed with device-scope atomic loads and stores,
+// which are coherent across the XCDs without cache maintenance; a device-scope
+// release or acquire fence would write back or invalidate a whole L2, which
+// costs more than the Lloyd iteration itself.  Before arriving, every wave
+// waits for its own slot stores to complete.
 __device__ bool seg_barrier(KMSync* sy, int G, unsigned b, KMLocal& sh) {
   if (G == 1) {
     __syncthreads();
@@ -75,28 +77,37 @@ __device__ bool seg_barrier(KMSync* sy, int G, unsigned b, KMLocal& sh) {
   __builtin_amdgcn_s_waitcnt(0);   // this wave's slot stores have completed
   __syncthreads();
   if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(&sy->arrive, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(&sy->arrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const unsigned target = b * (unsigned)G;
     unsigned spins = 0;
     int ok = 1;
     while (__hip_atomic_load(&sy->arrive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      __builtin_amdgcn_s_sleep(2);
+      __builtin_amdgcn_s_sleep(1);
       if (++spins > kSpinLimit) { ok = 0; break; }
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     sh.ok = ok;
   }
   __syncthreads();
   return sh.ok != 0;
 }
 
+template <typename T>
+__device__ __forceinline__ void put(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T>
+__device__ __forceinline__ T get(const T* p) {
+  return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ void seg_leave(KMSync* sy, int G) {
   __syncthreads();
   if (G == 1 || threadIdx.x != 0) return;
-  __threadfence();
-  if (atomicAdd(&sy->leave, 1u) == (unsigned)(G - 1)) {   // last one out resets the barrier
-    atomicExch(&sy->arrive, 0u);
-    atomicExch(&sy->leave, 0u);
+  // every workgroup has passed its last barrier: the last one out resets them
+  if (__hip_atomic_fetch_add(&sy->leave, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (unsigned)(G - 1)) {
+    __hip_atomic_store(&sy->arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&sy->leave, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -165,14 +176,16 @@ __global__ __launch_bounds__(KT) void k_kmeans_grid(const KMJob* jobs, KMJob sin
     float a = sh.red[0], b = sh.red[1];
     int c = sh.redb[0];
     for (int i = 1; i < KWAVES; ++i) { a = fminf(a, sh.red[2 * i]); b = fmaxf(b, sh.red[2 * i + 1]); c |= sh.redb[i]; }
-    my[0].mn = a; my[0].mx = b; my[0].bad = c;
+    put(&my[0].mn, a);
+    put(&my[0].mx, b);
+    put(&my[0].bad, c);
   }
   bool ok = seg_barrier(sy, G, ++bar, sh);
   lo = INFINITY; hi = -INFINITY; bad = 0;
   for (int q = 0; q < G; ++q) {
-    lo = fminf(lo, all[2 * q].mn);
-    hi = fmaxf(hi, all[2 * q].mx);
-    bad |= all[2 * q].bad;
+    lo = fminf(lo, get(&all[2 * q].mn));
+    hi = fmaxf(hi, get(&all[2 * q].mx));
+    bad |= get(&all[2 * q].bad);
   }
   if (!ok || bad || hi == lo) {
     // constant slice: one cluster at lo; non-finite input or lost barrier: flagged
@@ -241,23 +254,23 @@ __global__ __launch_bounds__(KT) void k_kmeans_grid(const KMJob* jobs, KMJob sin
       long long q = 0;
       unsigned c = 0;
       for (int ww = 0; ww < KWAVES; ++ww) { q += (long long)sh.sum[ww][j]; c += sh.cnt[ww][j]; }
-      slot->sum[j] = q;
-      slot->cnt[j] = c;
+      put(&slot->sum[j], q);
+      put(&slot->cnt[j], c);
     }
-    if (tid == 0) { slot->changed = sh.flag; sh.flag = 0; }
+    if (tid == 0) { put(&slot->changed, sh.flag); sh.flag = 0; }
     ok = seg_barrier(sy, G, ++bar, sh);
     if (!ok) break;
     // did any slice change its labels in the previous reassignment?
     int any = 0;
-    for (int q = 0; q < G; ++q) any |= all[2 * q + (t & 1)].changed;
+    for (int q = 0; q < G; ++q) any |= get(&all[2 * q + (t & 1)].changed);
     if (t > 1 && !any) break;          // labels of iteration t-1 are final
     it = t;
     if (tid < k) {
       long long q = 0;
       unsigned long long c = 0;
       for (int gg = 0; gg < G; ++gg) {
-        q += all[2 * gg + (t & 1)].sum[tid];
-        c += all[2 * gg + (t & 1)].cnt[tid];
+        q += get(&all[2 * gg + (t & 1)].sum[tid]);
+        c += get(&all[2 * gg + (t & 1)].cnt[tid]);
       }
       if (c > 0) sh.cent[tid] = (float)(ldexp((double)q, -S) / (double)c);
     }

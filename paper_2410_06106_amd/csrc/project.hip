@@ -247,19 +247,22 @@ __global__ __launch_bounds__(PTHREADS) void k_project(Src src) {
   }
 }
 
-// Sum of the regions' partial ray sums of one angle chunk (one workgroup per
-// chunk of a job with more than one region): out = scale * sum - d.
+// Sum of the regions' partial ray sums, one thread per (angle chunk, bin):
+// out = scale * sum_regions partial - d, regions added in region order.  A job
+// spans n_achunk * ceil(nb / PTHREADS) workgroups of this launch.
 template <class Src>
 __global__ __launch_bounds__(PTHREADS) void k_project_reduce(Src src) {
   __shared__ int fin_bbase[PMAXREG * PA];
-  int achunk;
-  const ProjJob J = src.get(blockIdx.x, achunk);
+  int lid;
+  const ProjJob J = src.get(blockIdx.x, lid);
   const int G = J.n_rr * J.n_rc;
+  const int nbb = (J.nb + PTHREADS - 1) / PTHREADS;
+  const int achunk = lid / nbb;
+  const int b = (lid - achunk * nbb) * PTHREADS + threadIdx.x;
   const int a0 = achunk * PA;
   const int na = min(PA, J.n_ang - a0);
-  const int tid = threadIdx.x;
   const double h = 0.5 * (J.n - 1), hb = 0.5 * (J.nb - 1);
-  for (int i = tid; i < G * PA; i += PTHREADS) {
+  for (int i = threadIdx.x; i < G * PA; i += PTHREADS) {
     int g = i / PA, a = i - g * PA;
     int bb = 0;
     if (a < na) {
@@ -271,17 +274,23 @@ __global__ __launch_bounds__(PTHREADS) void k_project_reduce(Src src) {
     fin_bbase[i] = bb;
   }
   __syncthreads();
+  if (b >= J.nb) return;
   const float* pbase = J.partial + (size_t)achunk * G * (PA * PACC);
-  for (int idx = tid; idx < na * J.nb; idx += PTHREADS) {
-    int a = idx / J.nb, b = idx - a * J.nb;
-    float s = 0.f;
-    for (int g = 0; g < G; ++g) {
+  float s[PA] = {};
+  for (int g = 0; g < G; ++g) {
+#pragma unroll
+    for (int a = 0; a < PA; ++a) {
       int j = b - fin_bbase[g * PA + a];
-      if (j >= 0 && j < PACC) s += pbase[((size_t)g * PA + a) * PACC + j];
+      if (a < na && j >= 0 && j < PACC) s[a] += pbase[((size_t)g * PA + a) * PACC + j];
     }
-    s *= J.scale;
-    size_t o = (size_t)(a0 + a) * J.nb + b;
-    J.out[o] = J.d ? s - J.d[o] : s;
+  }
+#pragma unroll
+  for (int a = 0; a < PA; ++a) {
+    if (a < na) {
+      size_t o = (size_t)(a0 + a) * J.nb + b;
+      float v = s[a] * J.scale;
+      J.out[o] = J.d ? v - J.d[o] : v;
+    }
   }
 }
 
