@@ -59,6 +59,23 @@ const char* tomo_status_string(int status);
 /* Text of the latest error recorded on `ctx` ("" if none). */
 const char* tomo_last_error(const tomo_ctx* ctx);
 
+/*
+ * Launch-shape options of a context (the tile choices an autotuner varies).
+ * Values take effect for plans built afterwards: setting an option retires the
+ * context's cached plans (their memory stays allocated until tomo_destroy, so
+ * graphs captured earlier remain valid).  Results do not depend on the options except for
+ * floating-point summation order in the projector (regions are added in a
+ * fixed order, so a given option value is bit-reproducible).
+ *   TOMO_OPT_PROJ_JOB_WGS   projector workgroups wanted per node before its
+ *                           image is split into smaller regions (default 64,
+ *                           1 .. 65536)
+ *   TOMO_OPT_KMEANS_GROUPS  workgroups per K-means segment (0 = automatic,
+ *                           else 1 .. 256; more than the device can keep
+ *                           resident for all segments at once is clamped)
+ */
+enum { TOMO_OPT_PROJ_JOB_WGS = 1, TOMO_OPT_KMEANS_GROUPS = 2 };
+int tomo_set_option(tomo_ctx* ctx, int32_t option, int64_t value);
+
 typedef struct {
   int32_t n;       /* image side: the image is n x n pixels (1 <= n <= 4096) */
   int32_t n_bins;  /* detector bins per angle (n_bins >= 1)                  */

@@ -29,7 +29,6 @@ static_assert(sizeof(tomo_msg) == 40, "tomo_msg must have no padding");
 
 namespace {
 
-constexpr int kJobWGs = 64;      // projector workgroups wanted per job
 constexpr int kMaxRegions = PMAXREG;  // regions per projector job (finalizer table size)
 
 struct DevBuf {
@@ -69,9 +68,9 @@ ProjShape base_shape(int n, int n_ang) {
 // node gives bit-identical results whether it is launched alone or batched.
 // Region sides stay multiples of 16 so that rows of a region start on
 // 16-byte boundaries whenever the image side is a multiple of 4.
-void split_for_parallelism(ProjShape& s, int n) {
+void split_for_parallelism(ProjShape& s, int n, int job_wgs) {
   auto half = [](int r) { return ((r / 2) + 15) & ~15; };
-  while (s.wgs() < kJobWGs) {
+  while (s.wgs() < job_wgs) {
     ProjShape c = s;
     if (c.reg_h >= c.reg_w && c.reg_h >= 128) {
       c.reg_h = half(c.reg_h); c.n_rr = (n + c.reg_h - 1) / c.reg_h;
@@ -110,9 +109,10 @@ constexpr int kKmRegElems = 256 * 16;   // values a K-means workgroup keeps in r
 
 // Workgroups per K-means segment: spread segments over the CUs (all of a
 // segment's workgroups must be resident together) with >= 1024 values each.
-int kmeans_groups(int n_cu, int n_seg, long long max_n) {
+int kmeans_groups(int n_cu, int n_seg, long long max_n, int forced) {
+  long long fit = std::max(1, n_cu / std::max(1, n_seg));
+  if (forced > 0) return (int)std::min<long long>(forced, fit);
   long long want = (max_n + 1023) / 1024;
-  long long fit = n_cu / std::max(1, n_seg);
   return (int)std::max(1ll, std::min(want, fit));
 }
 
@@ -125,11 +125,17 @@ bool same_nodes(const std::vector<tomo_node>& k, const tomo_node* nodes, int n) 
 struct tomo_ctx {
   int device = 0;
   int n_cu = 1;
+  int proj_job_wgs = 64;      // TOMO_OPT_PROJ_JOB_WGS
+  int kmeans_groups = 0;      // TOMO_OPT_KMEANS_GROUPS (0 = automatic)
   std::string err;
   DevBuf partial;                                // standalone projector workspace
   DevBuf km_slots, km_sync;                      // standalone K-means workspace
   std::vector<std::unique_ptr<LocalPlan>> lplans;
   std::vector<std::unique_ptr<ConsPlan>> cplans;
+  // plans dropped by tomo_set_option stay allocated (a captured graph may
+  // still reference their buffers) until the context is destroyed
+  std::vector<std::unique_ptr<LocalPlan>> retired_l;
+  std::vector<std::unique_ptr<ConsPlan>> retired_c;
   int fail(int code, const std::string& msg) { err = msg; return code; }
 };
 
@@ -215,7 +221,7 @@ LocalPlan* get_local_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, in
   size_t resid_elems = 0, part_elems = 0;
   for (int i = 0; i < n_nodes; ++i) {
     shapes.push_back(base_shape(nodes[i].g.n, nodes[i].n_ang));
-    split_for_parallelism(shapes.back(), nodes[i].g.n);
+    split_for_parallelism(shapes.back(), nodes[i].g.n, ctx->proj_job_wgs);
   }
   std::vector<size_t> roff(n_nodes), poff(n_nodes);
   for (int i = 0; i < n_nodes; ++i) {
@@ -333,7 +339,7 @@ ConsPlan* get_cons_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, cons
     avg.back().n_nodes++;
   }
   plan->label_stride = (max_seg + 255) / 256 * 256;
-  plan->km_G = kmeans_groups(ctx->n_cu, n_nodes, max_seg);
+  plan->km_G = kmeans_groups(ctx->n_cu, n_nodes, max_seg, ctx->kmeans_groups);
   plan->km_reg = (max_seg + plan->km_G - 1) / plan->km_G <= kKmRegElems;
   std::vector<KMJob> km;
   for (int i = 0; i < n_nodes; ++i) {
@@ -423,6 +429,27 @@ int tomo_destroy(tomo_ctx* ctx) {
   return TOMO_OK;
 }
 
+int tomo_set_option(tomo_ctx* ctx, int32_t option, int64_t value) {
+  if (!ctx) return TOMO_EINVAL;
+  switch (option) {
+    case TOMO_OPT_PROJ_JOB_WGS:
+      if (value < 1 || value > 65536) return ctx->fail(TOMO_EINVAL, "projector workgroups per job out of range");
+      ctx->proj_job_wgs = (int)value;
+      break;
+    case TOMO_OPT_KMEANS_GROUPS:
+      if (value < 0 || value > 256) return ctx->fail(TOMO_EINVAL, "K-means groups out of range");
+      ctx->kmeans_groups = (int)value;
+      break;
+    default:
+      return ctx->fail(TOMO_EINVAL, "unknown option");
+  }
+  for (auto& p : ctx->lplans) ctx->retired_l.push_back(std::move(p));
+  for (auto& p : ctx->cplans) ctx->retired_c.push_back(std::move(p));
+  ctx->lplans.clear();
+  ctx->cplans.clear();
+  return TOMO_OK;
+}
+
 int tomo_project(tomo_ctx* ctx, tomo_geom g, const double* angles, int32_t n_ang, const float* image,
                  float* sino, void* stream) {
   if (!ctx) return TOMO_EINVAL;
@@ -434,7 +461,7 @@ int tomo_project(tomo_ctx* ctx, tomo_geom g, const double* angles, int32_t n_ang
     return ctx->fail(TOMO_EINVAL, "image and sino overlap");
   if (int rc = set_device(ctx)) return rc;
   std::vector<ProjShape> sh{base_shape(g.n, n_ang)};
-  split_for_parallelism(sh[0], g.n);
+  split_for_parallelism(sh[0], g.n, ctx->proj_job_wgs);
   ProjJob j = make_proj_job(image, angles, nullptr, sino, g.n, g.n_bins, n_ang, sh[0]);
   if (sh[0].regions() > 1) {
     if (!ctx->partial.ensure((size_t)sh[0].wgs() * PA * PACC * 4)) return ctx->fail(TOMO_ENOMEM, "workspace");
@@ -566,7 +593,7 @@ int quantize_kmeans(tomo_ctx* ctx, const float* a, int64_t n, int32_t k, int32_t
   if (a_hat && a_hat != a && overlaps(a, (size_t)n * 4, a_hat, (size_t)n * 4))
     return ctx->fail(TOMO_EINVAL, "a_hat partially overlaps a");
   if (int rc = set_device(ctx)) return rc;
-  const int G = kmeans_groups(ctx->n_cu, 1, n);
+  const int G = kmeans_groups(ctx->n_cu, 1, n, ctx->kmeans_groups);
   const bool reg = (n + G - 1) / G <= kKmRegElems;
   if (!ctx->km_slots.ensure((size_t)G * 2 * sizeof(KMSlot))) return ctx->fail(TOMO_ENOMEM, "workspace");
   size_t had = ctx->km_sync.bytes;
