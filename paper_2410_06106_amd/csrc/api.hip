@@ -105,14 +105,17 @@ struct ConsPlan {
   long long label_stride = 0;
 };
 
-constexpr int kKmRegElems = 256 * 16;   // values a K-means workgroup keeps in registers
-
 // Workgroups per K-means segment: spread segments over the CUs (all of a
 // segment's workgroups must be resident together) with >= 1024 values each.
+constexpr int kKmRegElems = 256 * 16;   // values a K-means workgroup keeps in registers
+
+// Automatic choice: the fewest workgroups whose slices fit in registers (one
+// workgroup, no barrier, when the segment fits), at most 16 and never more than
+// the CUs can hold for all segments at once.
 int kmeans_groups(int n_cu, int n_seg, long long max_n, int forced) {
-  long long fit = std::max(1, n_cu / std::max(1, n_seg));
+  long long fit = std::max(1, std::min(16, n_cu / std::max(1, n_seg)));
   if (forced > 0) return (int)std::min<long long>(forced, fit);
-  long long want = (max_n + 1023) / 1024;
+  long long want = (max_n + kKmRegElems - 1) / kKmRegElems;
   return (int)std::max(1ll, std::min(want, fit));
 }
 

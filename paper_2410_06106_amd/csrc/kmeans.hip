@@ -51,12 +51,18 @@ __device__ __forceinline__ float km_xupdate(float xv, float uv, float lv, float 
   return xv;
 }
 
+constexpr int KMAXG = 16;               // workgroups per segment at most
+
 struct KMLocal {
-  unsigned long long sum[KWAVES][KM_MAX_K];
+  unsigned long long sum[KWAVES][KM_MAX_K];   // per-wave cluster sums of this workgroup
   unsigned cnt[KWAVES][KM_MAX_K];
+  long long gsum[KMAXG][KM_MAX_K];            // every workgroup's published sums of the segment
+  unsigned gcnt[KMAXG][KM_MAX_K];
   float cent[KM_MAX_K];
   float red[2 * KWAVES];
   int redb[KWAVES];
+  float gmn[KMAXG], gmx[KMAXG];
+  int gflag[KMAXG];
   int flag;
   int ok;
 };
@@ -114,6 +120,13 @@ __device__ void seg_leave(KMSync* sy, int G) {
 
 }  // namespace
 
+// Global-address-space views of a job's arrays (plain global loads and stores
+// instead of flat accesses).
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gptr(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
 template <bool REG>
 __global__ __launch_bounds__(KT) void k_kmeans_grid(const KMJob* jobs, KMJob single, int G, int k, int max_iter,
                                                     int e2, KMSlot* slots, KMSync* syncs) {
@@ -121,8 +134,8 @@ __global__ __launch_bounds__(KT) void k_kmeans_grid(const KMJob* jobs, KMJob sin
   __shared__ KMLocal sh;
   const int seg = blockIdx.x / G, g = blockIdx.x - seg * G;
   const KMJob J = jobs ? jobs[seg] : single;
-  if (threadIdx.x == 0) sh.flag = 0;
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  if (tid == 0) sh.flag = 0;
   const long long chunk = (J.n + G - 1) / G;
   const long long i0 = min(J.n, (long long)g * chunk), i1 = min(J.n, i0 + chunk);
   KMSync* sy = syncs + seg;
@@ -131,6 +144,12 @@ __global__ __launch_bounds__(KT) void k_kmeans_grid(const KMJob* jobs, KMJob sin
   unsigned bar = 0;
   const bool do_x = J.u != nullptr;
   const float irho = 1.f / J.rho;
+  const auto src = gptr(J.src);
+  const auto xo = gptr(J.x);
+  const auto ahat = gptr(J.a_hat);
+  const auto uu = gptr(J.u);
+  const auto ll = gptr(J.lam);
+  const auto labels = gptr(J.labels);
 
   // values of this workgroup's slice (after the optional x-update)
   float v[REG ? KVPT : 1];
@@ -142,10 +161,10 @@ __global__ __launch_bounds__(KT) void k_kmeans_grid(const KMJob* jobs, KMJob sin
       long long i = i0 + tid + (long long)e * KT;
       float a = 0.f;
       if (i < i1) {
-        a = J.src[i];
+        a = src[i];
         if (do_x) {
-          a = km_xupdate(a, J.u[i], J.lam[i], J.rho, irho, J.eta2, e2);
-          J.x[i] = a;
+          a = km_xupdate(a, uu[i], ll[i], J.rho, irho, J.eta2, e2);
+          xo[i] = a;
         }
         bad |= !isfinite(a);
         lo = fminf(lo, a);
@@ -155,10 +174,10 @@ __global__ __launch_bounds__(KT) void k_kmeans_grid(const KMJob* jobs, KMJob sin
     }
   } else {
     for (long long i = i0 + tid; i < i1; i += KT) {
-      float a = J.src[i];
+      float a = src[i];
       if (do_x) {
-        a = km_xupdate(a, J.u[i], J.lam[i], J.rho, irho, J.eta2, e2);
-        J.x[i] = a;
+        a = km_xupdate(a, uu[i], ll[i], J.rho, irho, J.eta2, e2);
+        xo[i] = a;
       }
       bad |= !isfinite(a);
       lo = fminf(lo, a);
@@ -176,23 +195,33 @@ __global__ __launch_bounds__(KT) void k_kmeans_grid(const KMJob* jobs, KMJob sin
     float a = sh.red[0], b = sh.red[1];
     int c = sh.redb[0];
     for (int i = 1; i < KWAVES; ++i) { a = fminf(a, sh.red[2 * i]); b = fmaxf(b, sh.red[2 * i + 1]); c |= sh.redb[i]; }
-    put(&my[0].mn, a);
-    put(&my[0].mx, b);
-    put(&my[0].bad, c);
+    if (G == 1) {
+      sh.gmn[0] = a; sh.gmx[0] = b; sh.gflag[0] = c;
+    } else {
+      put(&my[0].mn, a);
+      put(&my[0].mx, b);
+      put(&my[0].bad, c);
+    }
   }
   bool ok = seg_barrier(sy, G, ++bar, sh);
+  if (G > 1 && tid < G) {          // every workgroup's range, loaded in parallel
+    sh.gmn[tid] = get(&all[2 * tid].mn);
+    sh.gmx[tid] = get(&all[2 * tid].mx);
+    sh.gflag[tid] = get(&all[2 * tid].bad);
+  }
+  __syncthreads();
   lo = INFINITY; hi = -INFINITY; bad = 0;
   for (int q = 0; q < G; ++q) {
-    lo = fminf(lo, get(&all[2 * q].mn));
-    hi = fmaxf(hi, get(&all[2 * q].mx));
-    bad |= get(&all[2 * q].bad);
+    lo = fminf(lo, sh.gmn[q]);
+    hi = fmaxf(hi, sh.gmx[q]);
+    bad |= sh.gflag[q];
   }
   if (!ok || bad || hi == lo) {
     // constant slice: one cluster at lo; non-finite input or lost barrier: flagged
     const int code = !ok ? -2 : (bad ? -1 : 0);
     for (long long i = i0 + tid; i < i1; i += KT) {
-      if (J.labels) J.labels[i] = 0;
-      if (J.a_hat && J.a_hat != J.src) J.a_hat[i] = J.src[i];
+      if (J.labels) labels[i] = 0;
+      if (J.a_hat && J.a_hat != J.src) ahat[i] = src[i];
     }
     if (g == 0) {
       if (J.cent) for (int j = tid; j < k; j += KT) J.cent[j] = code == 0 ? lo : 0.f;
@@ -219,11 +248,15 @@ __global__ __launch_bounds__(KT) void k_kmeans_grid(const KMJob* jobs, KMJob sin
   __syncthreads();
 
   uint8_t lab[REG ? KVPT : 1];
+  long long qv[REG ? KVPT : 1];
   if (REG) {
 #pragma unroll
-    for (int e2i = 0; e2i < KVPT; ++e2i) lab[e2i] = (uint8_t)km_assign(v[e2i], sh.cent, k);
+    for (int q = 0; q < KVPT; ++q) {
+      lab[q] = (uint8_t)km_assign(v[q], sh.cent, k);
+      qv[q] = km_fixed(v[q], S);
+    }
   } else {
-    for (long long i = i0 + tid; i < i1; i += KT) J.labels[i] = (uint8_t)km_assign(J.src[i], sh.cent, k);
+    for (long long i = i0 + tid; i < i1; i += KT) labels[i] = (uint8_t)km_assign(src[i], sh.cent, k);
   }
 
   int changed = 1, it = 0;
@@ -236,42 +269,59 @@ __global__ __launch_bounds__(KT) void k_kmeans_grid(const KMJob* jobs, KMJob sin
       for (int q = 0; q < KVPT; ++q) {
         long long i = i0 + tid + (long long)q * KT;
         if (i < i1) {
-          atomicAdd(&sh.sum[w][lab[q]], (unsigned long long)km_fixed(v[q], S));
+          atomicAdd(&sh.sum[w][lab[q]], (unsigned long long)qv[q]);
           atomicAdd(&sh.cnt[w][lab[q]], 1u);
         }
       }
     } else {
       for (long long i = i0 + tid; i < i1; i += KT) {
-        int lb = J.labels[i];
-        atomicAdd(&sh.sum[w][lb], (unsigned long long)km_fixed(J.src[i], S));
+        int lb = labels[i];
+        atomicAdd(&sh.sum[w][lb], (unsigned long long)km_fixed(src[i], S));
         atomicAdd(&sh.cnt[w][lb], 1u);
       }
     }
-    if (changed) sh.flag = 1;   // published with this iteration's sums
+    if (changed) sh.flag = 1;
     __syncthreads();
+    // this workgroup's totals: into the shared table directly (G == 1) or
+    // published for the other workgroups of the segment
     KMSlot* slot = my + (t & 1);
     for (int j = tid; j < k; j += KT) {
       long long q = 0;
       unsigned c = 0;
       for (int ww = 0; ww < KWAVES; ++ww) { q += (long long)sh.sum[ww][j]; c += sh.cnt[ww][j]; }
-      put(&slot->sum[j], q);
-      put(&slot->cnt[j], c);
+      if (G == 1) {
+        sh.gsum[0][j] = q;
+        sh.gcnt[0][j] = c;
+      } else {
+        put(&slot->sum[j], q);
+        put(&slot->cnt[j], c);
+      }
     }
-    if (tid == 0) { put(&slot->changed, sh.flag); sh.flag = 0; }
+    if (tid == 0) {
+      if (G == 1) sh.gflag[0] = sh.flag;
+      else put(&slot->changed, sh.flag);
+      sh.flag = 0;
+    }
     ok = seg_barrier(sy, G, ++bar, sh);
     if (!ok) break;
+    if (G > 1) {                      // all published totals, loaded in parallel
+      for (int idx = tid; idx < G * k; idx += KT) {
+        int gg = idx / k, j = idx - gg * k;
+        sh.gsum[gg][j] = get(&all[2 * gg + (t & 1)].sum[j]);
+        sh.gcnt[gg][j] = get(&all[2 * gg + (t & 1)].cnt[j]);
+      }
+      if (tid < G) sh.gflag[tid] = get(&all[2 * tid + (t & 1)].changed);
+    }
+    __syncthreads();
     // did any slice change its labels in the previous reassignment?
     int any = 0;
-    for (int q = 0; q < G; ++q) any |= get(&all[2 * q + (t & 1)].changed);
+    for (int q = 0; q < G; ++q) any |= sh.gflag[q];
     if (t > 1 && !any) break;          // labels of iteration t-1 are final
     it = t;
     if (tid < k) {
       long long q = 0;
       unsigned long long c = 0;
-      for (int gg = 0; gg < G; ++gg) {
-        q += get(&all[2 * gg + (t & 1)].sum[tid]);
-        c += get(&all[2 * gg + (t & 1)].cnt[tid]);
-      }
+      for (int gg = 0; gg < G; ++gg) { q += sh.gsum[gg][tid]; c += sh.gcnt[gg][tid]; }
       if (c > 0) sh.cent[tid] = (float)(ldexp((double)q, -S) / (double)c);
     }
     __syncthreads();
@@ -286,8 +336,8 @@ __global__ __launch_bounds__(KT) void k_kmeans_grid(const KMJob* jobs, KMJob sin
       }
     } else {
       for (long long i = i0 + tid; i < i1; i += KT) {
-        int nl = km_assign(J.src[i], sh.cent, k);
-        if (nl != J.labels[i]) { changed = 1; J.labels[i] = (uint8_t)nl; }
+        int nl = km_assign(src[i], sh.cent, k);
+        if (nl != labels[i]) { changed = 1; labels[i] = (uint8_t)nl; }
       }
     }
     __syncthreads();
@@ -302,12 +352,12 @@ __global__ __launch_bounds__(KT) void k_kmeans_grid(const KMJob* jobs, KMJob sin
     for (int q = 0; q < KVPT; ++q) {
       long long i = i0 + tid + (long long)q * KT;
       if (i < i1) {
-        if (J.labels) J.labels[i] = lab[q];
-        if (J.a_hat) J.a_hat[i] = sh.cent[lab[q]];
+        if (J.labels) labels[i] = lab[q];
+        if (J.a_hat) ahat[i] = sh.cent[lab[q]];
       }
     }
   } else if (J.a_hat) {
-    for (long long i = i0 + tid; i < i1; i += KT) J.a_hat[i] = sh.cent[J.labels[i]];
+    for (long long i = i0 + tid; i < i1; i += KT) ahat[i] = sh.cent[labels[i]];
   }
   if (g == 0) {
     if (J.cent) for (int j = tid; j < k; j += KT) J.cent[j] = sh.cent[j];
