@@ -107,11 +107,12 @@ struct ConsPlan {
 
 // Workgroups per K-means segment: spread segments over the CUs (all of a
 // segment's workgroups must be resident together) with >= 1024 values each.
-constexpr int kKmRegElems = 256 * 16;   // values a K-means workgroup keeps in registers
+constexpr int kKmRegElems = 1024 * 16;  // values a K-means workgroup keeps in registers
+constexpr int kKmThreads = 1024;
 
-// Automatic choice: the fewest workgroups whose slices fit in registers (one
-// workgroup, no barrier, when the segment fits), at most 16 and never more than
-// the CUs can hold for all segments at once.
+// Automatic choice: one workgroup per segment (no barrier) unless the segment
+// is larger than a workgroup's registers hold, then the fewest that fit, at
+// most 16 and never more than the CUs can hold for all segments at once.
 int kmeans_groups(int n_cu, int n_seg, long long max_n, int forced) {
   long long fit = std::max(1, std::min(16, n_cu / std::max(1, n_seg)));
   if (forced > 0) return (int)std::min<long long>(forced, fit);
@@ -572,10 +573,10 @@ int admm_consensus(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, int32
     const int ex = do_x ? e2 : 0;
     dim3 grid(plan->n_seg * plan->km_G);
     if (plan->km_reg)
-      hipLaunchKernelGGL(k_kmeans_grid<true>, grid, dim3(256), 0, s, kj, KMJob{}, plan->km_G, q->levels,
+      hipLaunchKernelGGL(k_kmeans_grid<true>, grid, dim3(kKmThreads), 0, s, kj, KMJob{}, plan->km_G, q->levels,
                          q->max_iter, ex, sl, sy);
     else
-      hipLaunchKernelGGL(k_kmeans_grid<false>, grid, dim3(256), 0, s, kj, KMJob{}, plan->km_G, q->levels,
+      hipLaunchKernelGGL(k_kmeans_grid<false>, grid, dim3(kKmThreads), 0, s, kj, KMJob{}, plan->km_G, q->levels,
                          q->max_iter, ex, sl, sy);
   } else if (kind == TOMO_QUANT_DCT) {
     hipLaunchKernelGGL(k_seg_dct, dim3(plan->n_seg), dim3(256), 0, s, seg, do_x, e2, q->quality);
@@ -614,10 +615,10 @@ int quantize_kmeans(tomo_ctx* ctx, const float* a, int64_t n, int32_t k, int32_t
   KMSlot* sl = static_cast<KMSlot*>(ctx->km_slots.p);
   KMSync* sy = static_cast<KMSync*>(ctx->km_sync.p);
   if (reg)
-    hipLaunchKernelGGL(k_kmeans_grid<true>, dim3(G), dim3(256), 0, (hipStream_t)stream, nullptr, j, G, k,
+    hipLaunchKernelGGL(k_kmeans_grid<true>, dim3(G), dim3(kKmThreads), 0, (hipStream_t)stream, nullptr, j, G, k,
                        max_iter, 0, sl, sy);
   else
-    hipLaunchKernelGGL(k_kmeans_grid<false>, dim3(G), dim3(256), 0, (hipStream_t)stream, nullptr, j, G, k,
+    hipLaunchKernelGGL(k_kmeans_grid<false>, dim3(G), dim3(kKmThreads), 0, (hipStream_t)stream, nullptr, j, G, k,
                        max_iter, 0, sl, sy);
   return launch_status(ctx, "quantize_kmeans");
 }

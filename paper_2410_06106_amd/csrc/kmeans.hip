@@ -23,9 +23,10 @@ namespace tomo {
 
 namespace {
 
-constexpr int KT = 256;                 // threads per workgroup
+constexpr int KT = 1024;                // threads per workgroup
 constexpr int KWAVES = KT / 64;
 constexpr int KVPT = 16;                // values per thread kept in registers
+constexpr int KCOPY = 4;                // replicas of each cluster bin (fewer LDS atomic conflicts)
 constexpr unsigned kSpinLimit = 1u << 20;
 
 __device__ __forceinline__ int km_assign(float v, const float* cent, int k) {
@@ -36,6 +37,28 @@ __device__ __forceinline__ int km_assign(float v, const float* cent, int k) {
     if (d < best) { best = d; bj = j; }
   }
   return bj;
+}
+
+// Same result as km_assign when the centres are sorted (non-decreasing): with
+// p the first centre >= v, |v - c_j| (float32) does not increase for j < p and
+// does not decrease for j >= p, so the minimum is at p - 1 or p; ties go to the
+// lowest index, found by walking left over equal distances.
+__device__ __forceinline__ int km_assign_sorted(float v, const float* cent, int k, int steps) {
+  int lo = 0, len = k;              // p in [lo, lo + len]
+  for (int s = 0; s < steps; ++s) {
+    int half = len >> 1;
+    int mid = lo + half;
+    bool right = half > 0 && mid < k && cent[mid] < v;
+    lo = right ? mid + 1 : lo;
+    len = right ? len - half - 1 : half;
+  }
+  int p = lo + ((len > 0 && lo < k && cent[lo] < v) ? 1 : 0);
+  if (p == 0) return 0;
+  const float dl = fabsf(v - cent[p - 1]);
+  if (p < k && fabsf(v - cent[p]) < dl) return p;
+  int j = p - 1;
+  while (j > 0 && fabsf(v - cent[j - 1]) == dl) --j;
+  return j;
 }
 
 __device__ __forceinline__ long long km_fixed(float v, int S) {
@@ -54,7 +77,7 @@ __device__ __forceinline__ float km_xupdate(float xv, float uv, float lv, float 
 constexpr int KMAXG = 16;               // workgroups per segment at most
 
 struct KMLocal {
-  unsigned long long sum[KWAVES][KM_MAX_K];   // per-wave cluster sums of this workgroup
+  unsigned long long sum[KWAVES][KM_MAX_K];   // per-wave cluster sums (KCOPY replicas when k <= 64)
   unsigned cnt[KWAVES][KM_MAX_K];
   long long gsum[KMAXG][KM_MAX_K];            // every workgroup's published sums of the segment
   unsigned gcnt[KMAXG][KM_MAX_K];
@@ -65,6 +88,7 @@ struct KMLocal {
   int gflag[KMAXG];
   int flag;
   int ok;
+  int sorted;
 };
 
 // Monotonic per-segment barrier: the b-th barrier of a launch completes when
@@ -247,37 +271,51 @@ __global__ __launch_bounds__(KT) void k_kmeans_grid(const KMJob* jobs, KMJob sin
   }
   __syncthreads();
 
+  // centre order decides which (equivalent) assignment routine is used
+  int steps = 0;
+  while ((1 << steps) <= k) ++steps;
+  auto assign = [&](float val) -> int {
+    return (k > 8 && sh.sorted) ? km_assign_sorted(val, sh.cent, k, steps) : km_assign(val, sh.cent, k);
+  };
+  if (tid == 0) {
+    int srt = 1;
+    for (int j = 1; j < k; ++j) srt &= !(sh.cent[j] < sh.cent[j - 1]);
+    sh.sorted = srt;
+  }
+  __syncthreads();
+
   uint8_t lab[REG ? KVPT : 1];
-  long long qv[REG ? KVPT : 1];
   if (REG) {
 #pragma unroll
     for (int q = 0; q < KVPT; ++q) {
-      lab[q] = (uint8_t)km_assign(v[q], sh.cent, k);
-      qv[q] = km_fixed(v[q], S);
+      lab[q] = (uint8_t)assign(v[q]);
     }
   } else {
-    for (long long i = i0 + tid; i < i1; i += KT) labels[i] = (uint8_t)km_assign(src[i], sh.cent, k);
+    for (long long i = i0 + tid; i < i1; i += KT) labels[i] = (uint8_t)assign(src[i]);
   }
 
+  const int ncopy = k * KCOPY <= KM_MAX_K ? KCOPY : 1;
+  const int nbins = k * ncopy;
   int changed = 1, it = 0;
   for (int t = 1; t <= max_iter; ++t) {
-    // cluster sums of the current labels
-    for (int j = l; j < k; j += 64) { sh.sum[w][j] = 0ull; sh.cnt[w][j] = 0u; }
+    // cluster sums of the current labels (exact integer sums: any order)
+    for (int j = l; j < nbins; j += 64) { sh.sum[w][j] = 0ull; sh.cnt[w][j] = 0u; }
     __syncthreads();
     if (REG) {
 #pragma unroll
       for (int q = 0; q < KVPT; ++q) {
         long long i = i0 + tid + (long long)q * KT;
         if (i < i1) {
-          atomicAdd(&sh.sum[w][lab[q]], (unsigned long long)qv[q]);
-          atomicAdd(&sh.cnt[w][lab[q]], 1u);
+          int bin = lab[q] * ncopy + (l & (ncopy - 1));
+          atomicAdd(&sh.sum[w][bin], (unsigned long long)km_fixed(v[q], S));
+          atomicAdd(&sh.cnt[w][bin], 1u);
         }
       }
     } else {
       for (long long i = i0 + tid; i < i1; i += KT) {
-        int lb = labels[i];
-        atomicAdd(&sh.sum[w][lb], (unsigned long long)km_fixed(src[i], S));
-        atomicAdd(&sh.cnt[w][lb], 1u);
+        int bin = labels[i] * ncopy + (l & (ncopy - 1));
+        atomicAdd(&sh.sum[w][bin], (unsigned long long)km_fixed(src[i], S));
+        atomicAdd(&sh.cnt[w][bin], 1u);
       }
     }
     if (changed) sh.flag = 1;
@@ -288,7 +326,8 @@ __global__ __launch_bounds__(KT) void k_kmeans_grid(const KMJob* jobs, KMJob sin
     for (int j = tid; j < k; j += KT) {
       long long q = 0;
       unsigned c = 0;
-      for (int ww = 0; ww < KWAVES; ++ww) { q += (long long)sh.sum[ww][j]; c += sh.cnt[ww][j]; }
+      for (int ww = 0; ww < KWAVES; ++ww)
+        for (int r = 0; r < ncopy; ++r) { q += (long long)sh.sum[ww][j * ncopy + r]; c += sh.cnt[ww][j * ncopy + r]; }
       if (G == 1) {
         sh.gsum[0][j] = q;
         sh.gcnt[0][j] = c;
@@ -325,18 +364,24 @@ __global__ __launch_bounds__(KT) void k_kmeans_grid(const KMJob* jobs, KMJob sin
       if (c > 0) sh.cent[tid] = (float)(ldexp((double)q, -S) / (double)c);
     }
     __syncthreads();
+    if (tid == 0) {
+      int srt = 1;
+      for (int j = 1; j < k; ++j) srt &= !(sh.cent[j] < sh.cent[j - 1]);
+      sh.sorted = srt;
+    }
+    __syncthreads();
     changed = 0;
     if (REG) {
 #pragma unroll
       for (int q = 0; q < KVPT; ++q) {
         long long i = i0 + tid + (long long)q * KT;
-        int nl = km_assign(v[q], sh.cent, k);
+        int nl = assign(v[q]);
         if (i < i1 && nl != lab[q]) changed = 1;
         lab[q] = (uint8_t)nl;
       }
     } else {
       for (long long i = i0 + tid; i < i1; i += KT) {
-        int nl = km_assign(src[i], sh.cent, k);
+        int nl = assign(src[i]);
         if (nl != labels[i]) { changed = 1; labels[i] = (uint8_t)nl; }
       }
     }
