@@ -44,15 +44,15 @@ __device__ __forceinline__ int km_assign(float v, const float* cent, int k) {
 // does not decrease for j >= p, so the minimum is at p - 1 or p; ties go to the
 // lowest index, found by walking left over equal distances.
 __device__ __forceinline__ int km_assign_sorted(float v, const float* cent, int k, int steps) {
-  int lo = 0, len = k;              // p in [lo, lo + len]
-  for (int s = 0; s < steps; ++s) {
-    int half = len >> 1;
-    int mid = lo + half;
-    bool right = half > 0 && mid < k && cent[mid] < v;
+  int lo = 0, len = k;              // lower bound: p in [lo, lo + len]
+  for (int s = 0; s < steps; ++s) {  // 2^steps > k, so len reaches 0
+    int step = len >> 1;
+    int mid = lo + step;             // < lo + len <= k whenever len > 0
+    bool right = len > 0 && cent[mid] < v;
     lo = right ? mid + 1 : lo;
-    len = right ? len - half - 1 : half;
+    len = right ? len - step - 1 : step;
   }
-  int p = lo + ((len > 0 && lo < k && cent[lo] < v) ? 1 : 0);
+  const int p = lo;
   if (p == 0) return 0;
   const float dl = fabsf(v - cent[p - 1]);
   if (p < k && fabsf(v - cent[p]) < dl) return p;
