@@ -181,8 +181,8 @@ int admm_consensus(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, int32
  *  lo,hi = min,max (NaN/Inf -> TOMO_EINVAL is NOT detectable on the host: the
  *  kernel then writes iters = -1 and leaves the outputs unspecified);
  *  centres start at lo + (hi-lo)(2j+1)/(2k) (float64, no FMA, rounded to float32);
- *  values enter the centroid sums as int64 fixed point round(a * 2^S),
- *  S = 40 - e (n <= 2^22), e the binary exponent of max(|lo|,|hi|);
+ *  values enter the centroid sums as fixed point round(a * 2^S), S = 30 - e,
+ *  e the binary exponent of max(|lo|,|hi|), summed exactly in int64;
  *  label = lowest j minimising |a - c_j| in float32; Lloyd iterations until the
  *  labels repeat or max_iter.  hi == lo: labels 0, centres lo, iters 0.
  * Outputs: labels uint8 [n], centroids float32 [k], a_hat float32 [n] (nullable,

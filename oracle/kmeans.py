@@ -11,9 +11,9 @@ implementation that follows the same steps reaches identical labels:
 2. Initial centres c_j = f32(lo + ((hi - lo) * (2j + 1)) / (2k)) in float64,
    evaluated in that order without fused multiply-add.
 3. Fixed point: e = binary exponent of max(|lo|, |hi|) as returned by frexp
-   (so every |a_i| < 2^e), S = 40 - e when n <= 2^22, else
-   S = 62 - ceil(log2 n) - e; q_i = round-half-even(a_i * 2^S) as an integer.
-   Every cluster sum of q is then exact in int64.
+   (so every |a_i| < 2^e), S = 30 - e; q_i = round-half-even(a_i * 2^S) as an
+   integer, |q_i| <= 2^30.  Every cluster sum of q is then exact in int64 for
+   any n < 2^32.
 4. Assignment: label_i = the lowest j that minimises |a_i - c_j| computed as a
    float32 subtraction and absolute value.
 5. Lloyd iterations t = 1..T_max: c_j <- f32(f64(sum_{label=j} q) * 2^-S / f64(count_j))
@@ -41,9 +41,7 @@ class KMeansResult:
 
 def fixed_point_shift(lo: float, hi: float, n: int) -> int:
     _, e = math.frexp(max(abs(lo), abs(hi)))
-    if n <= (1 << 22):
-        return 40 - e
-    return 62 - math.ceil(math.log2(n)) - e
+    return 30 - e
 
 
 def initial_centres(lo: float, hi: float, k: int) -> np.ndarray:
@@ -71,7 +69,7 @@ def kmeans_quantize(a, k: int, max_iter: int = 30) -> KMeansResult:
     if hi == lo:
         return KMeansResult(np.zeros(n, np.uint8), np.full(k, a32[0], np.float32), a32.copy(), 0, 0)
     S = fixed_point_shift(lo, hi, n)
-    q = np.rint(np.ldexp(a32.astype(np.float64), S)).astype(np.int64)   # |q| < 2^40
+    q = np.rint(np.ldexp(a32.astype(np.float64), S)).astype(np.int64)   # |q| <= 2^30
     c = initial_centres(lo, hi, k)
     labels = assign(a32, c)
     iters = 0

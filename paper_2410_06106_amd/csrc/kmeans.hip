@@ -2,9 +2,10 @@
 //
 // Arithmetic is fixed so that results are bit-exact and independent of the
 // launch shape: centres start at lo + (hi - lo)(2j + 1)/(2k) (float64, no
-// contraction); values enter the centroid sums as int64 fixed point
-// round(a * 2^S) (S = 40 - e for n <= 2^22, else 62 - ceil(log2 n) - e, e the
-// binary exponent of max(|lo|, |hi|)), so every sum is exact in any order;
+// contraction); values enter the centroid sums as fixed point
+// q = round(a * 2^S), S = 30 - e (e the binary exponent of max(|lo|, |hi|), so
+// |q| <= 2^30 fits an int32 and a * 2^S is exact in float32), summed in int64,
+// so every sum is exact in any order;
 // label = lowest j minimising |a - c_j| in float32; a centre becomes
 // f32(f64(sum) * 2^-S / f64(count)); Lloyd iterations stop when no label
 // changes or after max_iter.
@@ -61,8 +62,8 @@ __device__ __forceinline__ int km_assign_sorted(float v, const float* cent, int 
   return j;
 }
 
-__device__ __forceinline__ long long km_fixed(float v, int S) {
-  return (long long)rint(ldexp((double)v, S));
+__device__ __forceinline__ int km_fixed(float v, int S) {
+  return (int)rintf(ldexpf(v, S));     // exact scaling, round half to even
 }
 
 __device__ __forceinline__ float km_xupdate(float xv, float uv, float lv, float rho, float irho, float eta2,
@@ -143,6 +144,37 @@ __device__ void seg_leave(KMSync* sy, int G) {
 
 
 }  // namespace
+
+// Labels of KVPT register-resident values: the centres are read once each
+// (outer loop) and compared with every value; sorted centres with k > 8 use
+// the equivalent binary search.
+template <int NV>
+__device__ __forceinline__ void assign_regs(const float (&v)[NV], uint8_t (&lab)[NV], const float* cent, int k,
+                                            int steps, int sorted) {
+  if (k > 8 && sorted) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) lab[q] = (uint8_t)km_assign_sorted(v[q], cent, k, steps);
+    return;
+  }
+  constexpr int H = NV > 8 ? 8 : NV;   // values per pass (bounds register use)
+#pragma unroll
+  for (int h0 = 0; h0 < NV; h0 += H) {
+    float best[H];
+    const float c0 = cent[0];
+#pragma unroll
+    for (int q = 0; q < H; ++q) { best[q] = fabsf(v[h0 + q] - c0); lab[h0 + q] = 0; }
+    for (int j = 1; j < k; ++j) {
+      const float c = cent[j];
+#pragma unroll
+      for (int q = 0; q < H; ++q) {
+        float d = fabsf(v[h0 + q] - c);
+        bool lt = d < best[q];
+        best[q] = lt ? d : best[q];
+        lab[h0 + q] = lt ? (uint8_t)j : lab[h0 + q];
+      }
+    }
+  }
+}
 
 // Global-address-space views of a job's arrays (plain global loads and stores
 // instead of flat accesses).
@@ -256,13 +288,7 @@ __global__ __launch_bounds__(KT) void k_kmeans_grid(const KMJob* jobs, KMJob sin
   }
   int e;
   frexp(fmax(fabs((double)lo), fabs((double)hi)), &e);
-  int S;
-  if (J.n <= (1ll << 22)) {
-    S = 40 - e;
-  } else {
-    int lg = 64 - __clzll((unsigned long long)(J.n - 1));   // ceil(log2 n)
-    S = 62 - lg - e;
-  }
+  const int S = 30 - e;
   if (tid < k) {
     double lo64 = lo, hi64 = hi;
     double t = (hi64 - lo64) * (double)(2 * tid + 1);
@@ -286,10 +312,7 @@ __global__ __launch_bounds__(KT) void k_kmeans_grid(const KMJob* jobs, KMJob sin
 
   uint8_t lab[REG ? KVPT : 1];
   if (REG) {
-#pragma unroll
-    for (int q = 0; q < KVPT; ++q) {
-      lab[q] = (uint8_t)assign(v[q]);
-    }
+    assign_regs(v, lab, sh.cent, k, steps, sh.sorted);
   } else {
     for (long long i = i0 + tid; i < i1; i += KT) labels[i] = (uint8_t)assign(src[i]);
   }
@@ -307,14 +330,14 @@ __global__ __launch_bounds__(KT) void k_kmeans_grid(const KMJob* jobs, KMJob sin
         long long i = i0 + tid + (long long)q * KT;
         if (i < i1) {
           int bin = lab[q] * ncopy + (l & (ncopy - 1));
-          atomicAdd(&sh.sum[w][bin], (unsigned long long)km_fixed(v[q], S));
+          atomicAdd(&sh.sum[w][bin], (unsigned long long)(long long)km_fixed(v[q], S));
           atomicAdd(&sh.cnt[w][bin], 1u);
         }
       }
     } else {
       for (long long i = i0 + tid; i < i1; i += KT) {
         int bin = labels[i] * ncopy + (l & (ncopy - 1));
-        atomicAdd(&sh.sum[w][bin], (unsigned long long)km_fixed(src[i], S));
+        atomicAdd(&sh.sum[w][bin], (unsigned long long)(long long)km_fixed(src[i], S));
         atomicAdd(&sh.cnt[w][bin], 1u);
       }
     }
@@ -323,11 +346,20 @@ __global__ __launch_bounds__(KT) void k_kmeans_grid(const KMJob* jobs, KMJob sin
     // this workgroup's totals: into the shared table directly (G == 1) or
     // published for the other workgroups of the segment
     KMSlot* slot = my + (t & 1);
+    // fold the waves' bins into wave 0's row, then the replicas of a cluster
+    for (int b = tid; b < nbins; b += KT) {
+      unsigned long long q = 0;
+      unsigned c = 0;
+#pragma unroll
+      for (int ww = 0; ww < KWAVES; ++ww) { q += sh.sum[ww][b]; c += sh.cnt[ww][b]; }
+      sh.sum[0][b] = q;
+      sh.cnt[0][b] = c;
+    }
+    __syncthreads();
     for (int j = tid; j < k; j += KT) {
       long long q = 0;
       unsigned c = 0;
-      for (int ww = 0; ww < KWAVES; ++ww)
-        for (int r = 0; r < ncopy; ++r) { q += (long long)sh.sum[ww][j * ncopy + r]; c += sh.cnt[ww][j * ncopy + r]; }
+      for (int r = 0; r < ncopy; ++r) { q += (long long)sh.sum[0][j * ncopy + r]; c += sh.cnt[0][j * ncopy + r]; }
       if (G == 1) {
         sh.gsum[0][j] = q;
         sh.gcnt[0][j] = c;
@@ -372,12 +404,13 @@ __global__ __launch_bounds__(KT) void k_kmeans_grid(const KMJob* jobs, KMJob sin
     __syncthreads();
     changed = 0;
     if (REG) {
+      uint8_t nl[REG ? KVPT : 1];
+      assign_regs(v, nl, sh.cent, k, steps, sh.sorted);
 #pragma unroll
       for (int q = 0; q < KVPT; ++q) {
         long long i = i0 + tid + (long long)q * KT;
-        int nl = assign(v[q]);
-        if (i < i1 && nl != lab[q]) changed = 1;
-        lab[q] = (uint8_t)nl;
+        if (i < i1 && nl[q] != lab[q]) changed = 1;
+        lab[q] = nl[q];
       }
     } else {
       for (long long i = i0 + tid; i < i1; i += KT) {
