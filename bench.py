@@ -91,6 +91,9 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--profile-kernels", action="store_true",
+                    help="only launch the projector and backprojector of the workload a few times, and a "
+                         "device copy of known size (for counter runs); prints their launch counts")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: every node of the workload runs on one device "
@@ -122,6 +125,22 @@ def main():
     run = A.DADMM(ctx, [s], rho=rho, eta2=w.eta2, e1=w.inner_iters, e2=w.x_iters,
                   mode=T.TOMO_XUPDATE_SEGMENT, quant=q, msgs=msgs)
     updates_per_step = 2 * w.inner_iters * w.n_angles * w.n * w.n
+
+    if args.profile_kernels:
+        reps = 5
+        for phase in (0, 1):
+            for _ in range(reps):
+                T.admm_local_phase(ctx, run.nodes, phase)
+        copy_bytes = 1 << 28
+        a = torch.empty(copy_bytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(reps):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_kernels": {"project_launches": reps, "backproject_launches": reps,
+                                              "copy_launches": reps, "copy_bytes": copy_bytes,
+                                              "updates_per_launch": w.n_angles * w.n * w.n}}), flush=True)
+        return
 
     # --- equal-RMSE check: plain per-node loop vs batched graph, same iterations
     n_eq = args.plain_steps
