@@ -14,11 +14,17 @@ implementation that follows the same steps reaches identical labels:
    (so every |a_i| < 2^e), S = 30 - e; q_i = round-half-even(a_i * 2^S) as an
    integer, |q_i| <= 2^30.  Every cluster sum of q is then exact in int64 for
    any n < 2^32.
-4. Assignment: label_i = the lowest j that minimises |a_i - c_j| computed as a
-   float32 subtraction and absolute value.
+4. Assignment: with the centres in increasing order, the nearest centre of a
+   value is the number of midpoints between consecutive centres that lie below
+   it: label_i = #{j < k-1 : 2 a_i > c_j + c_{j+1}}, where 2 a_i is exact in
+   float64 and the sum c_j + c_{j+1} is rounded once to float64.  A value at a
+   midpoint goes to the lower centre.  (This rule is monotone in the value, so
+   every cluster is a run of the sorted values.)
 5. Lloyd iterations t = 1..T_max: c_j <- f32(f64(sum_{label=j} q) * 2^-S / f64(count_j))
-   for non-empty clusters (an empty cluster keeps its centre), then reassign;
-   stop as soon as the labels do not change.
+   for non-empty clusters (an empty cluster keeps its centre), then the centres
+   are put in increasing order (a stable sort; Lloyd's update keeps the order
+   except in degenerate cases of rounding next to an empty cluster), then
+   reassign; stop as soon as the labels do not change.
 Outputs: labels, the centres that produced them, a_hat_i = c_{label_i}, and the
 number of Lloyd iterations run.
 """
@@ -50,10 +56,17 @@ def initial_centres(lo: float, hi: float, k: int) -> np.ndarray:
                     dtype=np.float32)
 
 
+def midpoint_sums(c32: np.ndarray) -> np.ndarray:
+    """c_j + c_{j+1} of consecutive centres, each rounded once to float64."""
+    c = c32.astype(np.float64)
+    return c[:-1] + c[1:]
+
+
 def assign(a32: np.ndarray, c32: np.ndarray) -> np.ndarray:
-    dist = np.abs(a32[:, None] - c32[None, :])        # float32 arithmetic
-    assert dist.dtype == np.float32
-    return np.argmin(dist, axis=1)                   # first index of the minimum
+    """Nearest centre of every value (centres in increasing order): the count
+    of midpoints below the value, ties to the lower centre (step 4)."""
+    twice = 2.0 * a32.astype(np.float64)             # exact
+    return np.sum(twice[:, None] > midpoint_sums(c32)[None, :], axis=1)
 
 
 def kmeans_quantize(a, k: int, max_iter: int = 30) -> KMeansResult:
@@ -80,6 +93,7 @@ def kmeans_quantize(a, k: int, max_iter: int = 30) -> KMeansResult:
         for j in range(k):
             if counts[j] > 0:
                 c[j] = np.float32(math.ldexp(float(int(sums[j])), -S) / float(counts[j]))
+        c = np.sort(c, kind="stable")
         new = assign(a32, c)
         iters = t
         if np.array_equal(new, labels):

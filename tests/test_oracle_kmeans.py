@@ -7,11 +7,12 @@ with a nearest centre), the paper's remark that an image with three grey levels
 is represented exactly by K = 3, and degenerate cases.
 """
 import itertools
+from fractions import Fraction
 
 import numpy as np
 import pytest
 
-from oracle.kmeans import kmeans_quantize
+from oracle.kmeans import assign, kmeans_quantize
 
 
 def _brute_force_distortion(a, k):
@@ -106,3 +107,22 @@ def test_degenerate_inputs():
     # more clusters than distinct values: the extra centres stay where they were put
     res = kmeans_quantize(np.array([0.0, 1.0, 1.0, 0.0], np.float32), 8)
     np.testing.assert_array_equal(res.a_hat, [0.0, 1.0, 1.0, 0.0])
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_assignment_is_the_exact_nearest_centre(seed):
+    """The midpoint count equals the nearest centre found in exact rational
+    arithmetic (distinct increasing centres), a value at a midpoint going to
+    the lower centre."""
+    rng = np.random.default_rng(50 + seed)
+    k = int(rng.integers(2, 12))
+    c = np.unique(rng.uniform(-2, 3, k).astype(np.float32))
+    a = rng.uniform(-3, 4, 400).astype(np.float32)
+    mids = ((c[:-1].astype(np.float64) + c[1:]) / 2).astype(np.float32)
+    exact_mid = mids[mids.astype(np.float64) * 2 == c[:-1].astype(np.float64) + c[1:]]
+    a = np.concatenate([a, exact_mid, c])
+    got = assign(a, c)
+    cf = [Fraction(float(x)) for x in c]
+    for v, lab in zip(a, got):
+        d = [abs(Fraction(float(v)) - x) for x in cf]
+        assert lab == d.index(min(d)), (v, lab)
