@@ -72,8 +72,11 @@ const char* tomo_last_error(const tomo_ctx* ctx);
  *   TOMO_OPT_KMEANS_GROUPS  workgroups per K-means segment (0 = automatic,
  *                           else 1 .. 256; more than the device can keep
  *                           resident for all segments at once is clamped)
+ *   TOMO_OPT_PROJ_BAND      image lines the projector stages in LDS per pass
+ *                           (16 or 32, default 16); changes the projector's
+ *                           summation order only
  */
-enum { TOMO_OPT_PROJ_JOB_WGS = 1, TOMO_OPT_KMEANS_GROUPS = 2 };
+enum { TOMO_OPT_PROJ_JOB_WGS = 1, TOMO_OPT_KMEANS_GROUPS = 2, TOMO_OPT_PROJ_BAND = 3 };
 int tomo_set_option(tomo_ctx* ctx, int32_t option, int64_t value);
 
 typedef struct {

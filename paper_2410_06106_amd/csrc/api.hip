@@ -10,7 +10,7 @@
 #include "../../include/tomoadmm.h"
 
 namespace tomo {
-template <class Src> __global__ void k_project(Src);
+template <int R, class Src> __global__ void k_project(Src);
 template <class Src> __global__ void k_project_reduce(Src);
 template <class Src> __global__ void k_backproject(Src);
 __global__ void k_seg_none(const SegJob*, int, int);
@@ -93,6 +93,7 @@ struct LocalPlan {
   std::vector<tomo_node> key;
   DevBuf pjobs, rjobs, bjobs, resid, partial;
   int n_p = 0, p_wgs = 0, n_r = 0, r_wgs = 0, n_b = 0, b_wgs = 0;
+  int band = 16;                 // projector band depth (16 or 32)
 };
 
 struct ConsPlan {
@@ -130,6 +131,7 @@ struct tomo_ctx {
   int device = 0;
   int n_cu = 1;
   int proj_job_wgs = 64;      // TOMO_OPT_PROJ_JOB_WGS
+  int proj_band = 16;         // TOMO_OPT_PROJ_BAND
   int kmeans_groups = 0;      // TOMO_OPT_KMEANS_GROUPS (0 = automatic)
   std::string err;
   DevBuf partial;                                // standalone projector workspace
@@ -284,6 +286,7 @@ LocalPlan* get_local_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, in
   plan->p_wgs = pw;
   plan->n_b = (int)bj.size();
   plan->b_wgs = bw;
+  plan->band = ctx->proj_band;
   ctx->lplans.push_back(std::move(plan));
   return ctx->lplans.back().get();
 }
@@ -292,7 +295,10 @@ LocalPlan* get_local_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, in
 // nodes split into several regions) the reduction pass.
 void launch_projection(const LocalPlan* plan, void* stream) {
   Many<ProjJob> ps{static_cast<const ProjJob*>(plan->pjobs.p), plan->n_p};
-  hipLaunchKernelGGL(k_project<Many<ProjJob>>, dim3(plan->p_wgs), dim3(PTHREADS), 0, (hipStream_t)stream, ps);
+  if (plan->band == 32)
+    hipLaunchKernelGGL((k_project<32, Many<ProjJob>>), dim3(plan->p_wgs), dim3(PTHREADS), 0, (hipStream_t)stream, ps);
+  else
+    hipLaunchKernelGGL((k_project<16, Many<ProjJob>>), dim3(plan->p_wgs), dim3(PTHREADS), 0, (hipStream_t)stream, ps);
   if (plan->n_r > 0) {
     Many<ProjJob> rs{static_cast<const ProjJob*>(plan->rjobs.p), plan->n_r};
     hipLaunchKernelGGL(k_project_reduce<Many<ProjJob>>, dim3(plan->r_wgs), dim3(PTHREADS), 0, (hipStream_t)stream,
@@ -444,6 +450,10 @@ int tomo_set_option(tomo_ctx* ctx, int32_t option, int64_t value) {
       if (value < 0 || value > 256) return ctx->fail(TOMO_EINVAL, "K-means groups out of range");
       ctx->kmeans_groups = (int)value;
       break;
+    case TOMO_OPT_PROJ_BAND:
+      if (value != 16 && value != 32) return ctx->fail(TOMO_EINVAL, "projector band depth must be 16 or 32");
+      ctx->proj_band = (int)value;
+      break;
     default:
       return ctx->fail(TOMO_EINVAL, "unknown option");
   }
@@ -471,8 +481,12 @@ int tomo_project(tomo_ctx* ctx, tomo_geom g, const double* angles, int32_t n_ang
     if (!ctx->partial.ensure((size_t)sh[0].wgs() * PA * PACC * 4)) return ctx->fail(TOMO_ENOMEM, "workspace");
     j.partial = static_cast<float*>(ctx->partial.p);
   }
-  hipLaunchKernelGGL(k_project<Single<ProjJob>>, dim3(sh[0].wgs()), dim3(PTHREADS), 0,
-                     (hipStream_t)stream, Single<ProjJob>{j});
+  if (ctx->proj_band == 32)
+    hipLaunchKernelGGL((k_project<32, Single<ProjJob>>), dim3(sh[0].wgs()), dim3(PTHREADS), 0,
+                       (hipStream_t)stream, Single<ProjJob>{j});
+  else
+    hipLaunchKernelGGL((k_project<16, Single<ProjJob>>), dim3(sh[0].wgs()), dim3(PTHREADS), 0,
+                       (hipStream_t)stream, Single<ProjJob>{j});
   if (sh[0].regions() > 1)
     hipLaunchKernelGGL(k_project_reduce<Single<ProjJob>>, dim3(reduce_wgs(sh[0], g.n_bins)), dim3(PTHREADS), 0,
                        (hipStream_t)stream, Single<ProjJob>{j});

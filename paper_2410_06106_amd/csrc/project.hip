@@ -6,27 +6,35 @@
 // axis (rows when |cos| >= |sin|, columns otherwise) and interpolates linearly
 // between the two nearest pixels of each row (column); the region is staged in
 // LDS one band of R rows (columns, transposed on the fly) at a time and every
-// staged band serves all PA angles.  LDS pads of R+3 zero samples on both sides
-// of a band row mean the inner loop needs no bounds checks; pixels outside the
-// region count as zero, so the region's partial ray sums add up exactly to the
+// staged band serves all PA angles.  Zero pads of R+4 samples on both sides of
+// a band row mean the inner loop needs no bounds checks; pixels outside the
+// region count as zero, so the regions' partial ray sums add up exactly to the
 // full projection.  When a job has several regions, a second small launch adds
 // the regions' partials in region order: no atomics and no cross-workgroup
 // handshakes inside a launch, results are bit-reproducible.
+//
+// LDS rows are 16-byte aligned so whole float4s are staged with one store, and
+// transposed staging assigns consecutive image rows to consecutive lanes, so
+// neither staging pattern has bank conflicts.
 #include "common.h"
 
 namespace tomo {
 
 namespace {
 
-constexpr int PR = 16;                         // band depth (driving direction)
-constexpr int PPAD = PR + 3;                   // zero pad on each side of a band row
-constexpr int PLS = PREG + 2 * PPAD + 1;       // LDS row stride in floats (odd)
+template <int R>
+struct Band {
+  static constexpr int PAD = R + 4;                 // zero samples on each side of a band row
+  static constexpr int LS = PREG + 2 * PAD;         // LDS row stride in floats (multiple of 4)
+};
 
 struct AngleParam {
   double xi0;     // interpolation coordinate of ray j = 0 at driving index 0 (LDS units)
   double beta;    // d(xi)/dj
   double gamma;   // d(xi)/d(driving index)
-  double ibeta;   // 1 / beta
+  double rlo0;    // first candidate ray of the band at driving index 0 (affine in it)
+  double rhi0;    // last candidate ray of the band at driving index 0
+  double rsl;     // slope of both with the band's first driving index
   float scale;    // path length per step: 1/|cos| or 1/|sin|
   int cls;        // 0 row-driven, 1 column-driven, -1 inactive
   int bbase;      // detector bin of ray j = 0 for this region
@@ -52,9 +60,10 @@ __device__ __forceinline__ void region_of(const ProjJob& J, int region, int& gr0
 
 }  // namespace
 
-template <class Src>
+template <int R, class Src>
 __global__ __launch_bounds__(PTHREADS) void k_project(Src src) {
-  __shared__ float band[PR * PLS];
+  using B = Band<R>;
+  __shared__ __align__(16) float band[R * B::LS];
   __shared__ float acc[PA * PACC];
   __shared__ AngleParam prm[PA];
 
@@ -67,6 +76,7 @@ __global__ __launch_bounds__(PTHREADS) void k_project(Src src) {
   const int na = min(PA, J.n_ang - a0);
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
+  constexpr int NW = PTHREADS / 64;
   const double h = 0.5 * (J.n - 1), hb = 0.5 * (J.nb - 1);
 
   int gr0, gc0, gh, gw;
@@ -75,35 +85,46 @@ __global__ __launch_bounds__(PTHREADS) void k_project(Src src) {
   if (tid < PA) {
     AngleParam p;
     p.cls = -1;
-    p.xi0 = p.beta = p.gamma = p.ibeta = 0.0;
+    p.xi0 = p.beta = p.gamma = p.rlo0 = p.rhi0 = p.rsl = 0.0;
     p.scale = 0.f;
     p.bbase = 0;
     if (tid < na) {
       double th = J.ang[a0 + tid];
       double cs = cos(th), sn = sin(th);
       p.bbase = region_bbase(cs, sn, h, hb, gr0, gc0, gh, gw);
+      double ib, W;
       if (fabs(cs) >= fabs(sn)) {   // walk rows, interpolate across columns
         p.cls = 0;
         p.beta = 1.0 / cs;
-        p.ibeta = cs;
+        ib = cs;
         p.gamma = -sn / cs;
-        p.xi0 = (p.bbase - hb - (gr0 - h) * sn) / cs + h - gc0 + PPAD;
+        p.xi0 = (p.bbase - hb - (gr0 - h) * sn) / cs + h - gc0 + B::PAD;
         p.scale = (float)(1.0 / fabs(cs));
+        W = gw;
       } else {                      // walk columns, interpolate across rows
         p.cls = 1;
         p.beta = 1.0 / sn;
-        p.ibeta = sn;
+        ib = sn;
         p.gamma = -cs / sn;
-        p.xi0 = (p.bbase - hb - (gc0 - h) * cs) / sn + h - gr0 + PPAD;
+        p.xi0 = (p.bbase - hb - (gc0 - h) * cs) / sn + h - gr0 + B::PAD;
         p.scale = (float)(1.0 / fabs(sn));
+        W = gh;
       }
+      // rays j with PAD-1 < xi(j, d) < PAD+W for some driving index d of the
+      // band [db, db+R): both bounds are affine in db with slope -gamma/beta
+      const double span = (R - 1) * p.gamma;
+      const double t1 = (B::PAD - 1 - p.xi0 - fmax(0.0, span)) * ib;
+      const double t2 = (B::PAD + W - p.xi0 - fmin(0.0, span)) * ib;
+      p.rlo0 = fmin(t1, t2);
+      p.rhi0 = fmax(t1, t2);
+      p.rsl = -p.gamma * ib;
     }
     prm[tid] = p;
   }
   for (int i = tid; i < PA * PACC; i += PTHREADS) acc[i] = 0.f;
   __syncthreads();
 
-  // vectorised staging needs 16-byte aligned rows and region corners
+  // whole-float4 staging needs 16-byte aligned rows and region corners
   const bool vec4 = ((J.n & 3) == 0) && ((gc0 & 3) == 0) && ((gw & 3) == 0) &&
                     ((reinterpret_cast<uintptr_t>(J.img) & 15) == 0);
 
@@ -115,108 +136,99 @@ __global__ __launch_bounds__(PTHREADS) void k_project(Src src) {
     const int W = cls == 0 ? gw : gh;   // interpolation extent
 
     __syncthreads();
-    for (int i = tid; i < PR * PLS; i += PTHREADS) band[i] = 0.f;
+    for (int i = tid; i < R * B::LS; i += PTHREADS) band[i] = 0.f;
 
-    for (int db = 0; db < D; db += PR) {
+    for (int db = 0; db < D; db += R) {
       __syncthreads();
-      // stage PR driving lines of the region (lines beyond D stay zero)
-      const int nl = min(PR, D - db);
+      // stage R driving lines of the region (lines beyond D are zero)
+      const int nl = min(R, D - db);
       if (cls == 0) {
         if (vec4) {
-          const int W4 = W >> 2;        // W is a multiple of 4 when vec4 holds
-          for (int i = tid >> 6; i < PR; i += PTHREADS / 64) {
-            float* dst = band + i * PLS + PPAD;
-            if (i < nl) {
-              const float4* src4 = reinterpret_cast<const float4*>(J.img + (size_t)(gr0 + db + i) * J.n + gc0);
-              for (int k = lane; k < W4; k += 64) {
-                float4 v = src4[k];
-                dst[4 * k] = v.x; dst[4 * k + 1] = v.y; dst[4 * k + 2] = v.z; dst[4 * k + 3] = v.w;
-              }
-            } else {
-              for (int k = lane; k < W; k += 64) dst[k] = 0.f;
-            }
+          const int W4 = W >> 2;
+          for (int i = wave; i < R; i += NW) {
+            float4* dst = reinterpret_cast<float4*>(band + i * B::LS + B::PAD);
+            const float4* srow = reinterpret_cast<const float4*>(J.img + (size_t)(gr0 + db + i) * J.n + gc0);
+            for (int k = lane; k < W4; k += 64) dst[k] = i < nl ? srow[k] : make_float4(0.f, 0.f, 0.f, 0.f);
           }
         } else {
-          for (int i = 0; i < PR; ++i) {
-            float* dst = band + i * PLS + PPAD;
+          for (int i = wave; i < R; i += NW) {
+            float* dst = band + i * B::LS + B::PAD;
             const float* srow = J.img + (size_t)(gr0 + db + i) * J.n + gc0;
-            for (int k = tid; k < W; k += PTHREADS) dst[k] = i < nl ? srow[k] : 0.f;
+            for (int k = lane; k < W; k += 64) dst[k] = i < nl ? srow[k] : 0.f;
           }
         }
       } else {
+        // lane -> image row k, each wave stages groups of 4 band columns
         if (vec4) {
-          // thread -> (image row k, 4 adjacent band columns), written transposed
-          const int q = tid & 3;
-          for (int k = tid >> 2; k < W; k += PTHREADS / 4) {
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            const int c = db + 4 * q;
-            if (c < D) v = *reinterpret_cast<const float4*>(J.img + (size_t)(gr0 + k) * J.n + gc0 + c);
-            // columns beyond D inside a partial group are masked individually
-            band[(4 * q + 0) * PLS + PPAD + k] = (c + 0 < D) ? v.x : 0.f;
-            band[(4 * q + 1) * PLS + PPAD + k] = (c + 1 < D) ? v.y : 0.f;
-            band[(4 * q + 2) * PLS + PPAD + k] = (c + 2 < D) ? v.z : 0.f;
-            band[(4 * q + 3) * PLS + PPAD + k] = (c + 3 < D) ? v.w : 0.f;
+          for (int k0 = 0; k0 < W; k0 += 64) {
+            const int k = k0 + lane;
+            for (int q = wave; q < R / 4; q += NW) {
+              const int c = db + 4 * q;
+              float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+              if (k < W && c < D) v = *reinterpret_cast<const float4*>(J.img + (size_t)(gr0 + k) * J.n + gc0 + c);
+              if (k < W) {
+                float* dst = band + 4 * q * B::LS + B::PAD + k;
+                dst[0] = v.x;                // D is a multiple of 4 here, so c < D covers c+3
+                dst[B::LS] = v.y;
+                dst[2 * B::LS] = v.z;
+                dst[3 * B::LS] = v.w;
+              }
+            }
           }
         } else {
-          for (int k = tid >> 4; k < W; k += PTHREADS / 16) {
-            const int i = tid & 15;
-            float v = (i < nl) ? J.img[(size_t)(gr0 + k) * J.n + gc0 + db + i] : 0.f;
-            band[i * PLS + PPAD + k] = v;
+          for (int k0 = 0; k0 < W; k0 += 64) {
+            const int k = k0 + lane;
+            if (k >= W) continue;
+            for (int i = wave; i < R; i += NW) {
+              float v = i < nl ? J.img[(size_t)(gr0 + k) * J.n + gc0 + db + i] : 0.f;
+              band[i * B::LS + B::PAD + k] = v;
+            }
           }
         }
       }
       __syncthreads();
 
-      // rays of each angle of this class that meet the band (wave-uniform values)
+      // rays of each angle of this class that meet the band (wave-uniform)
       int jlo[PA], jhi[PA], nch[PA];
-      double xib[PA];
       int tot = 0;
 #pragma unroll
       for (int a = 0; a < PA; ++a) {
         jlo[a] = 0;
         jhi[a] = -1;
         nch[a] = 0;
-        xib[a] = 0.0;
         if (a < na && prm[a].cls == cls) {
-          const double x0 = prm[a].xi0, gm = prm[a].gamma, ib = prm[a].ibeta;
-          double e0 = x0 + db * gm, e1 = x0 + (db + PR - 1) * gm;
-          double emin = fmin(e0, e1), emax = fmax(e0, e1);
-          double lo = (PPAD - 1 - emax) * ib, hi = (PPAD + W - emin) * ib;
-          if (lo > hi) { double t = lo; lo = hi; hi = t; }
           const int bb = prm[a].bbase;
-          int jl = max((int)floor(lo), max(0, -bb));
-          int jh = min((int)ceil(hi), min(PACC - 1, J.nb - 1 - bb));
+          int jl = max((int)floor(prm[a].rlo0 + db * prm[a].rsl), max(0, -bb));
+          int jh = min((int)ceil(prm[a].rhi0 + db * prm[a].rsl), min(PACC - 1, J.nb - 1 - bb));
           jlo[a] = jl;
           jhi[a] = jh;
           nch[a] = jh >= jl ? ((jh - jl + 1 + 63) >> 6) : 0;
-          xib[a] = e0;
         }
         tot += nch[a];
       }
       // each wave takes chunks of 64 consecutive rays of one angle
-      for (int ch = wave; ch < tot; ch += PTHREADS / 64) {
+      for (int ch = wave; ch < tot; ch += NW) {
         int a = 0, base = 0;
 #pragma unroll
         for (int q = 0; q < PA - 1; ++q) {
           if (ch >= base + nch[a]) { base += nch[a]; ++a; }
         }
         int ja = 0, jb = -1;
-        double xa = 0.0;
 #pragma unroll
-        for (int q = 0; q < PA; ++q) if (q == a) { ja = jlo[q]; jb = jhi[q]; xa = xib[q]; }
+        for (int q = 0; q < PA; ++q) if (q == a) { ja = jlo[q]; jb = jhi[q]; }
         const int j = ja + ((ch - base) << 6) + lane;
-        const AngleParam& p = prm[a];
         if (j > jb) continue;
-        const float xi = (float)(xa + (double)j * p.beta);
+        const AngleParam& p = prm[a];
+        const float xi = (float)(p.xi0 + db * p.gamma + (double)j * p.beta);
         const float g = (float)p.gamma;
         float s0 = 0.f, s1 = 0.f;
 #pragma unroll
-        for (int i = 0; i < PR; ++i) {
+        for (int i = 0; i < R; ++i) {
           float xx = i == 0 ? xi : fmaf((float)i, g, xi);
           float f = __builtin_amdgcn_fractf(xx);   // xx > 0: truncation is the floor
           int c0 = (int)xx;
-          float v0 = band[i * PLS + c0];
-          float v1 = band[i * PLS + c0 + 1];
+          float v0 = band[i * B::LS + c0];
+          float v1 = band[i * B::LS + c0 + 1];
           s0 += v0;
           s1 = fmaf(f, v1 - v0, s1);
         }
@@ -294,8 +306,10 @@ __global__ __launch_bounds__(PTHREADS) void k_project_reduce(Src src) {
   }
 }
 
-template __global__ void k_project<Single<ProjJob>>(Single<ProjJob>);
-template __global__ void k_project<Many<ProjJob>>(Many<ProjJob>);
+template __global__ void k_project<16, Single<ProjJob>>(Single<ProjJob>);
+template __global__ void k_project<16, Many<ProjJob>>(Many<ProjJob>);
+template __global__ void k_project<32, Single<ProjJob>>(Single<ProjJob>);
+template __global__ void k_project<32, Many<ProjJob>>(Many<ProjJob>);
 template __global__ void k_project_reduce<Single<ProjJob>>(Single<ProjJob>);
 template __global__ void k_project_reduce<Many<ProjJob>>(Many<ProjJob>);
 

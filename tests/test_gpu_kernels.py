@@ -99,6 +99,44 @@ def test_projector_full_size_sampled_angles(T, ctx):
     assert rel_l2(got_b, joseph.backproject(sino, th_all[pick], n)) <= 1e-5
 
 
+@pytest.mark.parametrize("band", [16, 32])
+@pytest.mark.parametrize("job_wgs", [1, 64, 4096])
+def test_projector_launch_options_match_oracle(T, band, job_wgs):
+    """Every band depth and region split gives the oracle's projection, both
+    through tomo_project and through the batched local update's residual."""
+    log(f"case options band={band} job_wgs={job_wgs}")
+    c = T.Context(0)
+    T.tomo_set_option(c, T.TOMO_OPT_PROJ_BAND, band)
+    T.tomo_set_option(c, T.TOMO_OPT_PROJ_JOB_WGS, job_wgs)
+    rng = np.random.default_rng(band + job_wgs)
+    for n, nb, k in ((300, 431, 11), (257, 180, 7), (64, 91, 90)):
+        th = rng.uniform(0, np.pi, k)
+        img = rng.random((n, n)).astype(np.float32)
+        got = T.tomo_project(c, to_dev(th, torch.float64), to_dev(img), nb).cpu().numpy()
+        assert rel_l2(got, joseph.project(img, th, nb)) <= 1e-5
+    n, nb, k, M = 96, 137, 40, 2
+    rng, th, parts, d = _nodes_problem(n, nb, k, M, band * job_wgs)
+    x = rng.random((n, n)).astype(np.float32)
+    us = [rng.random((n, n)).astype(np.float32) for _ in range(M)]
+    U = [to_dev(u) for u in us]
+    X, L0 = to_dev(x), to_dev(np.zeros((n, n), np.float32))
+    ents = [dict(n=n, n_bins=nb, angles=to_dev(th[p], torch.float64), slice=0, d=to_dev(d[m].astype(np.float32)),
+                 u=U[m], lam=L0, x=X, seg_row0=48 * m, seg_rows=48, rho=1.0, eta1=1e-4, eta2=0.2)
+            for m, p in enumerate(parts)]
+    T.admm_local_update(c, T.make_nodes(ents), 2)
+    for m, p in enumerate(parts):
+        ref = oadmm.local_update(us[m], x, np.zeros((n, n)), d[m].astype(np.float32), th[p], 1.0, 1e-4, 2)
+        assert rel_l2(U[m].cpu().numpy(), ref) <= 1e-5
+
+
+def test_set_option_rejects_bad_values(T):
+    c = T.Context(0)
+    for opt, bad in ((T.TOMO_OPT_PROJ_BAND, 8), (T.TOMO_OPT_PROJ_BAND, 64), (T.TOMO_OPT_PROJ_JOB_WGS, 0),
+                     (T.TOMO_OPT_KMEANS_GROUPS, 257), (99, 1)):
+        with pytest.raises(T.TomoError):
+            T.tomo_set_option(c, opt, bad)
+
+
 def test_projector_is_deterministic(T, ctx):
     rng = np.random.default_rng(2)
     n, nb = 700, 990
