@@ -69,14 +69,11 @@ const char* tomo_last_error(const tomo_ctx* ctx);
  *   TOMO_OPT_PROJ_JOB_WGS   projector workgroups wanted per node before its
  *                           image is split into smaller regions (default 64,
  *                           1 .. 65536)
- *   TOMO_OPT_KMEANS_GROUPS  workgroups per K-means segment (0 = automatic,
- *                           else 1 .. 256; more than the device can keep
- *                           resident for all segments at once is clamped)
  *   TOMO_OPT_PROJ_BAND      image lines the projector stages in LDS per pass
  *                           (16 or 32, default 16); changes the projector's
  *                           summation order only
  */
-enum { TOMO_OPT_PROJ_JOB_WGS = 1, TOMO_OPT_KMEANS_GROUPS = 2, TOMO_OPT_PROJ_BAND = 3 };
+enum { TOMO_OPT_PROJ_JOB_WGS = 1, TOMO_OPT_PROJ_BAND = 3 };
 int tomo_set_option(tomo_ctx* ctx, int32_t option, int64_t value);
 
 typedef struct {
@@ -173,7 +170,7 @@ typedef struct {
  * then each segment is replaced by Q(segment) in place (Eq. 23), and finally
  *   lambda_m <- lambda_m + rho (u_m - x)   for every node (Eq. 24).
  * q == NULL means no quantization.  msg == NULL or an array of n_nodes entries.
- * K-means requires seg_rows*n <= 2^22 values per segment; DCT requires seg_rows
+ * K-means requires seg_rows*n < 2^31 values per segment; DCT requires seg_rows
  * and n to be multiples of 8.
  */
 int admm_consensus(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, int32_t mode,
@@ -186,10 +183,14 @@ int admm_consensus(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, int32
  *  centres start at lo + (hi-lo)(2j+1)/(2k) (float64, no FMA, rounded to float32);
  *  values enter the centroid sums as fixed point round(a * 2^S), S = 30 - e,
  *  e the binary exponent of max(|lo|,|hi|), summed exactly in int64;
- *  label = lowest j minimising |a - c_j| in float32; Lloyd iterations until the
+ *  label = #{j < k-1 : 2a > c_j + c_{j+1}} in float64 (the nearest centre, the
+ *  centres being kept in increasing order: after each update they are stably
+ *  sorted; an empty cluster keeps its centre); Lloyd iterations until the
  *  labels repeat or max_iter.  hi == lo: labels 0, centres lo, iters 0.
- * Outputs: labels uint8 [n], centroids float32 [k], a_hat float32 [n] (nullable,
- * may alias a), iters int32 [1] (nullable).  1 <= k <= 256, 1 <= n <= 2^22.
+ * Outputs: labels uint8 [n], centroids float32 [k] (increasing), a_hat float32
+ * [n] (nullable, may alias a), iters int32 [1] (nullable).  1 <= k <= 256,
+ * 1 <= n < 2^31.  Segments above 16384 values use a context workspace of
+ * 4n bytes (allocated on first need, kept until tomo_destroy).
  */
 int quantize_kmeans(tomo_ctx* ctx, const float* a, int64_t n, int32_t k, int32_t max_iter,
                     uint8_t* labels, float* centroids, float* a_hat, int32_t* iters, void* stream);

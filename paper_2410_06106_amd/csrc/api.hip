@@ -14,7 +14,7 @@ template <int R, class Src> __global__ void k_project(Src);
 template <class Src> __global__ void k_project_reduce(Src);
 template <class Src> __global__ void k_backproject(Src);
 __global__ void k_seg_none(const SegJob*, int, int);
-template <bool REG> __global__ void k_kmeans_grid(const KMJob*, KMJob, int, int, int, int, KMSlot*, KMSync*);
+template <bool VLDS> __global__ void k_kmeans(const KMJob*, KMJob, int, int, int, float*, long long);
 __global__ void k_seg_dct(const SegJob*, int, int, int);
 __global__ void k_dct(const float*, int, int, int, int, int16_t*, float*, float*);
 __global__ void k_avg(Many<AvgJob>, const NodeRef*);
@@ -99,27 +99,17 @@ struct LocalPlan {
 struct ConsPlan {
   std::vector<tomo_node> key;
   std::vector<tomo_msg> msg_key;
-  DevBuf seg, avg, noderefs, labels, kmjobs, kmslots, kmsync;
+  DevBuf seg, avg, noderefs, labels, kmjobs, kmwork;
   int n_seg = 0, n_avg = 0, avg_wgs = 0, dual_wgs = 0;
-  int km_G = 1;
-  bool km_reg = true;
+  long long km_stride = 0;     // workspace floats per segment (0: segments regroup in LDS)
   long long label_stride = 0;
 };
 
-// Workgroups per K-means segment: spread segments over the CUs (all of a
-// segment's workgroups must be resident together) with >= 1024 values each.
-constexpr int kKmRegElems = 1024 * 16;  // values a K-means workgroup keeps in registers
 constexpr int kKmThreads = 1024;
 
-// Automatic choice: one workgroup per segment (no barrier) unless the segment
-// is larger than a workgroup's registers hold, then the fewest that fit, at
-// most 16 and never more than the CUs can hold for all segments at once.
-int kmeans_groups(int n_cu, int n_seg, long long max_n, int forced) {
-  long long fit = std::max(1, std::min(16, n_cu / std::max(1, n_seg)));
-  if (forced > 0) return (int)std::min<long long>(forced, fit);
-  long long want = (max_n + kKmRegElems - 1) / kKmRegElems;
-  return (int)std::max(1ll, std::min(want, fit));
-}
+// Workspace floats per segment of the K-means kernel: none when every segment
+// fits the LDS copy, else the longest segment.
+long long kmeans_stride(long long max_n) { return max_n <= KM_LDS_VALUES ? 0 : max_n; }
 
 bool same_nodes(const std::vector<tomo_node>& k, const tomo_node* nodes, int n) {
   return (int)k.size() == n && std::memcmp(k.data(), nodes, sizeof(tomo_node) * n) == 0;
@@ -132,10 +122,9 @@ struct tomo_ctx {
   int n_cu = 1;
   int proj_job_wgs = 64;      // TOMO_OPT_PROJ_JOB_WGS
   int proj_band = 16;         // TOMO_OPT_PROJ_BAND
-  int kmeans_groups = 0;      // TOMO_OPT_KMEANS_GROUPS (0 = automatic)
   std::string err;
   DevBuf partial;                                // standalone projector workspace
-  DevBuf km_slots, km_sync;                      // standalone K-means workspace
+  DevBuf km_work;                                // standalone K-means workspace
   std::vector<std::unique_ptr<LocalPlan>> lplans;
   std::vector<std::unique_ptr<ConsPlan>> cplans;
   // plans dropped by tomo_set_option stay allocated (a captured graph may
@@ -349,8 +338,7 @@ ConsPlan* get_cons_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, cons
     avg.back().n_nodes++;
   }
   plan->label_stride = (max_seg + 255) / 256 * 256;
-  plan->km_G = kmeans_groups(ctx->n_cu, n_nodes, max_seg, ctx->kmeans_groups);
-  plan->km_reg = (max_seg + plan->km_G - 1) / plan->km_G <= kKmRegElems;
+  plan->km_stride = kmeans_stride(max_seg);
   std::vector<KMJob> km;
   for (int i = 0; i < n_nodes; ++i) {
     const tomo_node& N = nodes[i];
@@ -369,19 +357,17 @@ ConsPlan* get_cons_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, cons
     j.iters = msg ? msg[i].iters : nullptr;
     km.push_back(j);
   }
-  const size_t n_slots = (size_t)n_nodes * plan->km_G * 2;
   if (!plan->seg.ensure(seg.size() * sizeof(SegJob)) || !plan->avg.ensure(avg.size() * sizeof(AvgJob)) ||
       !plan->noderefs.ensure(refs.size() * sizeof(NodeRef)) ||
       !plan->labels.ensure((size_t)plan->label_stride * n_nodes) ||
-      !plan->kmjobs.ensure(km.size() * sizeof(KMJob)) || !plan->kmslots.ensure(n_slots * sizeof(KMSlot)) ||
-      !plan->kmsync.ensure((size_t)n_nodes * sizeof(KMSync))) {
+      !plan->kmjobs.ensure(km.size() * sizeof(KMJob)) ||
+      !plan->kmwork.ensure((size_t)plan->km_stride * n_nodes * sizeof(float))) {
     rc = ctx->fail(TOMO_ENOMEM, "consensus plan allocation failed");
     return nullptr;
   }
   for (int i = 0; i < n_nodes; ++i)
     if (!km[i].labels) km[i].labels = static_cast<uint8_t*>(plan->labels.p) + (size_t)i * plan->label_stride;
-  if (hipMemset(plan->kmsync.p, 0, (size_t)n_nodes * sizeof(KMSync)) != hipSuccess ||
-      hipMemcpy(plan->kmjobs.p, km.data(), km.size() * sizeof(KMJob), hipMemcpyHostToDevice) != hipSuccess) {
+  if (hipMemcpy(plan->kmjobs.p, km.data(), km.size() * sizeof(KMJob), hipMemcpyHostToDevice) != hipSuccess) {
     rc = ctx->fail(TOMO_EDEVICE, "K-means plan upload failed");
     return nullptr;
   }
@@ -445,10 +431,6 @@ int tomo_set_option(tomo_ctx* ctx, int32_t option, int64_t value) {
     case TOMO_OPT_PROJ_JOB_WGS:
       if (value < 1 || value > 65536) return ctx->fail(TOMO_EINVAL, "projector workgroups per job out of range");
       ctx->proj_job_wgs = (int)value;
-      break;
-    case TOMO_OPT_KMEANS_GROUPS:
-      if (value < 0 || value > 256) return ctx->fail(TOMO_EINVAL, "K-means groups out of range");
-      ctx->kmeans_groups = (int)value;
       break;
     case TOMO_OPT_PROJ_BAND:
       if (value != 16 && value != 32) return ctx->fail(TOMO_EINVAL, "projector band depth must be 16 or 32");
@@ -562,7 +544,7 @@ int admm_consensus(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, int32
   if (kind < TOMO_QUANT_NONE || kind > TOMO_QUANT_DCT) return ctx->fail(TOMO_EINVAL, "bad quantizer");
   for (int i = 0; i < n_nodes; ++i) {
     long long segn = (long long)nodes[i].seg_rows * nodes[i].g.n;
-    if (kind == TOMO_QUANT_KMEANS && (q->levels < 1 || q->levels > 256 || q->max_iter < 0 || segn > (1ll << 31)))
+    if (kind == TOMO_QUANT_KMEANS && (q->levels < 1 || q->levels > 256 || q->max_iter < 0 || segn >= (1ll << 31)))
       return ctx->fail(TOMO_EINVAL, "bad K-means parameters");
     if (kind == TOMO_QUANT_DCT && (q->quality < 1 || q->quality > 100 || nodes[i].seg_rows % 8 || nodes[i].g.n % 8))
       return ctx->fail(TOMO_EINVAL, "bad DCT parameters (quality 1..100, segment sides multiples of 8)");
@@ -582,16 +564,14 @@ int admm_consensus(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, int32
   if (kind == TOMO_QUANT_KMEANS) {
     // the x-update (SEG) runs inside the K-means kernel; AVG already wrote x
     const KMJob* kj = static_cast<const KMJob*>(plan->kmjobs.p);
-    KMSlot* sl = static_cast<KMSlot*>(plan->kmslots.p);
-    KMSync* sy = static_cast<KMSync*>(plan->kmsync.p);
+    float* wk = static_cast<float*>(plan->kmwork.p);
     const int ex = do_x ? e2 : 0;
-    dim3 grid(plan->n_seg * plan->km_G);
-    if (plan->km_reg)
-      hipLaunchKernelGGL(k_kmeans_grid<true>, grid, dim3(kKmThreads), 0, s, kj, KMJob{}, plan->km_G, q->levels,
-                         q->max_iter, ex, sl, sy);
+    if (plan->km_stride == 0)
+      hipLaunchKernelGGL(k_kmeans<true>, dim3(plan->n_seg), dim3(kKmThreads), 0, s, kj, KMJob{}, q->levels,
+                         q->max_iter, ex, wk, 0ll);
     else
-      hipLaunchKernelGGL(k_kmeans_grid<false>, grid, dim3(kKmThreads), 0, s, kj, KMJob{}, plan->km_G, q->levels,
-                         q->max_iter, ex, sl, sy);
+      hipLaunchKernelGGL(k_kmeans<false>, dim3(plan->n_seg), dim3(kKmThreads), 0, s, kj, KMJob{}, q->levels,
+                         q->max_iter, ex, wk, plan->km_stride);
   } else if (kind == TOMO_QUANT_DCT) {
     hipLaunchKernelGGL(k_seg_dct, dim3(plan->n_seg), dim3(256), 0, s, seg, do_x, e2, q->quality);
   } else if (do_x) {
@@ -605,19 +585,14 @@ int admm_consensus(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, int32
 int quantize_kmeans(tomo_ctx* ctx, const float* a, int64_t n, int32_t k, int32_t max_iter, uint8_t* labels,
                     float* centroids, float* a_hat, int32_t* iters, void* stream) {
   if (!ctx) return TOMO_EINVAL;
-  if (n < 1 || n > (1ll << 31)) return ctx->fail(TOMO_EINVAL, "n must lie in [1, 2^31]");
+  if (n < 1 || n >= (1ll << 31)) return ctx->fail(TOMO_EINVAL, "n must lie in [1, 2^31)");
   if (k < 1 || k > 256 || max_iter < 0) return ctx->fail(TOMO_EINVAL, "k must lie in [1, 256], max_iter >= 0");
   if (!a || !labels || !centroids) return ctx->fail(TOMO_EINVAL, "null pointer");
   if (a_hat && a_hat != a && overlaps(a, (size_t)n * 4, a_hat, (size_t)n * 4))
     return ctx->fail(TOMO_EINVAL, "a_hat partially overlaps a");
   if (int rc = set_device(ctx)) return rc;
-  const int G = kmeans_groups(ctx->n_cu, 1, n, ctx->kmeans_groups);
-  const bool reg = (n + G - 1) / G <= kKmRegElems;
-  if (!ctx->km_slots.ensure((size_t)G * 2 * sizeof(KMSlot))) return ctx->fail(TOMO_ENOMEM, "workspace");
-  size_t had = ctx->km_sync.bytes;
-  if (!ctx->km_sync.ensure(sizeof(KMSync))) return ctx->fail(TOMO_ENOMEM, "workspace");
-  if (ctx->km_sync.bytes != had && hipMemset(ctx->km_sync.p, 0, sizeof(KMSync)) != hipSuccess)
-    return ctx->fail(TOMO_EDEVICE, "hipMemset failed");
+  const long long stride = kmeans_stride(n);
+  if (!ctx->km_work.ensure((size_t)stride * sizeof(float))) return ctx->fail(TOMO_ENOMEM, "workspace");
   KMJob j{};
   j.src = a;
   j.a_hat = a_hat;
@@ -626,14 +601,13 @@ int quantize_kmeans(tomo_ctx* ctx, const float* a, int64_t n, int32_t k, int32_t
   j.iters = iters;
   j.n = n;
   j.rho = 1.f;
-  KMSlot* sl = static_cast<KMSlot*>(ctx->km_slots.p);
-  KMSync* sy = static_cast<KMSync*>(ctx->km_sync.p);
-  if (reg)
-    hipLaunchKernelGGL(k_kmeans_grid<true>, dim3(G), dim3(kKmThreads), 0, (hipStream_t)stream, nullptr, j, G, k,
-                       max_iter, 0, sl, sy);
+  float* wk = static_cast<float*>(ctx->km_work.p);
+  if (stride == 0)
+    hipLaunchKernelGGL(k_kmeans<true>, dim3(1), dim3(kKmThreads), 0, (hipStream_t)stream, nullptr, j, k, max_iter,
+                       0, wk, 0ll);
   else
-    hipLaunchKernelGGL(k_kmeans_grid<false>, dim3(G), dim3(kKmThreads), 0, (hipStream_t)stream, nullptr, j, G, k,
-                       max_iter, 0, sl, sy);
+    hipLaunchKernelGGL(k_kmeans<false>, dim3(1), dim3(kKmThreads), 0, (hipStream_t)stream, nullptr, j, k, max_iter,
+                       0, wk, stride);
   return launch_status(ctx, "quantize_kmeans");
 }
 

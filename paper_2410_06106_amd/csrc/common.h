@@ -129,23 +129,16 @@ struct KMJob {
   float* a_hat;         // quantized values (nullable, may equal src)
   const float* u;       // Alg. 3 inputs, or null for no x-update
   const float* lam;
-  uint8_t* labels;      // [n] (required when the slice of a workgroup exceeds its registers)
+  uint8_t* labels;      // [n] (nullable)
   float* cent;          // [k] (nullable)
   int32_t* iters;       // [1] (nullable)
-  long long n;
+  long long n;          // < 2^31
   float rho, eta2;
 };
 
-struct KMSlot {         // statistics one workgroup publishes for its segment
-  long long sum[KM_MAX_K];
-  unsigned cnt[KM_MAX_K];
-  float mn, mx;
-  int changed, bad;
-};
-
-struct KMSync {         // per-segment barrier counters, zero between launches
-  unsigned arrive, leave;
-};
+// Segments up to this many values are regrouped in LDS; longer ones in a
+// global workspace of n floats per segment.
+constexpr int KM_LDS_VALUES = 16384;
 
 __device__ __forceinline__ float wave_sum(float v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
