@@ -67,10 +67,10 @@ const char* tomo_last_error(const tomo_ctx* ctx);
  * floating-point summation order in the projector (regions are added in a
  * fixed order, so a given option value is bit-reproducible).
  *   TOMO_OPT_PROJ_JOB_WGS   projector workgroups wanted per node before its
- *                           image is split into smaller regions (default 64,
+ *                           image is split into smaller regions (default 16,
  *                           1 .. 65536)
  *   TOMO_OPT_PROJ_BAND      image lines the projector stages in LDS per pass
- *                           (16 or 32, default 16); changes the projector's
+ *                           (16 or 32, default 32); changes the projector's
  *                           summation order only
  */
 enum { TOMO_OPT_PROJ_JOB_WGS = 1, TOMO_OPT_PROJ_BAND = 3 };

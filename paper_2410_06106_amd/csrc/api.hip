@@ -120,8 +120,8 @@ bool same_nodes(const std::vector<tomo_node>& k, const tomo_node* nodes, int n) 
 struct tomo_ctx {
   int device = 0;
   int n_cu = 1;
-  int proj_job_wgs = 64;      // TOMO_OPT_PROJ_JOB_WGS
-  int proj_band = 16;         // TOMO_OPT_PROJ_BAND
+  int proj_job_wgs = 16;      // TOMO_OPT_PROJ_JOB_WGS
+  int proj_band = 32;         // TOMO_OPT_PROJ_BAND
   std::string err;
   DevBuf partial;                                // standalone projector workspace
   DevBuf km_work;                                // standalone K-means workspace

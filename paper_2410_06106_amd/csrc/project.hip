@@ -15,7 +15,10 @@
 //
 // LDS rows are 16-byte aligned so whole float4s are staged with one store, and
 // transposed staging assigns consecutive image rows to consecutive lanes, so
-// neither staging pattern has bank conflicts.
+// neither staging pattern has bank conflicts.  With 32-line bands (whose LDS
+// use limits a CU to three workgroups) the next band is loaded into registers
+// while the current one is computed; 16-line bands rely on more resident
+// workgroups instead.
 #include "common.h"
 
 namespace tomo {
@@ -35,6 +38,7 @@ struct AngleParam {
   double rlo0;    // first candidate ray of the band at driving index 0 (affine in it)
   double rhi0;    // last candidate ray of the band at driving index 0
   double rsl;     // slope of both with the band's first driving index
+  float g32;      // gamma rounded to float32
   float scale;    // path length per step: 1/|cos| or 1/|sin|
   int cls;        // 0 row-driven, 1 column-driven, -1 inactive
   int bbase;      // detector bin of ray j = 0 for this region
@@ -77,6 +81,7 @@ __global__ __launch_bounds__(PTHREADS) void k_project(Src src) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   constexpr int NW = PTHREADS / 64;
+  static_assert(NW == 4 && PREG == 4 * 64 && R % 16 == 0, "staging assumes 4 waves and 256-wide regions");
   const double h = 0.5 * (J.n - 1), hb = 0.5 * (J.nb - 1);
 
   int gr0, gc0, gh, gw;
@@ -86,7 +91,7 @@ __global__ __launch_bounds__(PTHREADS) void k_project(Src src) {
     AngleParam p;
     p.cls = -1;
     p.xi0 = p.beta = p.gamma = p.rlo0 = p.rhi0 = p.rsl = 0.0;
-    p.scale = 0.f;
+    p.scale = p.g32 = 0.f;
     p.bbase = 0;
     if (tid < na) {
       double th = J.ang[a0 + tid];
@@ -118,6 +123,7 @@ __global__ __launch_bounds__(PTHREADS) void k_project(Src src) {
       p.rlo0 = fmin(t1, t2);
       p.rhi0 = fmax(t1, t2);
       p.rsl = -p.gamma * ib;
+      p.g32 = (float)p.gamma;
     }
     prm[tid] = p;
   }
@@ -135,92 +141,148 @@ __global__ __launch_bounds__(PTHREADS) void k_project(Src src) {
     const int D = cls == 0 ? gh : gw;   // driving extent
     const int W = cls == 0 ? gw : gh;   // interpolation extent
 
-    __syncthreads();
-    for (int i = tid; i < R * B::LS; i += PTHREADS) band[i] = 0.f;
-
-    for (int db = 0; db < D; db += R) {
-      __syncthreads();
-      // stage R driving lines of the region (lines beyond D are zero)
+    // R driving lines [db, db + R) of the region pass through R registers
+    // per thread, loaded one band ahead of the band being computed (lines
+    // beyond D and samples beyond W are zero)
+    float st[R];
+    auto load = [&](int db) {
       const int nl = min(R, D - db);
       if (cls == 0) {
         if (vec4) {
           const int W4 = W >> 2;
-          for (int i = wave; i < R; i += NW) {
-            float4* dst = reinterpret_cast<float4*>(band + i * B::LS + B::PAD);
-            const float4* srow = reinterpret_cast<const float4*>(J.img + (size_t)(gr0 + db + i) * J.n + gc0);
-            for (int k = lane; k < W4; k += 64) dst[k] = i < nl ? srow[k] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+          for (int m = 0; m < R / NW; ++m) {
+            const int i = wave + NW * m;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (i < nl && lane < W4)
+              v = reinterpret_cast<const float4*>(J.img + (size_t)(gr0 + db + i) * J.n + gc0)[lane];
+            st[4 * m] = v.x; st[4 * m + 1] = v.y; st[4 * m + 2] = v.z; st[4 * m + 3] = v.w;
           }
         } else {
-          for (int i = wave; i < R; i += NW) {
-            float* dst = band + i * B::LS + B::PAD;
-            const float* srow = J.img + (size_t)(gr0 + db + i) * J.n + gc0;
-            for (int k = lane; k < W; k += 64) dst[k] = i < nl ? srow[k] : 0.f;
-          }
+#pragma unroll
+          for (int m = 0; m < R / NW; ++m)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+              const int i = wave + NW * m, k = lane + 64 * c;
+              st[4 * m + c] = (i < nl && k < W) ? J.img[(size_t)(gr0 + db + i) * J.n + gc0 + k] : 0.f;
+            }
         }
       } else {
-        // lane -> image row k, each wave stages groups of 4 band columns
+        // lane -> image row k; groups of 4 consecutive band lines per float4
         if (vec4) {
-          for (int k0 = 0; k0 < W; k0 += 64) {
-            const int k = k0 + lane;
-            for (int q = wave; q < R / 4; q += NW) {
-              const int c = db + 4 * q;
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int m = 0; m < R / 16; ++m) {
+              const int k = lane + 64 * c, col = db + 4 * (wave + NW * m);
               float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-              if (k < W && c < D) v = *reinterpret_cast<const float4*>(J.img + (size_t)(gr0 + k) * J.n + gc0 + c);
-              if (k < W) {
-                float* dst = band + 4 * q * B::LS + B::PAD + k;
-                dst[0] = v.x;                // D is a multiple of 4 here, so c < D covers c+3
-                dst[B::LS] = v.y;
-                dst[2 * B::LS] = v.z;
-                dst[3 * B::LS] = v.w;
-              }
+              if (k < W && col < D)   // D is a multiple of 4 here, so col < D covers col + 3
+                v = *reinterpret_cast<const float4*>(J.img + (size_t)(gr0 + k) * J.n + gc0 + col);
+              const int o = 4 * (c * (R / 16) + m);
+              st[o] = v.x; st[o + 1] = v.y; st[o + 2] = v.z; st[o + 3] = v.w;
             }
-          }
         } else {
-          for (int k0 = 0; k0 < W; k0 += 64) {
-            const int k = k0 + lane;
-            if (k >= W) continue;
-            for (int i = wave; i < R; i += NW) {
-              float v = i < nl ? J.img[(size_t)(gr0 + k) * J.n + gc0 + db + i] : 0.f;
-              band[i * B::LS + B::PAD + k] = v;
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int m = 0; m < R / NW; ++m) {
+              const int k = lane + 64 * c, i = wave + NW * m;
+              st[c * (R / NW) + m] = (k < W && i < nl) ? J.img[(size_t)(gr0 + k) * J.n + gc0 + db + i] : 0.f;
             }
-          }
         }
       }
-      __syncthreads();
+    };
+    auto store = [&]() {
+      if (cls == 0) {
+        if (vec4) {
+#pragma unroll
+          for (int m = 0; m < R / NW; ++m) {
+            const int i = wave + NW * m;
+            if (lane < (W >> 2))
+              reinterpret_cast<float4*>(band + i * B::LS + B::PAD)[lane] =
+                  make_float4(st[4 * m], st[4 * m + 1], st[4 * m + 2], st[4 * m + 3]);
+          }
+        } else {
+#pragma unroll
+          for (int m = 0; m < R / NW; ++m)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+              const int i = wave + NW * m, k = lane + 64 * c;
+              if (k < W) band[i * B::LS + B::PAD + k] = st[4 * m + c];
+            }
+        }
+      } else {
+        if (vec4) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int m = 0; m < R / 16; ++m) {
+              const int k = lane + 64 * c, q = wave + NW * m;
+              const int o = 4 * (c * (R / 16) + m);
+              if (k < W) {
+                float* dst = band + 4 * q * B::LS + B::PAD + k;
+                dst[0] = st[o];
+                dst[B::LS] = st[o + 1];
+                dst[2 * B::LS] = st[o + 2];
+                dst[3 * B::LS] = st[o + 3];
+              }
+            }
+        } else {
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int m = 0; m < R / NW; ++m) {
+              const int k = lane + 64 * c, i = wave + NW * m;
+              if (k < W) band[i * B::LS + B::PAD + k] = st[c * (R / NW) + m];
+            }
+        }
+      }
+    };
 
-      // rays of each angle of this class that meet the band (wave-uniform)
-      int jlo[PA], jhi[PA], nch[PA];
+    __syncthreads();
+    for (int i = tid; i < R * B::LS; i += PTHREADS) band[i] = 0.f;
+    constexpr bool prefetch = R == 32;
+    if (prefetch) load(0);
+    for (int db = 0; db < D; db += R) {
+      __syncthreads();
+      if (!prefetch) load(db);
+      store();
+      __syncthreads();
+      if (prefetch && db + R < D) load(db + R);
+
+      // rays of the angles of this class that meet the band, all angles in
+      // one list (wave-uniform bookkeeping, kept in scalar registers)
+      int base[PA], off[PA];
       int tot = 0;
 #pragma unroll
       for (int a = 0; a < PA; ++a) {
-        jlo[a] = 0;
-        jhi[a] = -1;
-        nch[a] = 0;
+        int cnt = 0, jl = 0;
         if (a < na && prm[a].cls == cls) {
           const int bb = prm[a].bbase;
-          int jl = max((int)floor(prm[a].rlo0 + db * prm[a].rsl), max(0, -bb));
-          int jh = min((int)ceil(prm[a].rhi0 + db * prm[a].rsl), min(PACC - 1, J.nb - 1 - bb));
-          jlo[a] = jl;
-          jhi[a] = jh;
-          nch[a] = jh >= jl ? ((jh - jl + 1 + 63) >> 6) : 0;
+          jl = max((int)floor(prm[a].rlo0 + db * prm[a].rsl), max(0, -bb));
+          const int jh = min((int)ceil(prm[a].rhi0 + db * prm[a].rsl), min(PACC - 1, J.nb - 1 - bb));
+          cnt = max(0, jh - jl + 1);
         }
-        tot += nch[a];
+        base[a] = __builtin_amdgcn_readfirstlane(tot);
+        off[a] = __builtin_amdgcn_readfirstlane(jl - tot);
+        tot = __builtin_amdgcn_readfirstlane(tot + cnt);
       }
-      // each wave takes chunks of 64 consecutive rays of one angle
-      for (int ch = wave; ch < tot; ch += NW) {
-        int a = 0, base = 0;
+      // each wave takes chunks of 64 consecutive entries of the list; a lane
+      // finds its angle from the list offsets
+      for (int q0 = wave * 64; q0 < tot; q0 += NW * 64) {
+        const int q = q0 + lane;
+        if (q >= tot) continue;
+        int a = 0, jo = off[0];
 #pragma unroll
-        for (int q = 0; q < PA - 1; ++q) {
-          if (ch >= base + nch[a]) { base += nch[a]; ++a; }
+        for (int t = 1; t < PA; ++t) {
+          const bool ge = q >= base[t];
+          a = ge ? t : a;
+          jo = ge ? off[t] : jo;
         }
-        int ja = 0, jb = -1;
-#pragma unroll
-        for (int q = 0; q < PA; ++q) if (q == a) { ja = jlo[q]; jb = jhi[q]; }
-        const int j = ja + ((ch - base) << 6) + lane;
-        if (j > jb) continue;
+        const int j = q + jo;
         const AngleParam& p = prm[a];
         const float xi = (float)(p.xi0 + db * p.gamma + (double)j * p.beta);
-        const float g = (float)p.gamma;
+        const float g = p.g32;
         float s0 = 0.f, s1 = 0.f;
 #pragma unroll
         for (int i = 0; i < R; ++i) {
