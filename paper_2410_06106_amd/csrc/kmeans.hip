@@ -12,18 +12,24 @@
 // theirs), after which the centres are stably sorted; Lloyd iterations stop
 // when no label changes or after max_iter.
 //
-// Because the label is monotone in the value, every cluster is a run of the
-// sorted values, and the labelling is fixed by k - 1 boundary counts (values
-// at or below each midpoint).  One workgroup owns a segment.  It buckets the
-// values once by value range (a monotone bucket function), keeping exclusive
-// prefix counts and exact int64 prefix sums of the codes per bucket, and
-// regroups the values by bucket (in LDS, or in a global workspace for long
-// segments).  The count and code sum at or below a midpoint are then the prefix
-// of the buckets left of the midpoint's bucket plus that one bucket's share,
-// found by a wave scanning it: a Lloyd iteration costs k - 1 bucket scans
-// instead of a pass over every value, and "no label changed" is "no boundary
-// count changed".  Labels and quantized values are written once at the end.
-// The optional Alg. 3 x-update of the segment is applied on load.
+// For a float32 value a, 2a <= m holds exactly when a <= x(m), the largest
+// float32 whose double does not exceed m / 2, so every comparison with a
+// midpoint is one float32 comparison with its threshold x(m).  Because the
+// label is monotone in the value, every cluster is a run of the sorted values,
+// and the labelling is fixed by k - 1 boundary counts (values at or below each
+// threshold).  One workgroup owns a segment.  It buckets the values once by
+// value range (a monotone bucket function), keeping exclusive prefix counts and
+// exact int64 prefix sums of the codes per bucket, and regroups the values by
+// bucket (in LDS, or in a global workspace for long segments).  The count and
+// code sum at or below a threshold are then the prefix of the buckets left of
+// the threshold's bucket plus that one bucket's share: a Lloyd iteration costs
+// k - 1 bucket scans instead of a pass over every value, and "no label
+// changed" is "no boundary count changed".  For k <= 64 a Lloyd iteration
+// takes one workgroup barrier: the waves scan the buckets of different
+// thresholds in parallel, and each keeps all k centres in its lanes and
+// updates them from the shared counts.  Segments of up to 16384 values stay in
+// registers from the first pass to the last, where labels and quantized values
+// are written.  The optional Alg. 3 x-update of the segment is applied on load.
 #include "common.h"
 
 namespace tomo {
@@ -32,20 +38,25 @@ namespace {
 
 constexpr int KT = 1024;                // threads per workgroup
 constexpr int KWAVES = KT / 64;
-constexpr int KBUCKETS = 2048;          // value-range buckets at most
+constexpr int KVPT = 16;                // values per thread and pass (loads in flight)
+constexpr int KBUCKETS = 4096;          // value-range buckets at most
 constexpr int KPER = KBUCKETS / KT;     // bucket entries per thread in the scan
+static_assert(KT * KVPT == KM_LDS_VALUES, "register-resident segments are the LDS-resident ones");
 
 struct KMShared {
   int start[KBUCKETS + 1];        // bucket counts, then their exclusive prefix (start[B] = n)
   int fill[KBUCKETS];             // values placed per bucket so far
   long long psum[KBUCKETS + 1];   // code sums per bucket, then their exclusive prefix
-  double mid[KM_MAX_K];           // c_j + c_{j+1}
+  float thr[KM_MAX_K];            // thresholds x(c_j + c_{j+1}), increasing
   float cent[KM_MAX_K];           // centres, increasing
   float upd[KM_MAX_K];            // updated centres before sorting
-  int cb[2][KM_MAX_K + 1];        // values at or below midpoint j-1 (label < j), two generations
+  int cb[2][KM_MAX_K + 1];        // values at or below threshold j-1 (label < j), two generations
   long long sb[KM_MAX_K + 1];     // their code sums
-  int wcnt[KWAVES];
+  int cb3[3][65];                 // the same for k <= 64, three generations
+  long long sb3[3][65];
   long long wsum[KWAVES];
+  long long cell[KWAVES];         // per-wave partial code sums of a bucket scan
+  int wcnt[KWAVES];
   float red[2 * KWAVES];
   int redb[KWAVES];
 };
@@ -68,6 +79,16 @@ __device__ __forceinline__ float prev_float(float x) {
   if (x == 0.f) return __uint_as_float(0x80000001u);
   const unsigned u = __float_as_uint(x);
   return __uint_as_float(x > 0.f ? u - 1u : u + 1u);
+}
+
+// x(m): the largest float32 whose double is <= m / 2 (m / 2 is exact), so that
+// a <= x(m) exactly when 2a <= m for every float32 a.  Midpoints lie between
+// the smallest and largest value, so x(m) is finite.
+__device__ __forceinline__ float threshold(double m) {
+  const double h = 0.5 * m;
+  float x = (float)h;
+  if ((double)x > h) x = prev_float(x);
+  return x;
 }
 
 // Monotone (non-decreasing) bucket index of a value a >= lo: every rounding
@@ -123,43 +144,46 @@ __device__ void bucket_scan(KMShared& sh, int B) {
   __syncthreads();
 }
 
-// Count and code sum of the values with 2a <= m, for one wave (every lane
-// gets the result).  Buckets left of the bucket of x = the largest float32 with
-// 2x <= m hold only such values, buckets right of it none.
+// Count and code sum of the values a <= x, by one wave (every lane gets the
+// result): the buckets left of x's bucket plus the qualifying values of that
+// bucket.  The count comes from ballots, the sum from LDS atomics on *cell.
 template <class VP>
-__device__ __forceinline__ void at_or_below(const KMShared& sh, VP V, double m, const Buckets& bk, float lo,
-                                            float hi, int n, long long tot, int S, int& cnt, long long& sum) {
-  const double h = 0.5 * m;            // exact
-  if (h < (double)lo) { cnt = 0; sum = 0; return; }
-  if (h >= (double)hi) { cnt = n; sum = tot; return; }
-  float x = (float)h;
-  if ((double)x > h) x = prev_float(x);
+__device__ __forceinline__ void at_or_below(const KMShared& sh, VP V, float x, const Buckets& bk, float lo,
+                                            float hi, int n, long long tot, int S, long long* cell, int& cnt,
+                                            long long& sum) {
+  if (x < lo) { cnt = 0; sum = 0; return; }
+  if (x >= hi) { cnt = n; sum = tot; return; }
   const int b = bk.of(x);
   const int p0 = sh.start[b], p1 = sh.start[b + 1];
+  const int l = threadIdx.x & 63;
+  if (l == 0) *cell = 0;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
   int c = 0;
   long long s = 0;
-  for (int p = p0 + (int)(threadIdx.x & 63); p < p1; p += 64) {
-    const float a = V[p];
-    if (2.0 * (double)a <= m) { ++c; s += km_fixed(a, S); }
+  for (int pw = p0; pw < p1; pw += 64) {     // uniform trip count: every lane sees every ballot
+    const int p = pw + l;
+    const float a = p < p1 ? V[p] : 0.f;
+    const bool in = p < p1 && a <= x;
+    c += __popcll(__ballot(in));
+    if (in) s += km_fixed(a, S);
   }
-  for (int o = 32; o > 0; o >>= 1) {
-    c += __shfl_xor(c, o, 64);
-    s += __shfl_xor(s, o, 64);
-  }
+  if (s != 0) atomicAdd((unsigned long long*)cell, (unsigned long long)s);
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
   cnt = p0 + c;
-  sum = sh.psum[b] + s;
+  sum = sh.psum[b] + *cell;
 }
 
 }  // namespace
 
-// One workgroup per segment.  VLDS: the bucket-ordered values fit in LDS
-// (n <= KM_LDS_VALUES); otherwise they go to work + segment * work_stride.
-template <bool VLDS>
+// One workgroup per segment.  REG: the segment fits the registers (n <=
+// KM_LDS_VALUES) and its bucket-ordered copy fits LDS; otherwise the values
+// are streamed in every pass and the copy goes to work + segment * work_stride.
+template <bool REG>
 __global__ __launch_bounds__(KT) void k_kmeans(const KMJob* jobs, KMJob single, int k, int max_iter, int e2,
                                                float* work, long long work_stride) {
 #pragma clang fp contract(off)
   __shared__ KMShared sh;
-  __shared__ float vlds[VLDS ? KM_LDS_VALUES : 1];
+  __shared__ float vlds[REG ? KM_LDS_VALUES : 1];
   const int seg = blockIdx.x;
   const KMJob J = jobs ? jobs[seg] : single;
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
@@ -179,18 +203,68 @@ __global__ __launch_bounds__(KT) void k_kmeans(const KMJob* jobs, KMJob single, 
     return;
   }
 
-  // pass 1: x-update, range, finiteness
+  // every value once, KVPT per thread at a time: from registers (REG) or
+  // loaded from the segment after the x-update
+  float v[REG ? KVPT : 1];
+  auto each = [&](auto&& body) {
+    if constexpr (REG) {
+#pragma unroll
+      for (int e = 0; e < KVPT; ++e) {
+        const int i = tid + e * KT;
+        if (i < n) body(i, v[e]);
+      }
+    } else {
+      for (long long base = 0; base < n; base += (long long)KT * KVPT) {
+        float a[KVPT];
+#pragma unroll
+        for (int e = 0; e < KVPT; ++e) {   // clamped, unconditional loads: all in flight at once
+          const long long i = base + tid + (long long)e * KT;
+          a[e] = vals[i < n ? i : n - 1];
+        }
+#pragma unroll
+        for (int e = 0; e < KVPT; ++e) {
+          const long long i = base + tid + (long long)e * KT;
+          if (i < n) body((int)i, a[e]);
+        }
+      }
+    }
+  };
+
+  // pass 1: x-update, range, finiteness (all loads of a chunk issued first)
   float lo = INFINITY, hi = -INFINITY;
   int bad = 0;
-  for (int i = tid; i < n; i += KT) {
-    float a = src[i];
-    if (do_x) {
-      a = km_xupdate(a, uu[i], ll[i], J.rho, irho, J.eta2, e2);
-      xo[i] = a;
+  for (long long base = 0; base < n; base += (long long)KT * KVPT) {
+    // clamped, unconditional loads (all in flight at once); a clamped slot
+    // repeats the last value, which leaves the range and the flag unchanged
+    float a[KVPT];
+#pragma unroll
+    for (int e = 0; e < KVPT; ++e) {
+      const long long i = base + tid + (long long)e * KT;
+      a[e] = src[i < n ? i : n - 1];
     }
-    bad |= !isfinite(a);
-    lo = fminf(lo, a);
-    hi = fmaxf(hi, a);
+    if (do_x) {
+      float uv[KVPT], lv[KVPT];
+#pragma unroll
+      for (int e = 0; e < KVPT; ++e) {
+        const long long i = base + tid + (long long)e * KT;
+        uv[e] = uu[i < n ? i : n - 1];
+        lv[e] = ll[i < n ? i : n - 1];
+      }
+#pragma unroll
+      for (int e = 0; e < KVPT; ++e) {
+        const long long i = base + tid + (long long)e * KT;
+        a[e] = km_xupdate(a[e], uv[e], lv[e], J.rho, irho, J.eta2, e2);
+        if (i < n) xo[i] = a[e];
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < KVPT; ++e) {
+      bad |= !isfinite(a[e]);
+      lo = fminf(lo, a[e]);
+      hi = fmaxf(hi, a[e]);
+      if constexpr (REG) v[e] = a[e];
+    }
+    if constexpr (REG) break;   // n <= KT * KVPT: one chunk
   }
   for (int o = 32; o > 0; o >>= 1) {
     lo = fminf(lo, __shfl_xor(lo, o, 64));
@@ -209,10 +283,11 @@ __global__ __launch_bounds__(KT) void k_kmeans(const KMJob* jobs, KMJob single, 
   }
   if (bad || hi == lo) {
     // constant segment: one cluster at lo; non-finite input: flagged
-    for (int i = tid; i < n; i += KT) {
+    const bool copy = J.a_hat && J.a_hat != (do_x ? J.x : J.src);
+    each([&](int i, float a) {
       if (J.labels) labels[i] = 0;
-      if (J.a_hat && J.a_hat != (do_x ? J.x : J.src)) ahat[i] = vals[i];
-    }
+      if (copy) ahat[i] = a;
+    });
     if (J.cent) for (int j = tid; j < k; j += KT) J.cent[j] = bad ? 0.f : lo;
     if (J.iters && tid == 0) *J.iters = bad ? -1 : 0;
     return;
@@ -232,26 +307,24 @@ __global__ __launch_bounds__(KT) void k_kmeans(const KMJob* jobs, KMJob single, 
     sh.cent[tid] = (float)(lo64 + t);
   }
   __syncthreads();
-  for (int i = tid; i < n; i += KT) {
-    const float a = vals[i];
+  each([&](int, float a) {
     const int b = bk.of(a);
     atomicAdd(&sh.start[b], 1);
     atomicAdd((unsigned long long*)&sh.psum[b], (unsigned long long)(long long)km_fixed(a, S));
-  }
+  });
   __syncthreads();
   bucket_scan(sh, B);
   const long long tot = sh.psum[B];
 
   // pass 3: values regrouped by bucket
-  float* const wv = VLDS ? nullptr : work + (size_t)seg * work_stride;
-  for (int i = tid; i < n; i += KT) {
-    const float a = vals[i];
+  float* const wv = REG ? nullptr : work + (size_t)seg * work_stride;
+  each([&](int, float a) {
     const int b = bk.of(a);
     const int p = sh.start[b] + atomicAdd(&sh.fill[b], 1);
-    if constexpr (VLDS) vlds[p] = a;
+    if constexpr (REG) vlds[p] = a;
     else gptr(wv)[p] = a;
-  }
-  if (tid < k - 1) sh.mid[tid] = (double)sh.cent[tid] + (double)sh.cent[tid + 1];
+  });
+  if (tid < k - 1) sh.thr[tid] = threshold((double)sh.cent[tid] + (double)sh.cent[tid + 1]);
   if (tid == 0) {
     sh.cb[0][0] = sh.cb[1][0] = 0;
     sh.cb[0][k] = sh.cb[1][k] = n;
@@ -260,59 +333,130 @@ __global__ __launch_bounds__(KT) void k_kmeans(const KMJob* jobs, KMJob single, 
   }
   __syncthreads();
 
-  auto boundaries = [&](int gen) {
-    for (int j = w; j < k - 1; j += KWAVES) {
-      int c;
-      long long s;
-      if constexpr (VLDS) at_or_below(sh, vlds, sh.mid[j], bk, lo, hi, n, tot, S, c, s);
-      else at_or_below(sh, gptr((const float*)wv), sh.mid[j], bk, lo, hi, n, tot, S, c, s);
-      if (l == 0) { sh.cb[gen][j + 1] = c; sh.sb[j + 1] = s; }
-    }
+  auto scan_bucket = [&](float x, int& c, long long& s) {
+    if constexpr (REG) at_or_below(sh, vlds, x, bk, lo, hi, n, tot, S, &sh.cell[w], c, s);
+    else at_or_below(sh, gptr((const float*)wv), x, bk, lo, hi, n, tot, S, &sh.cell[w], c, s);
   };
 
-  boundaries(0);
-  __syncthreads();
-  int cur = 0, it = 0;
-  for (int t = 1; t <= max_iter; ++t) {
-    if (tid < k) {
-      const int c = sh.cb[cur][tid + 1] - sh.cb[cur][tid];
-      float cj = sh.cent[tid];
-      if (c > 0) cj = (float)(ldexp((double)(sh.sb[tid + 1] - sh.sb[tid]), -S) / (double)c);
-      sh.upd[tid] = cj;
-    }
-    __syncthreads();
-    if (tid < k) {                     // stable rank sort of the k centres
-      const float cj = sh.upd[tid];
+  int it = 0;
+  if (k <= 64) {
+    // Lloyd iterations with one workgroup barrier each: every wave holds the
+    // k centres in its lanes and updates them redundantly from the shared
+    // boundary counts; wave w scans the buckets of thresholds w, w + 16, ...
+    // The counts rotate through three generations, so the one written in an
+    // iteration was last read two barriers earlier.
+    float cj = l < k ? sh.cent[l] : 0.f;
+    int gen = 0;
+    for (int t = 0;; ++t) {
+      for (int j = w; j < k - 1; j += KWAVES) {
+        const float cl = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cj), j));
+        const float cr = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cj), j + 1));
+        const float x = threshold((double)cl + (double)cr);
+        int c;
+        long long sm;
+        scan_bucket(x, c, sm);
+        if (l == 0) {
+          sh.cb3[gen][j + 1] = c;
+          sh.sb3[gen][j + 1] = sm;
+          sh.thr[j] = x;
+        }
+      }
+      if (tid == 0) {
+        sh.cb3[gen][0] = 0;
+        sh.cb3[gen][k] = n;
+        sh.sb3[gen][0] = 0;
+        sh.sb3[gen][k] = tot;
+      }
+      __syncthreads();
+      if (t > 0) {
+        it = t;
+        const int prev = gen == 0 ? 2 : gen - 1;
+        const bool moved = __ballot(l + 1 < k && sh.cb3[gen][l + 1] != sh.cb3[prev][l + 1]) != 0;
+        if (!moved) break;
+      }
+      if (t == max_iter) break;
+      // centres of the current labels, then their stable ranks (broadcast one
+      // lane at a time); every lane picks the centre ranked l
+      const int c = l < k ? sh.cb3[gen][l + 1] - sh.cb3[gen][l] : 0;
+      float u = cj;
+      if (c > 0) u = (float)(ldexp((double)(sh.sb3[gen][l + 1] - sh.sb3[gen][l]), -S) / (double)c);
       int r = 0;
       for (int i = 0; i < k; ++i) {
-        const float ci = sh.upd[i];
-        r += (ci < cj) || (ci == cj && i < tid);
+        const float ui = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(u), i));
+        r += (ui < u) || (ui == u && i < l);
       }
-      sh.cent[r] = cj;
+      for (int i = 0; i < k; ++i) {
+        const float ui = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(u), i));
+        cj = __builtin_amdgcn_readlane(r, i) == l ? ui : cj;
+      }
+      gen = gen == 2 ? 0 : gen + 1;
     }
+    if (tid < k) sh.cent[tid] = cj;
     __syncthreads();
-    if (tid < k - 1) sh.mid[tid] = (double)sh.cent[tid] + (double)sh.cent[tid + 1];
+  } else {
+    auto boundaries = [&](int gen) {
+      for (int j = w; j < k - 1; j += KWAVES) {
+        int c;
+        long long s;
+        scan_bucket(sh.thr[j], c, s);
+        if (l == 0) { sh.cb[gen][j + 1] = c; sh.sb[j + 1] = s; }
+      }
+    };
+    boundaries(0);
     __syncthreads();
-    boundaries(cur ^ 1);
-    __syncthreads();
-    it = t;
-    const int moved = tid <= k && sh.cb[cur ^ 1][tid] != sh.cb[cur][tid];
-    cur ^= 1;
-    if (!__syncthreads_or(moved)) break;
+    int cur = 0;
+    for (int t = 1; t <= max_iter; ++t) {
+      if (tid < k) {
+        const int c = sh.cb[cur][tid + 1] - sh.cb[cur][tid];
+        float cj = sh.cent[tid];
+        if (c > 0) cj = (float)(ldexp((double)(sh.sb[tid + 1] - sh.sb[tid]), -S) / (double)c);
+        sh.upd[tid] = cj;
+      }
+      __syncthreads();
+      if (tid < k) {                     // stable rank sort of the k centres
+        const float cj = sh.upd[tid];
+        int r = 0;
+        for (int i = 0; i < k; ++i) {
+          const float ci = sh.upd[i];
+          r += (ci < cj) || (ci == cj && i < tid);
+        }
+        sh.cent[r] = cj;
+      }
+      __syncthreads();
+      if (tid < k - 1) sh.thr[tid] = threshold((double)sh.cent[tid] + (double)sh.cent[tid + 1]);
+      __syncthreads();
+      boundaries(cur ^ 1);
+      __syncthreads();
+      it = t;
+      const int moved = tid <= k && sh.cb[cur ^ 1][tid] != sh.cb[cur][tid];
+      cur ^= 1;
+      if (!__syncthreads_or(moved)) break;
+    }
   }
 
-  // labels and quantized values: the count of midpoints below 2a
-  for (int i = tid; i < n; i += KT) {
-    const float a = vals[i];
-    const double t2 = 2.0 * (double)a;
-    int p = 0, len = k - 1;
-    while (len > 0) {
-      const int half = len >> 1;
-      if (sh.mid[p + half] < t2) { p += half + 1; len -= half + 1; }
-      else len = half;
-    }
-    if (J.labels) labels[i] = (uint8_t)p;
-    if (J.a_hat) ahat[i] = sh.cent[p];
+  // labels and quantized values: the number of thresholds below the value
+  if (k <= 16) {
+    float th[15];
+#pragma unroll
+    for (int j = 0; j < 15; ++j) th[j] = j < k - 1 ? sh.thr[j] : INFINITY;
+    each([&](int i, float a) {
+      int p = 0;
+#pragma unroll
+      for (int j = 0; j < 15; ++j) p += th[j] < a ? 1 : 0;
+      if (J.labels) labels[i] = (uint8_t)p;
+      if (J.a_hat) ahat[i] = sh.cent[p];
+    });
+  } else {
+    each([&](int i, float a) {
+      int p = 0, len = k - 1;
+      while (len > 0) {
+        const int half = len >> 1;
+        if (sh.thr[p + half] < a) { p += half + 1; len -= half + 1; }
+        else len = half;
+      }
+      if (J.labels) labels[i] = (uint8_t)p;
+      if (J.a_hat) ahat[i] = sh.cent[p];
+    });
   }
   if (J.cent) for (int j = tid; j < k; j += KT) J.cent[j] = sh.cent[j];
   if (J.iters && tid == 0) *J.iters = it;
