@@ -31,6 +31,8 @@ sys.path.insert(0, ROOT)
 ALGO_FLOPS_PER_UPDATE = 4.0        # the two multiply-adds of the 2-tap interpolation
 PEAK_FP32_TFLOPS = 157.3           # MI355X vector FP32 (published)
 PEAK_HBM_GBS = 8000.0
+PHASE_KERNELS = {"project": "projection phase: k_project + k_project_reduce",
+                 "backproject": "backprojection phase: k_backproject"}
 KERNEL_SOURCES = ("paper_2410_06106_amd/csrc/project.hip", "paper_2410_06106_amd/csrc/backproject.hip",
                   "paper_2410_06106_amd/csrc/common.h")
 
@@ -128,18 +130,28 @@ def main():
 
     if args.profile_kernels:
         reps = 5
+        phase_us = {}
         for phase in (0, 1):
+            T.admm_local_phase(ctx, run.nodes, phase)      # builds the batched plan
+        torch.cuda.synchronize()
+        for phase, name in ((0, "project"), (1, "backproject")):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
             for _ in range(reps):
                 T.admm_local_phase(ctx, run.nodes, phase)
+            e1.record()
+            torch.cuda.synchronize()
+            phase_us[name] = e0.elapsed_time(e1) / reps * 1e3
         copy_bytes = 1 << 28
         a = torch.empty(copy_bytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
         b = torch.empty_like(a)
         for _ in range(reps):
             b.copy_(a)
         torch.cuda.synchronize()
-        print(json.dumps({"profile_kernels": {"project_launches": reps, "backproject_launches": reps,
+        print(json.dumps({"profile_kernels": {"project_launches": reps + 1, "backproject_launches": reps + 1,
                                               "copy_launches": reps, "copy_bytes": copy_bytes,
-                                              "updates_per_launch": w.n_angles * w.n * w.n}}), flush=True)
+                                              "updates_per_launch": w.n_angles * w.n * w.n,
+                                              "event_us_per_phase": phase_us}}), flush=True)
         return
 
     # --- equal-RMSE check: plain per-node loop vs batched graph, same iterations
@@ -239,7 +251,7 @@ def main():
         "kmeans_lloyd_iters_last_step": {"mean": float(lloyd.mean()), "max": int(lloyd.max()),
                                           "min": int(lloyd.min())},
         "kernels_us": {k: v * 1e3 for k, v in kern.items()},
-        "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+        "roofline": {"bound": "alu", "kernel": PHASE_KERNELS[dom], "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
                      "traffic": traffic,
                      "algorithmic": f"{ALGO_FLOPS_PER_UPDATE:g} flop per ray-voxel update x "
