@@ -1,19 +1,29 @@
 """Benchmark of the decentralized-ADMM hot path on one MI355X.
 
-One step = one outer iteration of Alg. 4 over every node of the 512 x 512,
-720-angle, 725-bin, 16-node workload (contiguous angle blocks, Poisson data at
-1e5 photons, SEG x-update, K-means with 8 levels): E1 = 5 local steps (Joseph
-projection, residual, matched backprojection, u-step) per node, the segment
-x-update with K-means exchange, and the dual update.  The iteration is launched
-in its batched form and replayed from a HIP graph; inputs are resident on the
-device before timing starts.
+One step = one outer iteration of Alg. 4 over every node of every slice of the
+workload: E1 = 5 local steps (Joseph projection, residual, matched
+backprojection, u-step) per node, the segment x-update with the quantized
+exchange, and the dual update.  The iteration is launched in its batched form
+(one launch per kernel for all slices and nodes) and replayed from a HIP graph;
+inputs are resident on the device before timing starts.  Workloads:
 
-value = (ray-voxel updates in P + in P^T) per second = 2 E1 K N^2 / step time.
-Also reported: ADMM iterations/s of the batched graph and of the plain
-per-node launch loop, and their RMSE after the same iterations (equal by
-construction: a node's work decomposes identically in both forms).
+* ``single`` (default): 512 x 512, 720 angles, 725 bins, 16 nodes with
+  contiguous angle blocks, Poisson data at 1e5 photons, K-means with 8 levels;
+* ``batch``: 256 slices of sizes drawn from {128, ..., 1024} (angles 1.5 N,
+  bins ceil(1.414 N)), 2 to 16 interleaved nodes each, K-means with 16 levels;
+* ``large``: 2048 x 2048 (50 ellipses + texture), 1800 angles, 2897 bins, 64
+  contiguous nodes, 8x8 DCT exchange at quality 50.
 
-    python bench.py [--gpus 1] [--steps 100] [--warmup 3] [--no-cpu-baseline]
+value = (ray-voxel updates in P + in P^T) per second = sum over slices of
+2 E1 K N^2 / step time.  Also reported: ADMM iterations/s (summed over slices)
+of the batched graph and of the plain per-slice, per-node launch loop, and the
+RMSE of every slice after the same iterations in both forms (identical by
+construction: a node's work decomposes the same way alone or batched); the
+projector tiles picked by the autotuner; per-phase durations, the ALU roofline
+of the projection phase and its HBM traffic.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload single|batch|large]
+                    [--no-cpu-baseline] [--no-autotune] [--profile-kernels]
 """
 from __future__ import annotations
 
@@ -35,6 +45,8 @@ PHASE_KERNELS = {"project": "projection phase: k_project + k_project_reduce",
                  "backproject": "backprojection phase: k_backproject"}
 KERNEL_SOURCES = ("paper_2410_06106_amd/csrc/project.hip", "paper_2410_06106_amd/csrc/backproject.hip",
                   "paper_2410_06106_amd/csrc/common.h")
+DEFAULT_STEPS = {"single": 100, "batch": 5, "large": 10}
+EQUAL_RMSE_STEPS = {"single": 5, "batch": 2, "large": 2}
 
 
 def _source_sha(paths):
@@ -45,53 +57,112 @@ def _source_sha(paths):
     return h.hexdigest()[:16]
 
 
-def _traffic(kernel: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_single512.json")
-    if not os.path.exists(path):
+def _traffic(kernel: str, workload: str, tiles):
+    """HBM bytes per launch from the committed rocprofv3 counter record of this
+    workload, if it was taken on the current kernel sources with the same
+    projector tiles; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}512.json") if workload == "single" else None
+    if not path or not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
     if rec.get("source_sha") != _source_sha(KERNEL_SOURCES):
         return None
+    if rec.get("tiles") and tiles and rec["tiles"] != tiles:
+        return None
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(w, sample_nodes=8):
+def cpu_baseline(slices_info, sample_nodes):
     """The oracle's Alg. 2 local update (E1 steps of P and P^T) on a sample of
-    the workload's nodes, timed on the host; returns ray-voxel updates/s."""
+    nodes, timed on the host; returns ray-voxel updates/s and seconds."""
     import numpy as np
 
     import synthdata
     from oracle import admm as oadmm
     from oracle import joseph
 
-    th = synthdata.angles(w.n_angles)
-    parts = synthdata.partition_angles(w.n_angles, w.n_nodes, w.split)
-    truth = synthdata.phantom(w)
     rng = np.random.default_rng(0)
-    n = w.n
     upd = 0
     t0 = time.perf_counter()
-    for m in range(sample_nodes):
-        d = joseph.project(truth, th[parts[m]], w.n_bins) if m == 0 else d0
-        d0 = d
-        u = rng.random((n, n))
-        oadmm.local_update(u, np.zeros((n, n)), np.zeros((n, n)), d, th[parts[m]], 1.0, 1e-5, w.inner_iters)
-        upd += 2 * w.inner_iters * len(parts[m]) * n * n
+    for w, si, m in sample_nodes:
+        th = synthdata.angles(w.n_angles)
+        part = synthdata.partition_angles(w.n_angles, w.n_nodes, w.split)[m]
+        truth = synthdata.phantom(w, si)
+        d = joseph.project(truth, th[part], w.n_bins)
+        u = rng.random((w.n, w.n))
+        oadmm.local_update(u, np.zeros((w.n, w.n)), np.zeros((w.n, w.n)), d, th[part], 1.0, 1e-5, w.inner_iters)
+        upd += 2 * w.inner_iters * len(part) * w.n * w.n
     dt = time.perf_counter() - t0
     return upd / dt, dt
+
+
+def build(which, ctx, A, T, synthdata, log):
+    """Slices, quantizer and description of a workload."""
+    import torch
+
+    if which == "single":
+        w = synthdata.WORKLOADS["single"]
+        log(f"setup: {w.n}^2, {w.n_angles} angles, {w.n_bins} bins, {w.n_nodes} nodes")
+        s = A.make_slice(ctx, w)
+        s.eta1 = A.step_size(ctx, s, w.rho, 0.1)
+        q = T.tomo_quant(T.TOMO_QUANT_KMEANS, w.levels, 30, 50)
+        desc = ("single-GPU plain method: 512x512 random-ellipse phantom (20 ellipses), 720 angles, 725 bins, "
+                "Poisson 1e5, 16 nodes contiguous, SEG x-update, K-means 8 levels, E1=5, E2=10, rho=1")
+        cfg = {"n": w.n, "angles": w.n_angles, "bins": w.n_bins, "nodes": w.n_nodes}
+        sample = [(w, 0, m) for m in range(8)]
+        sample_desc = f"nodes 0-7 of 16 (512^2, 45 angles each)"
+        return [s], [w], q, desc, cfg, sample, sample_desc
+    if which == "large":
+        w = synthdata.WORKLOADS["large"]
+        log(f"setup: {w.n}^2, {w.n_angles} angles, {w.n_bins} bins, {w.n_nodes} nodes")
+        s = A.make_slice(ctx, w)
+        # contiguous angle blocks: the operator norm varies by node; the max over
+        # 8 nodes spread over the angle range, 20 power iterations each
+        L = max(A.operator_norm(ctx, s.angles[m], s.n, s.n_bins, iters=20) for m in range(0, w.n_nodes, 8))
+        s.eta1 = 0.1 / (L + w.rho)
+        q = T.tomo_quant(T.TOMO_QUANT_DCT, 0, 0, 50)
+        desc = ("large: 2048x2048 random-ellipse phantom (50 ellipses + texture 0.02), 1800 angles, 2897 bins, "
+                "Gaussian 1%, 64 nodes contiguous, SEG x-update, 8x8 DCT exchange at quality 50, E1=5, E2=10, rho=1")
+        cfg = {"n": w.n, "angles": w.n_angles, "bins": w.n_bins, "nodes": w.n_nodes, "dct_quality": 50}
+        sample = [(w, 0, 0)]
+        sample_desc = "node 0 of 64 (2048^2, 29 angles)"
+        return [s], [w], q, desc, cfg, sample, sample_desc
+    if which == "batch":
+        ws = synthdata.batch_slices(256)
+        log(f"setup: 256 slices, {sum(w.n_nodes for w in ws)} nodes")
+        slices = []
+        for si, w in enumerate(ws):
+            s = A.make_slice(ctx, w, slice_idx=si)
+            # interleaved angles: every node of a slice has nearly the same
+            # operator norm; node 0, 20 power iterations
+            L = A.operator_norm(ctx, s.angles[0], s.n, s.n_bins, iters=20)
+            s.eta1 = 0.1 / (L + w.rho)
+            slices.append(s)
+        torch.cuda.synchronize()
+        q = T.tomo_quant(T.TOMO_QUANT_KMEANS, 16, 30, 50)
+        desc = ("batch: 256 slices, N uniform over {128,256,384,512,768,1024}, 1.5N angles, ceil(1.414N) bins, "
+                "2/4/8/16 interleaved nodes per slice (seed 4000), Gaussian 1%, SEG x-update, K-means 16 levels, "
+                "E1=5, E2=10, rho=1")
+        cfg = {"slices": len(ws), "nodes": sum(w.n_nodes for w in ws),
+               "sizes": sorted({w.n for w in ws}), "node_counts": sorted({w.n_nodes for w in ws})}
+        w0 = ws[0]
+        sample = [(w0, 0, 0), (w0, 0, 1)]
+        sample_desc = f"nodes 0-1 of slice 0 ({w0.n}^2, {w0.n_nodes} nodes, {w0.n_angles // w0.n_nodes} angles each)"
+        return slices, ws, q, desc, cfg, sample, sample_desc
+    raise SystemExit(f"unknown workload {which}")
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--plain-steps", type=int, default=5)
+    ap.add_argument("--workload", default="single", choices=("single", "batch", "large"))
+    ap.add_argument("--plain-steps", type=int, default=None)
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only launch the projector and backprojector of the workload a few times, and a "
@@ -101,12 +172,15 @@ def main():
         print("bench.py measures one GPU: every node of the workload runs on one device "
               "(no multi-GPU path is built); run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    steps = args.steps if args.steps is not None else DEFAULT_STEPS[args.workload]
+    n_eq = args.plain_steps if args.plain_steps is not None else EQUAL_RMSE_STEPS[args.workload]
 
     import numpy as np
     import torch
 
     import synthdata
     from paper_2410_06106_amd import admm as A
+    from paper_2410_06106_amd import autotune
     from paper_2410_06106_amd import tomoadmm as T
 
     def log(msg):
@@ -115,18 +189,26 @@ def main():
 
     torch.cuda.set_device(0)
     ctx = T.Context(0)
-    w = synthdata.WORKLOADS["single"]
-    log(f"setup: {w.n}^2, {w.n_angles} angles, {w.n_bins} bins, {w.n_nodes} nodes")
-    s = A.make_slice(ctx, w)
-    rho, c_seg = w.rho, 0.1
-    s.eta1 = A.step_size(ctx, s, rho, c_seg)
-    q = T.tomo_quant(T.TOMO_QUANT_KMEANS, w.levels, 30, 50)
-    km_iters = torch.zeros((w.n_nodes, 1), dtype=torch.int32, device="cuda")
-    km_cent = torch.zeros((w.n_nodes, w.levels), dtype=torch.float32, device="cuda")
-    msgs = T.make_msgs([dict(iters=km_iters[m], centroids=km_cent[m]) for m in range(w.n_nodes)])
-    run = A.DADMM(ctx, [s], rho=rho, eta2=w.eta2, e1=w.inner_iters, e2=w.x_iters,
-                  mode=T.TOMO_XUPDATE_SEGMENT, quant=q, msgs=msgs)
-    updates_per_step = 2 * w.inner_iters * w.n_angles * w.n * w.n
+    t_setup = time.perf_counter()
+    slices, ws, q, desc, cfg, sample, sample_desc = build(args.workload, ctx, A, T, synthdata, log)
+    n_slices = len(slices)
+    msgs = None
+    km_iters = None
+    if q.kind == T.TOMO_QUANT_KMEANS:
+        n_nodes = sum(len(s.d) for s in slices)
+        km_iters = torch.zeros((n_nodes, 1), dtype=torch.int32, device="cuda")
+        msgs = T.make_msgs([dict(iters=km_iters[i]) for i in range(n_nodes)])
+    run = A.DADMM(ctx, slices, rho=1.0, eta2=0.2, e1=5, e2=10, mode=T.TOMO_XUPDATE_SEGMENT, quant=q, msgs=msgs)
+    updates_per_step = sum(2 * w.inner_iters * w.n_angles * w.n * w.n for w in ws)
+    upd_per_launch = sum(w.n_angles * w.n * w.n for w in ws)
+    tiles = None
+    if not args.no_autotune:
+        choice = autotune.tune(ctx, run.nodes)
+        tiles = {"band": choice["band"], "job_wgs": choice["job_wgs"]}
+        log(f"autotune: band {choice['band']}, {choice['job_wgs']} workgroups per node "
+            f"({choice['us']:.1f} us per projection phase; tried {len(choice['tried'])})")
+    setup_s = time.perf_counter() - t_setup
+    log(f"setup done in {setup_s:.1f} s")
 
     if args.profile_kernels:
         reps = 5
@@ -148,37 +230,41 @@ def main():
         for _ in range(reps):
             b.copy_(a)
         torch.cuda.synchronize()
-        print(json.dumps({"profile_kernels": {"project_launches": reps + 1, "backproject_launches": reps + 1,
-                                              "copy_launches": reps, "copy_bytes": copy_bytes,
-                                              "updates_per_launch": w.n_angles * w.n * w.n,
-                                              "event_us_per_phase": phase_us}}), flush=True)
+        print(json.dumps({"profile_kernels": {"workload": args.workload, "project_launches": reps + 1,
+                                              "backproject_launches": reps + 1, "copy_launches": reps,
+                                              "copy_bytes": copy_bytes, "updates_per_launch": upd_per_launch,
+                                              "tiles": tiles, "event_us_per_phase": phase_us}}), flush=True)
         return
 
-    # --- equal-RMSE check: plain per-node loop vs batched graph, same iterations
-    n_eq = args.plain_steps
-    s.zero()
+    def zero_all():
+        for s in slices:
+            s.zero()
+
+    # --- equal-RMSE check: plain per-slice, per-node loop vs batched graph, same iterations
+    zero_all()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(n_eq):
         run.step_plain()
     torch.cuda.synchronize()
     plain_s = (time.perf_counter() - t0) / n_eq
-    rmse_plain = run.rmse()
-    x_plain = s.x.clone()
-    s.zero()
+    rmse_plain = [run.rmse(i) for i in range(n_slices)]
+    x_plain = [s.x.clone() for s in slices]
+    zero_all()
     for _ in range(args.warmup):
         run.step()                       # builds the batched plans
-    s.zero()
+    zero_all()
     torch.cuda.synchronize()
     graph = run.capture(1)
-    s.zero()
+    zero_all()
     for _ in range(n_eq):
         graph.replay()
     torch.cuda.synchronize()
-    rmse_batched = run.rmse()
-    identical = bool(torch.equal(x_plain, s.x))
-    log(f"plain loop {1.0 / plain_s:.1f} it/s, rmse plain {rmse_plain:.6g} batched {rmse_batched:.6g} "
-        f"identical={identical}")
+    rmse_batched = [run.rmse(i) for i in range(n_slices)]
+    identical = all(bool(torch.equal(xp, s.x)) for xp, s in zip(x_plain, slices))
+    del x_plain
+    log(f"plain loop {n_slices / plain_s:.1f} slice-iterations/s, rmse[0] plain {rmse_plain[0]:.6g} "
+        f"batched {rmse_batched[0]:.6g} identical={identical}")
 
     # --- timed region: K replays of the one-iteration graph
     for _ in range(args.warmup):
@@ -187,19 +273,18 @@ def main():
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         graph.replay()
     ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     gpu_ms = ev0.elapsed_time(ev1)
-    ms_per_step = max(gpu_ms, wall * 1e3) / args.steps
+    ms_per_step = max(gpu_ms, wall * 1e3) / steps
     value = updates_per_step / (ms_per_step * 1e-3)
-    rmse_final = run.rmse()
-    lloyd = km_iters.cpu().numpy().reshape(-1)
-    log(f"batched graph: {ms_per_step:.3f} ms/iteration, {value:.4g} updates/s, rmse {rmse_final:.6g}")
+    rmse_final = [run.rmse(i) for i in range(n_slices)]
+    log(f"batched graph: {ms_per_step:.3f} ms/iteration, {value:.4g} updates/s, rmse[0] {rmse_final[0]:.6g}")
 
-    # --- dominant kernels: average launch duration with HIP events on the launch stream
+    # --- local-update phases: average duration with HIP events on the launch stream
     kern = {}
     for phase, name in ((0, "project"), (1, "backproject")):
         T.admm_local_phase(ctx, run.nodes, phase)
@@ -211,28 +296,31 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         kern[name] = e0.elapsed_time(e1) / args.kernel_reps
-    upd_per_launch = w.n_angles * w.n * w.n
     dom = max(kern, key=kern.get)
     dur_s = kern[dom] * 1e-3
     achieved = ALGO_FLOPS_PER_UPDATE * upd_per_launch / dur_s / 1e12
-    traffic = _traffic(dom)
-    log(f"kernels: " + ", ".join(f"{k} {v * 1e3:.1f} us ({upd_per_launch / (v * 1e-3):.3g} upd/s)"
-                                  for k, v in kern.items()))
+    traffic = _traffic(dom, args.workload, tiles)
+    log("phases: " + ", ".join(f"{k} {v * 1e3:.1f} us ({upd_per_launch / (v * 1e-3):.3g} upd/s)"
+                                for k, v in kern.items()))
 
     cpu = None
     if not args.no_cpu_baseline:
-        log("cpu baseline: oracle local update on 8 of 16 nodes ...")
-        v_cpu, dt = cpu_baseline(w)
+        log(f"cpu baseline: oracle local update on {sample_desc} ...")
+        v_cpu, dt = cpu_baseline(ws, sample)
         cpu = {"value": v_cpu, "unit": "updates/s", "cores": 1, "kind": "oracle",
-               "sample": f"Alg. 2 local update (E1={w.inner_iters}: P and P^T) of nodes 0-7 of {w.n_nodes}, "
-                         f"{w.n}^2, {w.n_angles // w.n_nodes} angles each, float64 NumPy, {dt:.1f} s"}
+               "sample": f"Alg. 2 local update (E1=5: P and P^T) of {sample_desc}, float64 NumPy, {dt:.1f} s"}
 
+    lloyd = None
+    if km_iters is not None:
+        it = km_iters.cpu().numpy().reshape(-1)
+        lloyd = {"mean": float(it.mean()), "max": int(it.max()), "min": int(it.min())}
+    rel = [abs(a - b) / b if b > 0 else 0.0 for a, b in zip(rmse_batched, rmse_plain)]
     out = {
         "metric": "proj+backproj ray-voxel updates/s; ADMM iter/s batched vs plain @ equal RMSE",
         "value": value,
         "unit": "updates/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps,
         "warmup": args.warmup,
         "ms_per_step": ms_per_step,
         "higher_is_better": True,
@@ -240,22 +328,22 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "single-GPU plain method: 512x512 random-ellipse phantom (20 ellipses), "
-                               "720 angles, 725 bins, Poisson 1e5, 16 nodes contiguous, SEG x-update, "
-                               "K-means 8 levels, E1=5, E2=10, rho=1",
-                   "n": w.n, "angles": w.n_angles, "bins": w.n_bins, "nodes": w.n_nodes},
-        "admm_iters_per_s": {"batched_graph": 1e3 / ms_per_step, "plain_loop": 1.0 / plain_s},
-        "equal_rmse": {"iterations": n_eq, "plain": rmse_plain, "batched": rmse_batched,
-                       "bit_identical": identical},
-        "rmse_after_timed_steps": rmse_final,
-        "kmeans_lloyd_iters_last_step": {"mean": float(lloyd.mean()), "max": int(lloyd.max()),
-                                          "min": int(lloyd.min())},
-        "kernels_us": {k: v * 1e3 for k, v in kern.items()},
+        "config": dict({"workload": desc}, **cfg),
+        "admm_iters_per_s": {"batched_graph": n_slices * 1e3 / ms_per_step, "plain_loop": n_slices / plain_s,
+                             "unit": "slice-iterations/s"},
+        "equal_rmse": {"iterations": n_eq, "bit_identical": identical, "max_rel_rmse_diff": max(rel),
+                       "plain_slice0": rmse_plain[0], "batched_slice0": rmse_batched[0]},
+        "rmse_after_timed_steps": {"slice0": rmse_final[0], "mean": float(np.mean(rmse_final))},
+        "kmeans_lloyd_iters_last_step": lloyd,
+        "projector_tiles": tiles,
+        "phases_us": {k: v * 1e3 for k, v in kern.items()},
         "roofline": {"bound": "alu", "kernel": PHASE_KERNELS[dom], "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                     "traffic": traffic,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
                      "algorithmic": f"{ALGO_FLOPS_PER_UPDATE:g} flop per ray-voxel update x "
                                     f"{upd_per_launch} updates per launch"},
+        "hbm": ({"achieved": traffic / dur_s / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                 "frac": traffic / dur_s / 1e9 / PEAK_HBM_GBS} if traffic else None),
+        "setup_s": setup_s,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -4,6 +4,7 @@
 #include <memory>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "common.h"
@@ -14,7 +15,7 @@ template <int R, class Src> __global__ void k_project(Src);
 template <class Src> __global__ void k_project_reduce(Src);
 template <class Src> __global__ void k_backproject(Src);
 __global__ void k_seg_none(const SegJob*, int, int);
-template <bool VLDS> __global__ void k_kmeans(const KMJob*, KMJob, int, int, int, float*, long long);
+template <bool REG> __global__ void k_kmeans(const KMJob*, KMJob, int, int, int);
 __global__ void k_seg_dct(const SegJob*, int, int, int);
 __global__ void k_dct(const float*, int, int, int, int, int16_t*, float*, float*);
 __global__ void k_avg(Many<AvgJob>, const NodeRef*);
@@ -101,15 +102,17 @@ struct ConsPlan {
   std::vector<tomo_msg> msg_key;
   DevBuf seg, avg, noderefs, labels, kmjobs, kmwork;
   int n_seg = 0, n_avg = 0, avg_wgs = 0, dual_wgs = 0;
-  long long km_stride = 0;     // workspace floats per segment (0: segments regroup in LDS)
-  long long label_stride = 0;
+  int km_small = 0, km_big = 0;   // K-means jobs regrouping in LDS, then those using the workspace
 };
 
 constexpr int kKmThreads = 1024;
 
-// Workspace floats per segment of the K-means kernel: none when every segment
-// fits the LDS copy, else the longest segment.
-long long kmeans_stride(long long max_n) { return max_n <= KM_LDS_VALUES ? 0 : max_n; }
+// FNV-1a hash of a descriptor array: the plan caches are indexed by it.
+uint64_t hash_bytes(const void* p, size_t n, uint64_t h = 1469598103934665603ull) {
+  const unsigned char* c = static_cast<const unsigned char*>(p);
+  for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 1099511628211ull;
+  return h;
+}
 
 bool same_nodes(const std::vector<tomo_node>& k, const tomo_node* nodes, int n) {
   return (int)k.size() == n && std::memcmp(k.data(), nodes, sizeof(tomo_node) * n) == 0;
@@ -127,6 +130,8 @@ struct tomo_ctx {
   DevBuf km_work;                                // standalone K-means workspace
   std::vector<std::unique_ptr<LocalPlan>> lplans;
   std::vector<std::unique_ptr<ConsPlan>> cplans;
+  std::unordered_multimap<uint64_t, LocalPlan*> lindex;   // hash of the node array -> plan
+  std::unordered_multimap<uint64_t, ConsPlan*> cindex;    // hash of nodes and messages -> plan
   // plans dropped by tomo_set_option stay allocated (a captured graph may
   // still reference their buffers) until the context is destroyed
   std::vector<std::unique_ptr<LocalPlan>> retired_l;
@@ -202,9 +207,15 @@ int check_nodes(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes) {
 }
 
 LocalPlan* find_local_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes) {
-  for (auto& p : ctx->lplans)
-    if (same_nodes(p->key, nodes, n_nodes)) return p.get();
+  auto range = ctx->lindex.equal_range(hash_bytes(nodes, sizeof(tomo_node) * n_nodes));
+  for (auto it = range.first; it != range.second; ++it)
+    if (same_nodes(it->second->key, nodes, n_nodes)) return it->second;
   return nullptr;
+}
+
+uint64_t cons_hash(const tomo_node* nodes, int n_nodes, const tomo_msg* msg) {
+  uint64_t h = hash_bytes(nodes, sizeof(tomo_node) * n_nodes);
+  return msg ? hash_bytes(msg, sizeof(tomo_msg) * n_nodes, h) : h;
 }
 
 LocalPlan* get_local_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, int& rc) {
@@ -276,6 +287,7 @@ LocalPlan* get_local_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, in
   plan->n_b = (int)bj.size();
   plan->b_wgs = bw;
   plan->band = ctx->proj_band;
+  ctx->lindex.emplace(hash_bytes(nodes, sizeof(tomo_node) * n_nodes), plan.get());
   ctx->lplans.push_back(std::move(plan));
   return ctx->lplans.back().get();
 }
@@ -302,15 +314,17 @@ bool same_msg(const std::vector<tomo_msg>& k, const tomo_msg* msg, int n) {
 
 ConsPlan* get_cons_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, const tomo_msg* msg, int& rc) {
   rc = TOMO_OK;
-  for (auto& p : ctx->cplans)
-    if (same_nodes(p->key, nodes, n_nodes) && same_msg(p->msg_key, msg, n_nodes)) return p.get();
+  const uint64_t h = cons_hash(nodes, n_nodes, msg);
+  auto range = ctx->cindex.equal_range(h);
+  for (auto it = range.first; it != range.second; ++it)
+    if (same_nodes(it->second->key, nodes, n_nodes) && same_msg(it->second->msg_key, msg, n_nodes))
+      return it->second;
   auto plan = std::make_unique<ConsPlan>();
   plan->key.assign(nodes, nodes + n_nodes);
   if (msg) plan->msg_key.assign(msg, msg + n_nodes);
   std::vector<SegJob> seg;
   std::vector<AvgJob> avg;
   std::vector<NodeRef> refs;
-  long long max_seg = 0;
   int aw = 0, dw = 0;
   for (int i = 0; i < n_nodes; ++i) {
     const tomo_node& N = nodes[i];
@@ -323,7 +337,6 @@ ConsPlan* get_cons_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, cons
       s.coeffs = msg[i].coeffs; s.lohi = msg[i].lohi;
     }
     seg.push_back(s);
-    max_seg = std::max(max_seg, (long long)N.seg_rows * N.g.n);
     NodeRef r{};
     r.u = N.u; r.lam = N.lam; r.x = N.x; r.n = N.g.n; r.rho = N.rho;
     r.wg_begin = dw;
@@ -337,9 +350,28 @@ ConsPlan* get_cons_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, cons
     }
     avg.back().n_nodes++;
   }
-  plan->label_stride = (max_seg + 255) / 256 * 256;
-  plan->km_stride = kmeans_stride(max_seg);
-  std::vector<KMJob> km;
+  // K-means jobs: segments that fit the registers first, then the longer ones,
+  // each with its own slice of the label scratch and of the workspace
+  std::vector<KMJob> km_small, km_big;
+  std::vector<size_t> label_off(n_nodes), work_off(n_nodes, 0);
+  size_t label_elems = 0, work_elems = 0;
+  for (int i = 0; i < n_nodes; ++i) {
+    const long long segn = (long long)nodes[i].seg_rows * nodes[i].g.n;
+    label_off[i] = label_elems;
+    if (!(msg && msg[i].labels)) label_elems += (size_t)(segn + 255) / 256 * 256;
+    if (segn > KM_LDS_VALUES) {
+      work_off[i] = work_elems;
+      work_elems += (size_t)(segn + 63) / 64 * 64;
+    }
+  }
+  if (!plan->seg.ensure(seg.size() * sizeof(SegJob)) || !plan->avg.ensure(avg.size() * sizeof(AvgJob)) ||
+      !plan->noderefs.ensure(refs.size() * sizeof(NodeRef)) ||
+      !plan->labels.ensure(std::max<size_t>(label_elems, 1)) ||
+      !plan->kmjobs.ensure((size_t)n_nodes * sizeof(KMJob)) ||
+      !plan->kmwork.ensure(work_elems * sizeof(float))) {
+    rc = ctx->fail(TOMO_ENOMEM, "consensus plan allocation failed");
+    return nullptr;
+  }
   for (int i = 0; i < n_nodes; ++i) {
     const tomo_node& N = nodes[i];
     size_t off = (size_t)N.seg_row0 * N.g.n;
@@ -352,22 +384,21 @@ ConsPlan* get_cons_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, cons
     j.n = (long long)N.seg_rows * N.g.n;
     j.rho = N.rho;
     j.eta2 = N.eta2;
-    j.labels = (msg && msg[i].labels) ? msg[i].labels : nullptr;   // scratch filled in below
+    j.labels = (msg && msg[i].labels) ? msg[i].labels : static_cast<uint8_t*>(plan->labels.p) + label_off[i];
     j.cent = msg ? msg[i].centroids : nullptr;
     j.iters = msg ? msg[i].iters : nullptr;
-    km.push_back(j);
+    if (j.n > KM_LDS_VALUES) {
+      j.work = static_cast<float*>(plan->kmwork.p) + work_off[i];
+      km_big.push_back(j);
+    } else {
+      km_small.push_back(j);
+    }
   }
-  if (!plan->seg.ensure(seg.size() * sizeof(SegJob)) || !plan->avg.ensure(avg.size() * sizeof(AvgJob)) ||
-      !plan->noderefs.ensure(refs.size() * sizeof(NodeRef)) ||
-      !plan->labels.ensure((size_t)plan->label_stride * n_nodes) ||
-      !plan->kmjobs.ensure(km.size() * sizeof(KMJob)) ||
-      !plan->kmwork.ensure((size_t)plan->km_stride * n_nodes * sizeof(float))) {
-    rc = ctx->fail(TOMO_ENOMEM, "consensus plan allocation failed");
-    return nullptr;
-  }
-  for (int i = 0; i < n_nodes; ++i)
-    if (!km[i].labels) km[i].labels = static_cast<uint8_t*>(plan->labels.p) + (size_t)i * plan->label_stride;
-  if (hipMemcpy(plan->kmjobs.p, km.data(), km.size() * sizeof(KMJob), hipMemcpyHostToDevice) != hipSuccess) {
+  plan->km_small = (int)km_small.size();
+  plan->km_big = (int)km_big.size();
+  km_small.insert(km_small.end(), km_big.begin(), km_big.end());
+  if (hipMemcpy(plan->kmjobs.p, km_small.data(), km_small.size() * sizeof(KMJob), hipMemcpyHostToDevice) !=
+      hipSuccess) {
     rc = ctx->fail(TOMO_EDEVICE, "K-means plan upload failed");
     return nullptr;
   }
@@ -381,6 +412,7 @@ ConsPlan* get_cons_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, cons
   plan->n_avg = (int)avg.size();
   plan->avg_wgs = aw;
   plan->dual_wgs = dw;
+  ctx->cindex.emplace(h, plan.get());
   ctx->cplans.push_back(std::move(plan));
   return ctx->cplans.back().get();
 }
@@ -443,6 +475,8 @@ int tomo_set_option(tomo_ctx* ctx, int32_t option, int64_t value) {
   for (auto& p : ctx->cplans) ctx->retired_c.push_back(std::move(p));
   ctx->lplans.clear();
   ctx->cplans.clear();
+  ctx->lindex.clear();
+  ctx->cindex.clear();
   return TOMO_OK;
 }
 
@@ -564,14 +598,13 @@ int admm_consensus(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, int32
   if (kind == TOMO_QUANT_KMEANS) {
     // the x-update (SEG) runs inside the K-means kernel; AVG already wrote x
     const KMJob* kj = static_cast<const KMJob*>(plan->kmjobs.p);
-    float* wk = static_cast<float*>(plan->kmwork.p);
     const int ex = do_x ? e2 : 0;
-    if (plan->km_stride == 0)
-      hipLaunchKernelGGL(k_kmeans<true>, dim3(plan->n_seg), dim3(kKmThreads), 0, s, kj, KMJob{}, q->levels,
-                         q->max_iter, ex, wk, 0ll);
-    else
-      hipLaunchKernelGGL(k_kmeans<false>, dim3(plan->n_seg), dim3(kKmThreads), 0, s, kj, KMJob{}, q->levels,
-                         q->max_iter, ex, wk, plan->km_stride);
+    if (plan->km_small > 0)
+      hipLaunchKernelGGL(k_kmeans<true>, dim3(plan->km_small), dim3(kKmThreads), 0, s, kj, KMJob{}, q->levels,
+                         q->max_iter, ex);
+    if (plan->km_big > 0)
+      hipLaunchKernelGGL(k_kmeans<false>, dim3(plan->km_big), dim3(kKmThreads), 0, s, kj + plan->km_small,
+                         KMJob{}, q->levels, q->max_iter, ex);
   } else if (kind == TOMO_QUANT_DCT) {
     hipLaunchKernelGGL(k_seg_dct, dim3(plan->n_seg), dim3(256), 0, s, seg, do_x, e2, q->quality);
   } else if (do_x) {
@@ -591,8 +624,8 @@ int quantize_kmeans(tomo_ctx* ctx, const float* a, int64_t n, int32_t k, int32_t
   if (a_hat && a_hat != a && overlaps(a, (size_t)n * 4, a_hat, (size_t)n * 4))
     return ctx->fail(TOMO_EINVAL, "a_hat partially overlaps a");
   if (int rc = set_device(ctx)) return rc;
-  const long long stride = kmeans_stride(n);
-  if (!ctx->km_work.ensure((size_t)stride * sizeof(float))) return ctx->fail(TOMO_ENOMEM, "workspace");
+  const bool big = n > KM_LDS_VALUES;
+  if (big && !ctx->km_work.ensure((size_t)n * sizeof(float))) return ctx->fail(TOMO_ENOMEM, "workspace");
   KMJob j{};
   j.src = a;
   j.a_hat = a_hat;
@@ -601,13 +634,14 @@ int quantize_kmeans(tomo_ctx* ctx, const float* a, int64_t n, int32_t k, int32_t
   j.iters = iters;
   j.n = n;
   j.rho = 1.f;
-  float* wk = static_cast<float*>(ctx->km_work.p);
-  if (stride == 0)
-    hipLaunchKernelGGL(k_kmeans<true>, dim3(1), dim3(kKmThreads), 0, (hipStream_t)stream, nullptr, j, k, max_iter,
-                       0, wk, 0ll);
-  else
+  if (big) {
+    j.work = static_cast<float*>(ctx->km_work.p);
     hipLaunchKernelGGL(k_kmeans<false>, dim3(1), dim3(kKmThreads), 0, (hipStream_t)stream, nullptr, j, k, max_iter,
-                       0, wk, stride);
+                       0);
+  } else {
+    hipLaunchKernelGGL(k_kmeans<true>, dim3(1), dim3(kKmThreads), 0, (hipStream_t)stream, nullptr, j, k, max_iter,
+                       0);
+  }
   return launch_status(ctx, "quantize_kmeans");
 }
 

@@ -132,12 +132,13 @@ struct KMJob {
   uint8_t* labels;      // [n] (nullable)
   float* cent;          // [k] (nullable)
   int32_t* iters;       // [1] (nullable)
+  float* work;          // [n] regrouping workspace, required when n > KM_LDS_VALUES
   long long n;          // < 2^31
   float rho, eta2;
 };
 
-// Segments up to this many values are regrouped in LDS; longer ones in a
-// global workspace of n floats per segment.
+// Segments up to this many values are regrouped in LDS; longer ones in the
+// job's global workspace of n floats.
 constexpr int KM_LDS_VALUES = 16384;
 
 __device__ __forceinline__ float wave_sum(float v) {

@@ -177,10 +177,9 @@ __device__ __forceinline__ void at_or_below(const KMShared& sh, VP V, float x, c
 
 // One workgroup per segment.  REG: the segment fits the registers (n <=
 // KM_LDS_VALUES) and its bucket-ordered copy fits LDS; otherwise the values
-// are streamed in every pass and the copy goes to work + segment * work_stride.
+// are streamed in every pass and the copy goes to the job's workspace.
 template <bool REG>
-__global__ __launch_bounds__(KT) void k_kmeans(const KMJob* jobs, KMJob single, int k, int max_iter, int e2,
-                                               float* work, long long work_stride) {
+__global__ __launch_bounds__(KT) void k_kmeans(const KMJob* jobs, KMJob single, int k, int max_iter, int e2) {
 #pragma clang fp contract(off)
   __shared__ KMShared sh;
   __shared__ float vlds[REG ? KM_LDS_VALUES : 1];
@@ -317,7 +316,7 @@ __global__ __launch_bounds__(KT) void k_kmeans(const KMJob* jobs, KMJob single, 
   const long long tot = sh.psum[B];
 
   // pass 3: values regrouped by bucket
-  float* const wv = REG ? nullptr : work + (size_t)seg * work_stride;
+  float* const wv = REG ? nullptr : J.work;
   each([&](int, float a) {
     const int b = bk.of(a);
     const int p = sh.start[b] + atomicAdd(&sh.fill[b], 1);
@@ -462,7 +461,7 @@ __global__ __launch_bounds__(KT) void k_kmeans(const KMJob* jobs, KMJob single, 
   if (J.iters && tid == 0) *J.iters = it;
 }
 
-template __global__ void k_kmeans<true>(const KMJob*, KMJob, int, int, int, float*, long long);
-template __global__ void k_kmeans<false>(const KMJob*, KMJob, int, int, int, float*, long long);
+template __global__ void k_kmeans<true>(const KMJob*, KMJob, int, int, int);
+template __global__ void k_kmeans<false>(const KMJob*, KMJob, int, int, int);
 
 }  // namespace tomo

@@ -128,6 +128,33 @@ def test_batched_equals_plain_loop(mods, ctx):
         np.testing.assert_array_equal(s.x.cpu().numpy(), p)
 
 
+def test_batched_mixed_segment_sizes_equals_plain_loop(mods, ctx):
+    """Slices of uneven sizes and node counts in one batched call: K-means
+    segments above the register/LDS limit (128 x 256 = 32768 values) run in the
+    same consensus call as small ones; the result equals the per-slice,
+    per-node loop bit for bit."""
+    T, A = mods
+    shapes = [(256, 384, 362, 2), (64, 96, 91, 4), (128, 192, 181, 16), (96, 144, 136, 3)]
+    slices = []
+    for i, (n, k, b, m) in enumerate(shapes):
+        w = synthdata.Workload(f"mix{i}", 3, n, k, b, m, "interleaved", 6, "gaussian", 0.01, 4)
+        s = A.make_slice(ctx, w, slice_idx=i)
+        s.eta1 = A.step_size(ctx, s, 1.0, 0.1)
+        slices.append(s)
+    q = T.tomo_quant(T.TOMO_QUANT_KMEANS, 16, 30, 50)
+    run = A.DADMM(ctx, slices, quant=q)
+    for _ in range(3):
+        run.step_plain()
+    plain = [s.x.cpu().numpy().copy() for s in slices]
+    for s in slices:
+        s.zero()
+    for _ in range(3):
+        run.step()
+    for s, p in zip(slices, plain):
+        np.testing.assert_array_equal(s.x.cpu().numpy(), p)
+    assert all(np.isfinite(p).all() and np.abs(p).max() > 0 for p in plain)
+
+
 def test_graph_replay_matches_eager(mods, ctx):
     T, A = mods
     slices = _slices(T, A, ctx)
