@@ -66,11 +66,10 @@ def _traffic(kernel: str, workload: str, tiles):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    if rec.get("source_sha") != _source_sha(KERNEL_SOURCES):
+    if rec.get("source_sha") != _source_sha(KERNEL_SOURCES) or not tiles:
         return None
-    if rec.get("tiles") and tiles and rec["tiles"] != tiles:
-        return None
-    return rec.get("hbm_bytes_per_launch")
+    entry = rec.get("by_tiles", {}).get(f"{tiles['band']}/{tiles['job_wgs']}")
+    return entry.get("hbm_bytes_per_launch") if entry else None
 
 
 def cpu_baseline(slices_info, sample_nodes):
@@ -163,6 +162,7 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tiles", default=None, help="projector tiles BAND/JOB_WGS instead of autotuning")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only launch the projector and backprojector of the workload a few times, and a "
@@ -202,7 +202,13 @@ def main():
     updates_per_step = sum(2 * w.inner_iters * w.n_angles * w.n * w.n for w in ws)
     upd_per_launch = sum(w.n_angles * w.n * w.n for w in ws)
     tiles = None
-    if not args.no_autotune:
+    if args.tiles:
+        band, jw = (int(v) for v in args.tiles.split("/"))
+        tiles = {"band": band, "job_wgs": jw}
+        autotune.apply(ctx, tiles)
+    elif args.no_autotune:
+        tiles = {"band": 32, "job_wgs": 16}       # the context's defaults
+    else:
         choice = autotune.tune(ctx, run.nodes)
         tiles = {"band": choice["band"], "job_wgs": choice["job_wgs"]}
         log(f"autotune: band {choice['band']}, {choice['job_wgs']} workgroups per node "
