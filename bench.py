@@ -45,8 +45,8 @@ PHASE_KERNELS = {"project": "projection phase: k_project + k_project_reduce",
                  "backproject": "backprojection phase: k_backproject"}
 KERNEL_SOURCES = ("paper_2410_06106_amd/csrc/project.hip", "paper_2410_06106_amd/csrc/backproject.hip",
                   "paper_2410_06106_amd/csrc/common.h")
-DEFAULT_STEPS = {"single": 100, "batch": 5, "large": 10}
-EQUAL_RMSE_STEPS = {"single": 5, "batch": 2, "large": 2}
+DEFAULT_STEPS = {"single": 100, "batch": 5, "large": 10, "diff": 4}
+EQUAL_RMSE_STEPS = {"single": 5, "batch": 2, "large": 2, "diff": 0}
 
 
 def _source_sha(paths):
@@ -152,12 +152,101 @@ def build(which, ctx, A, T, synthdata, log):
     raise SystemExit(f"unknown workload {which}")
 
 
+def bench_diff(args, steps, ctx, log):
+    """Form (3): K = 10 unrolled ADMM iterations of the 1024^2, 1080-angle,
+    32-node workload with learnable (rho_k, eta_k), trained by Adam on seeded
+    phantom / sinogram pairs; the projector's backward is the hand-written
+    backprojector and iterates are checkpointed every 2 iterations.  One step =
+    one training step (forward, loss, backward with recomputation, Adam)."""
+    import numpy as np
+    import torch
+
+    import synthdata
+    from paper_2410_06106_amd import admm as A
+    from paper_2410_06106_amd import autograd as AG
+    from paper_2410_06106_amd import tomoadmm as T
+
+    w = synthdata.WORKLOADS["diff"]
+    n, nb, iters, e1 = w.n, w.n_bins, w.outer_iters, w.inner_iters
+    th = synthdata.angles(w.n_angles)
+    parts = synthdata.partition_angles(w.n_angles, w.n_nodes, w.split)
+    segs = synthdata.segment_rows(n, w.n_nodes)
+    ang_all = torch.from_numpy(th).cuda()
+    angs = [ang_all[torch.from_numpy(p).cuda()].contiguous() for p in parts]
+    t_setup = time.perf_counter()
+    L = A.operator_norm(ctx, angs[0], n, nb, iters=20)
+    model = AG.UnrolledADMM(ctx, n, nb, angs, segs, iters=iters, e1=e1, e2=w.x_iters, eta2=w.eta2,
+                            eta0=0.1 / (L + 1.0), ckpt=2).cuda()
+    opt = torch.optim.Adam(model.parameters(), lr=0.05)
+
+    def pair(i):
+        truth = synthdata.phantom(w, i)
+        t = torch.from_numpy(truth.astype(np.float32)).cuda()
+        clean = T.tomo_project(ctx, ang_all, t, nb).cpu().numpy()
+        d = synthdata.add_gaussian_noise(clean, w.noise_level, synthdata.sinogram_seed(w, i))
+        dd = torch.from_numpy(np.ascontiguousarray(d, dtype=np.float32)).cuda()
+        return t, [dd[torch.from_numpy(p).cuda()].contiguous() for p in parts]
+
+    data = [pair(i) for i in range(steps + 1)]
+    setup_s = time.perf_counter() - t_setup
+    log(f"setup: {n}^2, {w.n_angles} angles, {w.n_nodes} nodes, {iters} unrolled iterations, {setup_s:.1f} s")
+
+    def train_step(i):
+        tgt, ds = data[i]
+        opt.zero_grad()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x = model(ds)
+        loss = torch.mean((x - tgt) ** 2)
+        loss_v = float(loss.item())
+        t1 = time.perf_counter()
+        loss.backward()
+        opt.step()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return loss_v, t1 - t0, t2 - t1
+
+    train_step(0)                                  # warm-up: plans, allocator
+    losses, fw, bw = [], [], []
+    t0 = time.perf_counter()
+    for i in range(1, steps + 1):
+        lv, f, b = train_step(i)
+        losses.append(lv)
+        fw.append(f)
+        bw.append(b)
+        log(f"step {i}: loss {lv:.6g}, forward {f * 1e3:.0f} ms, backward + Adam {b * 1e3:.0f} ms")
+    wall = time.perf_counter() - t0
+    fwd_updates = iters * e1 * 2 * w.n_angles * n * n       # P and P^T in the forward unroll
+    upd_step = 3 * fwd_updates                               # forward, recomputation, backward
+    ms = wall * 1e3 / steps
+    out = {
+        "metric": "proj+backproj ray-voxel updates/s; ADMM iter/s batched vs plain @ equal RMSE",
+        "value": upd_step / (ms * 1e-3), "unit": "updates/s", "n_gpus": 1, "steps": steps, "warmup": 1,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "differentiation: 1024x1024 random-ellipse phantoms (20 ellipses), 1080 angles, "
+                               "1449 bins, Gaussian 1%, 32 nodes interleaved, 10 unrolled ADMM iterations (SEG, "
+                               "no quantizer), E1=5, E2=10, learnable rho_k and eta_k (20 scalars), Adam lr 0.05, "
+                               "checkpoint every 2 iterations", "n": n, "angles": w.n_angles, "bins": nb,
+                   "nodes": w.n_nodes, "unrolled_iterations": iters},
+        "training": {"losses": losses, "forward_ms": float(np.mean(fw)) * 1e3,
+                     "backward_adam_ms": float(np.mean(bw)) * 1e3,
+                     "backward_over_forward": float(np.mean(bw) / np.mean(fw)),
+                     "updates_per_step": upd_step, "forward_updates": fwd_updates,
+                     "rho": torch.exp(model.log_rho).tolist(), "eta": torch.exp(model.log_eta).tolist()},
+        "setup_s": setup_s,
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="single", choices=("single", "batch", "large"))
+    ap.add_argument("--workload", default="single", choices=("single", "batch", "large", "diff"))
     ap.add_argument("--plain-steps", type=int, default=None)
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -189,6 +278,8 @@ def main():
 
     torch.cuda.set_device(0)
     ctx = T.Context(0)
+    if args.workload == "diff":
+        return bench_diff(args, steps, ctx, log)
     t_setup = time.perf_counter()
     slices, ws, q, desc, cfg, sample, sample_desc = build(args.workload, ctx, A, T, synthdata, log)
     n_slices = len(slices)
