@@ -43,8 +43,8 @@ PEAK_FP32_TFLOPS = 157.3           # MI355X vector FP32 (published)
 PEAK_HBM_GBS = 8000.0
 PHASE_KERNELS = {"project": "projection phase: k_project + k_project_reduce",
                  "backproject": "backprojection phase: k_backproject"}
-KERNEL_SOURCES = ("paper_2410_06106_amd/csrc/project.hip", "paper_2410_06106_amd/csrc/backproject.hip",
-                  "paper_2410_06106_amd/csrc/common.h")
+KERNEL_SOURCES = ("paper_2410_06106_amd/csrc/project.hip", "paper_2410_06106_amd/csrc/project_res.hip",
+                  "paper_2410_06106_amd/csrc/backproject.hip", "paper_2410_06106_amd/csrc/common.h")
 DEFAULT_STEPS = {"single": 100, "batch": 5, "large": 10, "diff": 4}
 EQUAL_RMSE_STEPS = {"single": 5, "batch": 2, "large": 2, "diff": 0}
 
@@ -68,7 +68,8 @@ def _traffic(kernel: str, workload: str, tiles):
         rec = json.load(fh)
     if rec.get("source_sha") != _source_sha(KERNEL_SOURCES) or not tiles:
         return None
-    entry = rec.get("by_tiles", {}).get(f"{tiles['band']}/{tiles['job_wgs']}")
+    key = "resident" if tiles.get("kernel") == 1 else f"{tiles['band']}/{tiles['job_wgs']}"
+    entry = rec.get("by_tiles", {}).get(key)
     return entry.get("hbm_bytes_per_launch") if entry else None
 
 
@@ -251,7 +252,8 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--tiles", default=None, help="projector tiles BAND/JOB_WGS instead of autotuning")
+    ap.add_argument("--tiles", default=None,
+                    help="projector choice instead of autotuning: BAND/JOB_WGS (band kernel) or 'resident'")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only launch the projector and backprojector of the workload a few times, and a "
@@ -294,16 +296,20 @@ def main():
     upd_per_launch = sum(w.n_angles * w.n * w.n for w in ws)
     tiles = None
     if args.tiles:
-        band, jw = (int(v) for v in args.tiles.split("/"))
-        tiles = {"band": band, "job_wgs": jw}
+        if args.tiles == "resident":
+            tiles = {"kernel": 1, "band": 32, "job_wgs": 16}
+        else:
+            band, jw = (int(v) for v in args.tiles.split("/"))
+            tiles = {"kernel": 0, "band": band, "job_wgs": jw}
         autotune.apply(ctx, tiles)
     elif args.no_autotune:
-        tiles = {"band": 32, "job_wgs": 16}       # the context's defaults
+        tiles = {"kernel": 0, "band": 32, "job_wgs": 16}       # the context's defaults
     else:
         choice = autotune.tune(ctx, run.nodes)
-        tiles = {"band": choice["band"], "job_wgs": choice["job_wgs"]}
-        log(f"autotune: band {choice['band']}, {choice['job_wgs']} workgroups per node "
-            f"({choice['us']:.1f} us per projection phase; tried {len(choice['tried'])})")
+        tiles = {"kernel": choice["kernel"], "band": choice["band"], "job_wgs": choice["job_wgs"]}
+        kind = ("region-resident kernel" if choice["kernel"] == 1 else
+                f"band kernel, band {choice['band']}, {choice['job_wgs']} workgroups per node")
+        log(f"autotune: {kind} ({choice['us']:.1f} us per projection phase; tried {len(choice['tried'])})")
     setup_s = time.perf_counter() - t_setup
     log(f"setup done in {setup_s:.1f} s")
 

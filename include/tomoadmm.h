@@ -72,8 +72,13 @@ const char* tomo_last_error(const tomo_ctx* ctx);
  *   TOMO_OPT_PROJ_BAND      image lines the projector stages in LDS per pass
  *                           (16 or 32, default 32); changes the projector's
  *                           summation order only
+ *   TOMO_OPT_PROJ_KERNEL    0: band-streamed projector (the two options above
+ *                           apply); 1: region-resident projector (one
+ *                           workgroup per 128 x 128 region holds it in LDS for
+ *                           every angle of the node; images up to 2048 x 2048,
+ *                           larger ones use kernel 0).  Default 0.
  */
-enum { TOMO_OPT_PROJ_JOB_WGS = 1, TOMO_OPT_PROJ_BAND = 3 };
+enum { TOMO_OPT_PROJ_JOB_WGS = 1, TOMO_OPT_PROJ_BAND = 3, TOMO_OPT_PROJ_KERNEL = 4 };
 int tomo_set_option(tomo_ctx* ctx, int32_t option, int64_t value);
 
 typedef struct {

@@ -1,9 +1,10 @@
 """Autotuner of the projector's launch shape for a list of nodes.
 
-The forward projector has two shape choices (see ``tomo_set_option`` in the C
-header): the band depth staged in LDS per pass (16 or 32 image lines) and how
-many workgroups a node should span before its image is split into smaller
-regions.  The best pair depends on the image size, the angles per node and the
+The forward projector has two kernels and, for the band-streamed one, two
+shape choices (see ``tomo_set_option`` in the C header): the band depth staged
+in LDS per pass (16 or 32 image lines) and how many workgroups a node should
+span before its image is split into smaller regions; the region-resident
+kernel has none.  The best pair depends on the image size, the angles per node and the
 number of nodes launched together, so it is measured: every candidate pair is
 set on the context, the batched projection phase (``admm_local_phase`` phase 0,
 which reads u and writes the residual only) is launched a few times, timed
@@ -25,6 +26,7 @@ import torch
 from . import tomoadmm as T
 
 BANDS = (16, 32)
+MAX_RESIDENT_N = 2048          # the region-resident kernel's largest image side
 JOB_WGS = (8, 16, 32, 64, 128)
 
 
@@ -49,13 +51,15 @@ def _time_phase(ctx, nodes, reps: int) -> float:
 
 
 def apply(ctx, choice: dict):
+    T.tomo_set_option(ctx, T.TOMO_OPT_PROJ_KERNEL, int(choice.get("kernel", 0)))
     T.tomo_set_option(ctx, T.TOMO_OPT_PROJ_BAND, int(choice["band"]))
     T.tomo_set_option(ctx, T.TOMO_OPT_PROJ_JOB_WGS, int(choice["job_wgs"]))
 
 
 def tune(ctx, nodes, cache_path: str | None = None, reps: int = 5, bands=BANDS, job_wgs=JOB_WGS) -> dict:
-    """Pick and set the fastest (band, job_wgs) for ``nodes`` (a ``make_nodes``
-    array).  Returns {"band", "job_wgs", "us", "tried": {...}, "cached": bool}."""
+    """Pick and set the fastest projector (kernel, band, job_wgs) for ``nodes``
+    (a ``make_nodes`` array).  Returns {"kernel", "band", "job_wgs", "us",
+    "tried": {...}, "cached": bool}."""
     key = signature(nodes)
     cache = {}
     if cache_path and os.path.exists(cache_path):
@@ -68,11 +72,14 @@ def tune(ctx, nodes, cache_path: str | None = None, reps: int = 5, bands=BANDS, 
     tried = {}
     for band in bands:
         for jw in job_wgs:
-            apply(ctx, {"band": band, "job_wgs": jw})
-            tried[f"{band}/{jw}"] = _time_phase(ctx, nodes, reps)
+            apply(ctx, {"kernel": 0, "band": band, "job_wgs": jw})
+            tried[f"0/{band}/{jw}"] = _time_phase(ctx, nodes, reps)
+    if all(int(nd.g.n) <= MAX_RESIDENT_N for nd in nodes):
+        apply(ctx, {"kernel": 1, "band": bands[-1], "job_wgs": job_wgs[0]})
+        tried[f"1/{bands[-1]}/{job_wgs[0]}"] = _time_phase(ctx, nodes, reps)
     best = min(tried, key=tried.get)
-    band, jw = (int(v) for v in best.split("/"))
-    choice = {"band": band, "job_wgs": jw, "us": tried[best], "tried": tried}
+    kernel, band, jw = (int(v) for v in best.split("/"))
+    choice = {"kernel": kernel, "band": band, "job_wgs": jw, "us": tried[best], "tried": tried}
     apply(ctx, choice)
     if cache_path:
         cache[key] = choice

@@ -13,6 +13,8 @@
 namespace tomo {
 template <int R, class Src> __global__ void k_project(Src);
 template <class Src> __global__ void k_project_reduce(Src);
+template <class Src> __global__ void k_project_res(Src);
+template <class Src> __global__ void k_project_res_reduce(Src);
 template <class Src> __global__ void k_backproject(Src);
 __global__ void k_seg_none(const SegJob*, int, int);
 template <bool REG> __global__ void k_kmeans(const KMJob*, KMJob, int, int, int);
@@ -56,6 +58,18 @@ int reduce_wgs(const ProjShape& s, int n_bins) {
   return s.n_achunk * ((n_bins + PTHREADS - 1) / PTHREADS);
 }
 
+// Region-resident projector: one workgroup per 128 x 128 region of a node,
+// every angle of the node in it.
+ProjShape resident_shape(int n) {
+  ProjShape s;
+  s.n_achunk = 1;
+  s.reg_h = s.reg_w = std::min(n, QR);
+  s.n_rr = s.n_rc = (n + s.reg_h - 1) / s.reg_h;
+  return s;
+}
+
+int resident_reduce_wgs(int n_ang, int n_bins) { return n_ang * ((n_bins + QTHREADS - 1) / QTHREADS); }
+
 ProjShape base_shape(int n, int n_ang) {
   ProjShape s;
   s.n_achunk = (n_ang + PA - 1) / PA;
@@ -95,6 +109,7 @@ struct LocalPlan {
   DevBuf pjobs, rjobs, bjobs, resid, partial;
   int n_p = 0, p_wgs = 0, n_r = 0, r_wgs = 0, n_b = 0, b_wgs = 0;
   int band = 16;                 // projector band depth (16 or 32)
+  bool resident = false;         // region-resident projector (k_project_res)
 };
 
 struct ConsPlan {
@@ -125,6 +140,7 @@ struct tomo_ctx {
   int n_cu = 1;
   int proj_job_wgs = 16;      // TOMO_OPT_PROJ_JOB_WGS
   int proj_band = 32;         // TOMO_OPT_PROJ_BAND
+  int proj_kernel = 0;        // TOMO_OPT_PROJ_KERNEL
   std::string err;
   DevBuf partial;                                // standalone projector workspace
   DevBuf km_work;                                // standalone K-means workspace
@@ -225,16 +241,23 @@ LocalPlan* get_local_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, in
   plan->key.assign(nodes, nodes + n_nodes);
   std::vector<ProjShape> shapes;
   size_t resid_elems = 0, part_elems = 0;
+  bool resident = ctx->proj_kernel == 1;
+  for (int i = 0; i < n_nodes; ++i) resident = resident && nodes[i].g.n <= QMAXN;
   for (int i = 0; i < n_nodes; ++i) {
-    shapes.push_back(base_shape(nodes[i].g.n, nodes[i].n_ang));
-    split_for_parallelism(shapes.back(), nodes[i].g.n, ctx->proj_job_wgs);
+    if (resident) {
+      shapes.push_back(resident_shape(nodes[i].g.n));
+    } else {
+      shapes.push_back(base_shape(nodes[i].g.n, nodes[i].n_ang));
+      split_for_parallelism(shapes.back(), nodes[i].g.n, ctx->proj_job_wgs);
+    }
   }
   std::vector<size_t> roff(n_nodes), poff(n_nodes);
   for (int i = 0; i < n_nodes; ++i) {
     roff[i] = resid_elems;
     resid_elems += (size_t)nodes[i].n_ang * nodes[i].g.n_bins;
     poff[i] = part_elems;
-    if (shapes[i].regions() > 1) part_elems += (size_t)shapes[i].wgs() * PA * PACC;
+    if (resident) part_elems += (size_t)nodes[i].n_ang * shapes[i].regions() * QACC;
+    else if (shapes[i].regions() > 1) part_elems += (size_t)shapes[i].wgs() * PA * PACC;
   }
   if (!plan->resid.ensure(resid_elems * 4) || !plan->partial.ensure(std::max<size_t>(part_elems, 1) * 4)) {
     rc = ctx->fail(TOMO_ENOMEM, "plan workspace allocation failed");
@@ -252,10 +275,10 @@ LocalPlan* get_local_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, in
     j.wg_begin = pw;
     pw += shapes[i].wgs();
     pj.push_back(j);
-    if (shapes[i].regions() > 1) {     // reduction launch: angle chunks x bin blocks
+    if (resident || shapes[i].regions() > 1) {     // reduction launch
       ProjJob r = j;
       r.wg_begin = rw;
-      rw += reduce_wgs(shapes[i], N.g.n_bins);
+      rw += resident ? resident_reduce_wgs(N.n_ang, N.g.n_bins) : reduce_wgs(shapes[i], N.g.n_bins);
       rj.push_back(r);
     }
     BPJob b = make_bp_job(R + roff[i], N.angles, N.u, N.g.n, N.g.n_bins, N.n_ang);
@@ -287,6 +310,7 @@ LocalPlan* get_local_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, in
   plan->n_b = (int)bj.size();
   plan->b_wgs = bw;
   plan->band = ctx->proj_band;
+  plan->resident = resident;
   ctx->lindex.emplace(hash_bytes(nodes, sizeof(tomo_node) * n_nodes), plan.get());
   ctx->lplans.push_back(std::move(plan));
   return ctx->lplans.back().get();
@@ -296,6 +320,13 @@ LocalPlan* get_local_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, in
 // nodes split into several regions) the reduction pass.
 void launch_projection(const LocalPlan* plan, void* stream) {
   Many<ProjJob> ps{static_cast<const ProjJob*>(plan->pjobs.p), plan->n_p};
+  if (plan->resident) {
+    Many<ProjJob> rs{static_cast<const ProjJob*>(plan->rjobs.p), plan->n_r};
+    hipLaunchKernelGGL(k_project_res<Many<ProjJob>>, dim3(plan->p_wgs), dim3(QTHREADS), 0, (hipStream_t)stream, ps);
+    hipLaunchKernelGGL(k_project_res_reduce<Many<ProjJob>>, dim3(plan->r_wgs), dim3(QTHREADS), 0,
+                       (hipStream_t)stream, rs);
+    return;
+  }
   if (plan->band == 32)
     hipLaunchKernelGGL((k_project<32, Many<ProjJob>>), dim3(plan->p_wgs), dim3(PTHREADS), 0, (hipStream_t)stream, ps);
   else
@@ -468,6 +499,10 @@ int tomo_set_option(tomo_ctx* ctx, int32_t option, int64_t value) {
       if (value != 16 && value != 32) return ctx->fail(TOMO_EINVAL, "projector band depth must be 16 or 32");
       ctx->proj_band = (int)value;
       break;
+    case TOMO_OPT_PROJ_KERNEL:
+      if (value != 0 && value != 1) return ctx->fail(TOMO_EINVAL, "projector kernel must be 0 or 1");
+      ctx->proj_kernel = (int)value;
+      break;
     default:
       return ctx->fail(TOMO_EINVAL, "unknown option");
   }
@@ -490,6 +525,17 @@ int tomo_project(tomo_ctx* ctx, tomo_geom g, const double* angles, int32_t n_ang
   if (overlaps(image, (size_t)g.n * g.n * 4, sino, (size_t)n_ang * g.n_bins * 4))
     return ctx->fail(TOMO_EINVAL, "image and sino overlap");
   if (int rc = set_device(ctx)) return rc;
+  if (ctx->proj_kernel == 1 && g.n <= QMAXN) {
+    const ProjShape rs = resident_shape(g.n);
+    ProjJob j = make_proj_job(image, angles, nullptr, sino, g.n, g.n_bins, n_ang, rs);
+    if (!ctx->partial.ensure((size_t)n_ang * rs.regions() * QACC * 4)) return ctx->fail(TOMO_ENOMEM, "workspace");
+    j.partial = static_cast<float*>(ctx->partial.p);
+    hipLaunchKernelGGL(k_project_res<Single<ProjJob>>, dim3(rs.regions()), dim3(QTHREADS), 0, (hipStream_t)stream,
+                       Single<ProjJob>{j});
+    hipLaunchKernelGGL(k_project_res_reduce<Single<ProjJob>>, dim3(resident_reduce_wgs(n_ang, g.n_bins)),
+                       dim3(QTHREADS), 0, (hipStream_t)stream, Single<ProjJob>{j});
+    return launch_status(ctx, "tomo_project");
+  }
   std::vector<ProjShape> sh{base_shape(g.n, n_ang)};
   split_for_parallelism(sh[0], g.n, ctx->proj_job_wgs);
   ProjJob j = make_proj_job(image, angles, nullptr, sino, g.n, g.n_bins, n_ang, sh[0]);

@@ -48,12 +48,23 @@ constexpr int PACC = 384;      // ray accumulators per angle and region (>= PREG
 constexpr int PMAXREG = 256;   // max regions per job
 constexpr int PTHREADS = 256;
 
+// Region-resident projector: 128 x 128 regions held in LDS for all angles of
+// a node; one workgroup per region, partials [n_ang][G][QACC].
+constexpr int QR = 128;        // region side
+constexpr int QOFF = 2;        // zero samples before each LDS line
+constexpr int QLS = QR + 4;    // LDS line stride (zero samples on both sides)
+constexpr int QACC = 192;      // rays per angle and region (>= 128 * sqrt(2) + 3)
+constexpr int QBAND = 32;      // lines per unrolled band
+constexpr int QTHREADS = 1024;
+constexpr int QAG = 64;        // angles whose parameters are staged together
+constexpr int QMAXN = QR * 16; // images up to this side (at most PMAXREG regions)
+
 struct ProjJob {
   const float* img;     // [n][n]
   const double* ang;    // [n_ang]
   const float* d;       // [n_ang][nb] or null: out = scale * P img - d
   float* out;           // [n_ang][nb]
-  float* partial;       // [n_achunk][G][PA][PACC]
+  float* partial;       // band kernel: [n_achunk][G][PA][PACC]; region-resident: [n_ang][G][QACC]
   int n, nb, n_ang;
   int n_achunk;
   int reg_h, reg_w;     // region size (<= PREG)

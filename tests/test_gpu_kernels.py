@@ -99,13 +99,15 @@ def test_projector_full_size_sampled_angles(T, ctx):
     assert rel_l2(got_b, joseph.backproject(sino, th_all[pick], n)) <= 1e-5
 
 
-@pytest.mark.parametrize("band", [16, 32])
-@pytest.mark.parametrize("job_wgs", [1, 64, 4096])
-def test_projector_launch_options_match_oracle(T, band, job_wgs):
-    """Every band depth and region split gives the oracle's projection, both
-    through tomo_project and through the batched local update's residual."""
-    log(f"case options band={band} job_wgs={job_wgs}")
+@pytest.mark.parametrize("kernel,band,job_wgs", [(0, 16, 1), (0, 16, 64), (0, 16, 4096), (0, 32, 1),
+                                                  (0, 32, 64), (0, 32, 4096), (1, 32, 16)])
+def test_projector_launch_options_match_oracle(T, kernel, band, job_wgs):
+    """Both projector kernels, every band depth and region split give the
+    oracle's projection, through tomo_project and through the batched local
+    update's residual."""
+    log(f"case options kernel={kernel} band={band} job_wgs={job_wgs}")
     c = T.Context(0)
+    T.tomo_set_option(c, T.TOMO_OPT_PROJ_KERNEL, kernel)
     T.tomo_set_option(c, T.TOMO_OPT_PROJ_BAND, band)
     T.tomo_set_option(c, T.TOMO_OPT_PROJ_JOB_WGS, job_wgs)
     rng = np.random.default_rng(band + job_wgs)
@@ -132,19 +134,39 @@ def test_projector_launch_options_match_oracle(T, band, job_wgs):
 def test_set_option_rejects_bad_values(T):
     c = T.Context(0)
     for opt, bad in ((T.TOMO_OPT_PROJ_BAND, 8), (T.TOMO_OPT_PROJ_BAND, 64), (T.TOMO_OPT_PROJ_JOB_WGS, 0),
+                     (T.TOMO_OPT_PROJ_KERNEL, 2),
                      (2, 1), (99, 1)):
         with pytest.raises(T.TomoError):
             T.tomo_set_option(c, opt, bad)
 
 
-def test_projector_is_deterministic(T, ctx):
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_projector_is_deterministic(T, kernel):
+    c = T.Context(0)
+    T.tomo_set_option(c, T.TOMO_OPT_PROJ_KERNEL, kernel)
     rng = np.random.default_rng(2)
     n, nb = 700, 990
     ang = to_dev(rng.uniform(0, np.pi, 40), torch.float64)
     img = to_dev(rng.random((n, n)).astype(np.float32))
-    a = T.tomo_project(ctx, ang, img, nb).cpu()
+    a = T.tomo_project(c, ang, img, nb).cpu()
     for _ in range(3):
-        assert torch.equal(a, T.tomo_project(ctx, ang, img, nb).cpu())
+        assert torch.equal(a, T.tomo_project(c, ang, img, nb).cpu())
+
+
+@pytest.mark.parametrize("n,nb,k", [(1, 1, 3), (7, 11, 7), (128, 182, 13), (129, 150, 30), (513, 727, 6),
+                                    (300, 200, 5), (2048, 2897, 3)])
+def test_region_resident_projector_matches_oracle(T, n, nb, k):
+    """The region-resident kernel on single images: one region, ragged
+    regions, a detector narrower than the image, the 2048^2 large shape, and
+    the special angles 0, pi/4, pi/2, 3pi/4."""
+    log(f"case resident n={n} nb={nb} k={k}")
+    c = T.Context(0)
+    T.tomo_set_option(c, T.TOMO_OPT_PROJ_KERNEL, 1)
+    rng = np.random.default_rng(n + k)
+    th = np.concatenate([rng.uniform(0, np.pi, k), [0.0, np.pi / 4, np.pi / 2, 3 * np.pi / 4]])
+    img = rng.random((n, n)).astype(np.float32)
+    got = T.tomo_project(c, to_dev(th, torch.float64), to_dev(img), nb).cpu().numpy()
+    assert rel_l2(got, joseph.project(img, th, nb)) <= 1e-5
 
 
 KM_CASES = [  # (n, k, distribution)
