@@ -103,6 +103,24 @@ int tomo_backproject(tomo_ctx* ctx, tomo_geom g, const double* angles, int32_t n
                      const float* sino, float* image, float alpha, float beta, void* stream);
 
 /*
+ * Centralized tomographic reconstruction by gradient descent (Section 2.2,
+ * Alg. 1, minimising 0.5 ||P u - d||^2 of Eq. 5):
+ *   repeat `iters` times:  u <- u - eta * P^T (P u - d)
+ * over all `n_ang` angles, starting from the u passed in (Alg. 1 starts from
+ * zeros: pass a zeroed u).  Each step is one projection with the residual
+ * fused into its epilogue and one matched backprojection that updates u in
+ * place.
+ *   angles: float64 [n_ang];  d: float32 [n_ang][n_bins];  u: float32 [n][n],
+ *   read and overwritten.  u and d must not overlap.
+ * Errors: TOMO_EINVAL for n_ang < 1, iters < 0, a non-finite eta, a null
+ * pointer or overlapping u and d.  iters == 0 is a no-op.  The residual lives
+ * in the context's workspace (n_ang * n_bins floats, allocated on the first
+ * call that needs more).
+ */
+int tomo_ctr_gd(tomo_ctx* ctx, tomo_geom g, const double* angles, int32_t n_ang, const float* d,
+                float* u, float eta, int32_t iters, void* stream);
+
+/*
  * One node of the decentralized problem (Eq. 6-7): its angles and data d_m,
  * its local image u_m and dual variable lambda_m, the slice-wide consensus image
  * x, and the segment x[m] it owns (rows seg_row0 .. seg_row0+seg_rows-1 of x,

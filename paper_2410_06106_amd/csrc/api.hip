@@ -1,5 +1,6 @@
 // C ABI of the tomoadmm library: argument checks, workspace and plans, launches.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -144,6 +145,7 @@ struct tomo_ctx {
   std::string err;
   DevBuf partial;                                // standalone projector workspace
   DevBuf km_work;                                // standalone K-means workspace
+  DevBuf ctr_resid;                              // residual of tomo_ctr_gd
   std::vector<std::unique_ptr<LocalPlan>> lplans;
   std::vector<std::unique_ptr<ConsPlan>> cplans;
   std::unordered_multimap<uint64_t, LocalPlan*> lindex;   // hash of the node array -> plan
@@ -338,6 +340,41 @@ void launch_projection(const LocalPlan* plan, void* stream) {
   }
 }
 
+// out = P img (- d when d is not null) for one job, on the context's
+// standalone workspace: the projector the options select, then the region
+// reduction when the image is split.  Arguments are checked by the caller.
+int project_one(tomo_ctx* ctx, tomo_geom g, const double* angles, int n_ang, const float* img,
+                const float* d, float* out, void* stream) {
+  if (ctx->proj_kernel == 1 && g.n <= QMAXN) {
+    const ProjShape rs = resident_shape(g.n);
+    ProjJob j = make_proj_job(img, angles, d, out, g.n, g.n_bins, n_ang, rs);
+    if (!ctx->partial.ensure((size_t)n_ang * rs.regions() * QACC * 4)) return ctx->fail(TOMO_ENOMEM, "workspace");
+    j.partial = static_cast<float*>(ctx->partial.p);
+    hipLaunchKernelGGL(k_project_res<Single<ProjJob>>, dim3(rs.regions()), dim3(QTHREADS), 0, (hipStream_t)stream,
+                       Single<ProjJob>{j});
+    hipLaunchKernelGGL(k_project_res_reduce<Single<ProjJob>>, dim3(resident_reduce_wgs(n_ang, g.n_bins)),
+                       dim3(QTHREADS), 0, (hipStream_t)stream, Single<ProjJob>{j});
+    return TOMO_OK;
+  }
+  ProjShape sh = base_shape(g.n, n_ang);
+  split_for_parallelism(sh, g.n, ctx->proj_job_wgs);
+  ProjJob j = make_proj_job(img, angles, d, out, g.n, g.n_bins, n_ang, sh);
+  if (sh.regions() > 1) {
+    if (!ctx->partial.ensure((size_t)sh.wgs() * PA * PACC * 4)) return ctx->fail(TOMO_ENOMEM, "workspace");
+    j.partial = static_cast<float*>(ctx->partial.p);
+  }
+  if (ctx->proj_band == 32)
+    hipLaunchKernelGGL((k_project<32, Single<ProjJob>>), dim3(sh.wgs()), dim3(PTHREADS), 0, (hipStream_t)stream,
+                       Single<ProjJob>{j});
+  else
+    hipLaunchKernelGGL((k_project<16, Single<ProjJob>>), dim3(sh.wgs()), dim3(PTHREADS), 0, (hipStream_t)stream,
+                       Single<ProjJob>{j});
+  if (sh.regions() > 1)
+    hipLaunchKernelGGL(k_project_reduce<Single<ProjJob>>, dim3(reduce_wgs(sh, g.n_bins)), dim3(PTHREADS), 0,
+                       (hipStream_t)stream, Single<ProjJob>{j});
+  return TOMO_OK;
+}
+
 bool same_msg(const std::vector<tomo_msg>& k, const tomo_msg* msg, int n) {
   if (!msg) return k.empty();
   return (int)k.size() == n && std::memcmp(k.data(), msg, sizeof(tomo_msg) * n) == 0;
@@ -525,33 +562,7 @@ int tomo_project(tomo_ctx* ctx, tomo_geom g, const double* angles, int32_t n_ang
   if (overlaps(image, (size_t)g.n * g.n * 4, sino, (size_t)n_ang * g.n_bins * 4))
     return ctx->fail(TOMO_EINVAL, "image and sino overlap");
   if (int rc = set_device(ctx)) return rc;
-  if (ctx->proj_kernel == 1 && g.n <= QMAXN) {
-    const ProjShape rs = resident_shape(g.n);
-    ProjJob j = make_proj_job(image, angles, nullptr, sino, g.n, g.n_bins, n_ang, rs);
-    if (!ctx->partial.ensure((size_t)n_ang * rs.regions() * QACC * 4)) return ctx->fail(TOMO_ENOMEM, "workspace");
-    j.partial = static_cast<float*>(ctx->partial.p);
-    hipLaunchKernelGGL(k_project_res<Single<ProjJob>>, dim3(rs.regions()), dim3(QTHREADS), 0, (hipStream_t)stream,
-                       Single<ProjJob>{j});
-    hipLaunchKernelGGL(k_project_res_reduce<Single<ProjJob>>, dim3(resident_reduce_wgs(n_ang, g.n_bins)),
-                       dim3(QTHREADS), 0, (hipStream_t)stream, Single<ProjJob>{j});
-    return launch_status(ctx, "tomo_project");
-  }
-  std::vector<ProjShape> sh{base_shape(g.n, n_ang)};
-  split_for_parallelism(sh[0], g.n, ctx->proj_job_wgs);
-  ProjJob j = make_proj_job(image, angles, nullptr, sino, g.n, g.n_bins, n_ang, sh[0]);
-  if (sh[0].regions() > 1) {
-    if (!ctx->partial.ensure((size_t)sh[0].wgs() * PA * PACC * 4)) return ctx->fail(TOMO_ENOMEM, "workspace");
-    j.partial = static_cast<float*>(ctx->partial.p);
-  }
-  if (ctx->proj_band == 32)
-    hipLaunchKernelGGL((k_project<32, Single<ProjJob>>), dim3(sh[0].wgs()), dim3(PTHREADS), 0,
-                       (hipStream_t)stream, Single<ProjJob>{j});
-  else
-    hipLaunchKernelGGL((k_project<16, Single<ProjJob>>), dim3(sh[0].wgs()), dim3(PTHREADS), 0,
-                       (hipStream_t)stream, Single<ProjJob>{j});
-  if (sh[0].regions() > 1)
-    hipLaunchKernelGGL(k_project_reduce<Single<ProjJob>>, dim3(reduce_wgs(sh[0], g.n_bins)), dim3(PTHREADS), 0,
-                       (hipStream_t)stream, Single<ProjJob>{j});
+  if (int rc = project_one(ctx, g, angles, n_ang, image, nullptr, sino, stream)) return rc;
   return launch_status(ctx, "tomo_project");
 }
 
@@ -571,6 +582,32 @@ int tomo_backproject(tomo_ctx* ctx, tomo_geom g, const double* angles, int32_t n
   hipLaunchKernelGGL(k_backproject<Single<BPJob>>, dim3(j.tiles_x * j.tiles_x), dim3(BTHREADS), 0,
                      (hipStream_t)stream, Single<BPJob>{j});
   return launch_status(ctx, "tomo_backproject");
+}
+
+int tomo_ctr_gd(tomo_ctx* ctx, tomo_geom g, const double* angles, int32_t n_ang, const float* d, float* u,
+                float eta, int32_t iters, void* stream) {
+  if (!ctx) return TOMO_EINVAL;
+  if (int rc = check_geom(ctx, g)) return rc;
+  if (n_ang < 1) return ctx->fail(TOMO_EINVAL, "n_ang < 1");
+  if (iters < 0) return ctx->fail(TOMO_EINVAL, "iters < 0");
+  if (!std::isfinite(eta)) return ctx->fail(TOMO_EINVAL, "eta must be finite");
+  if (!angles || !d || !u) return ctx->fail(TOMO_EINVAL, "null pointer");
+  const size_t img = (size_t)g.n * g.n * 4, sino = (size_t)n_ang * g.n_bins * 4;
+  if (overlaps(u, img, d, sino)) return ctx->fail(TOMO_EINVAL, "u and d overlap");
+  if (iters == 0) return TOMO_OK;
+  if (int rc = set_device(ctx)) return rc;
+  if (!ctx->ctr_resid.ensure(sino)) return ctx->fail(TOMO_ENOMEM, "workspace");
+  float* r = static_cast<float*>(ctx->ctr_resid.p);
+  BPJob b = make_bp_job(r, angles, u, g.n, g.n_bins, n_ang);
+  b.mode = BP_PLAIN;
+  b.alpha = -eta;
+  b.beta = 1.f;
+  for (int it = 0; it < iters; ++it) {
+    if (int rc = project_one(ctx, g, angles, n_ang, u, d, r, stream)) return rc;     // r = P u - d
+    hipLaunchKernelGGL(k_backproject<Single<BPJob>>, dim3(b.tiles_x * b.tiles_x), dim3(BTHREADS), 0,
+                       (hipStream_t)stream, Single<BPJob>{b});                        // u -= eta P^T r
+  }
+  return launch_status(ctx, "tomo_ctr_gd");
 }
 
 int admm_local_update(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, int32_t e1, void* stream) {

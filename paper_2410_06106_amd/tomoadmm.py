@@ -26,7 +26,7 @@ TOMO_QUANT_NONE, TOMO_QUANT_KMEANS, TOMO_QUANT_DCT = 0, 1, 2
 TOMO_OPT_PROJ_JOB_WGS, TOMO_OPT_PROJ_BAND, TOMO_OPT_PROJ_KERNEL = 1, 3, 4
 EXPORTED = ("tomo_create", "tomo_destroy", "tomo_status_string", "tomo_last_error", "tomo_set_option",
             "tomo_project",
-            "tomo_backproject", "admm_local_update", "admm_local_phase", "admm_consensus",
+            "tomo_backproject", "tomo_ctr_gd", "admm_local_update", "admm_local_phase", "admm_consensus",
             "quantize_kmeans", "quantize_dct", "tomo_sqdiff")
 
 
@@ -69,6 +69,7 @@ _lib.tomo_set_option.argtypes = [_P, ctypes.c_int32, ctypes.c_int64]
 _lib.tomo_project.argtypes = [_P, tomo_geom, _P, ctypes.c_int32, _P, _P, _P]
 _lib.tomo_backproject.argtypes = [_P, tomo_geom, _P, ctypes.c_int32, _P, _P, ctypes.c_float,
                                   ctypes.c_float, _P]
+_lib.tomo_ctr_gd.argtypes = [_P, tomo_geom, _P, ctypes.c_int32, _P, _P, ctypes.c_float, ctypes.c_int32, _P]
 _lib.admm_local_update.argtypes = [_P, ctypes.POINTER(tomo_node), ctypes.c_int32, ctypes.c_int32, _P]
 _lib.admm_local_phase.argtypes = [_P, ctypes.POINTER(tomo_node), ctypes.c_int32, ctypes.c_int32, _P]
 _lib.admm_consensus.argtypes = [_P, ctypes.POINTER(tomo_node), ctypes.c_int32, ctypes.c_int32,
@@ -173,6 +174,18 @@ def tomo_backproject(ctx: Context, angles, sino, n: int, out=None, alpha: float 
                                _stream(stream))
     ctx.check(rc, "tomo_backproject")
     return out
+
+
+def tomo_ctr_gd(ctx: Context, angles, d, u, eta: float, iters: int, stream=None):
+    """Alg. 1 in place on ``u`` (float32 [n][n]): ``iters`` steps u <- u - eta P^T (P u - d)."""
+    n_ang, n_bins = d.shape
+    n = u.shape[0]
+    g = tomo_geom(n, n_bins)
+    rc = _lib.tomo_ctr_gd(ctx.handle, g, _dev(angles, torch.float64, "angles", (n_ang,)), n_ang,
+                          _dev(d, torch.float32, "d", (n_ang, n_bins)), _dev(u, torch.float32, "u", (n, n)),
+                          float(eta), int(iters), _stream(stream))
+    ctx.check(rc, "tomo_ctr_gd")
+    return u
 
 
 def admm_local_update(ctx: Context, nodes, e1: int, stream=None):

@@ -31,7 +31,7 @@ import numpy as np
 
 __all__ = [
     "EllipseSet", "Workload", "WORKLOADS", "batch_slices",
-    "ellipse_params", "rasterize", "texture", "phantom", "angles",
+    "ellipse_params", "rasterize", "paint_levels", "texture", "phantom", "angles",
     "partition_angles", "segment_rows", "add_gaussian_noise", "poisson_noisy",
     "standard_normal", "sinogram_seed", "phantom_seed",
 ]
@@ -63,6 +63,7 @@ class Workload:
     levels: int = 16        # K-means clusters
     quality: tuple = (50,)  # DCT quality factors
     texture_sigma: float = 0.0
+    gray_levels: int = 0    # 0: additive densities; L >= 2: painted phantom with L gray values
     extra: dict = field(default_factory=dict)
 
 
@@ -75,6 +76,13 @@ WORKLOADS = {
                       50, quant="dct", quality=(25, 50, 90), texture_sigma=0.02),
     "diff": Workload("diff", 4, 1024, 1080, 1449, 32, "interleaved", 20, "gaussian", 0.01,
                      10, quant="none"),
+    # quality studies of Section 3 (Fig. 4-7): 512^2 image, 804 angles, 724
+    # bins (the detector spans the image diagonal, as the paper's padding to
+    # 724^2 does), two interleaved nodes (odd and even angles), E1 = E2 = 10,
+    # a piecewise-constant phantom with three gray levels like the paper's
+    # Phantom; noise is set per run as an NSD level
+    "elbow": Workload("elbow", 5, 512, 804, 724, 2, "interleaved", 10, "gaussian", 0.0,
+                      1000, inner_iters=10, x_iters=10, quant="kmeans", levels=3, gray_levels=3),
 }
 
 
@@ -149,6 +157,26 @@ def rasterize(ell: EllipseSet, n: int) -> np.ndarray:
     return img
 
 
+def paint_levels(ell: EllipseSet, n: int, levels: int) -> np.ndarray:
+    """Piecewise-constant phantom with ``levels`` gray values {0, 1/(L-1), ..., 1}
+    (float64 [n][n]): background 0, a body ellipse (centre 0, semi-axes 0.85 and
+    0.7) at level 1, then the drawn ellipses in order, each overwriting the
+    pixels inside it with level 1 + (i mod (L-1)) for the i-th, so every level
+    appears once there are L-1 ellipses or more."""
+    if levels < 2:
+        raise ValueError("need at least two gray levels")
+    X, Y = _pixel_centres(n)
+    step = 1.0 / (levels - 1)
+    img = np.where((X / 0.85) ** 2 + (Y / 0.7) ** 2 <= 1.0, step, 0.0)
+    for i, (cx, cy, a, b, phi, _) in enumerate(ell.params):
+        dx, dy = X - cx, Y - cy
+        cp, sp = math.cos(phi), math.sin(phi)
+        p = dx * cp + dy * sp
+        q = -dx * sp + dy * cp
+        img = np.where((p / a) ** 2 + (q / b) ** 2 <= 1.0, (1 + i % (levels - 1)) * step, img)
+    return img
+
+
 def texture(ell: EllipseSet, n: int, sigma: float, rng: np.random.Generator) -> np.ndarray:
     """I.i.d. N(0, sigma^2) inside the union of the ellipses, zero elsewhere."""
     X, Y = _pixel_centres(n)
@@ -167,6 +195,8 @@ def phantom(w: Workload, slice_idx: int = 0, n: int | None = None) -> np.ndarray
     n = w.n if n is None else n
     rng = np.random.default_rng(phantom_seed(w, slice_idx))
     ell = ellipse_params(w.n_ellipses, rng)
+    if w.gray_levels:
+        return paint_levels(ell, n, w.gray_levels).astype(np.float32)
     img = rasterize(ell, n)
     if w.texture_sigma > 0:
         img = img + texture(ell, n, w.texture_sigma, rng)
