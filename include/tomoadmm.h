@@ -219,6 +219,26 @@ int quantize_kmeans(tomo_ctx* ctx, const float* a, int64_t n, int32_t k, int32_t
                     uint8_t* labels, float* centroids, float* a_hat, int32_t* iters, void* stream);
 
 /*
+ * Wire format of a K-means message (Section 2.5, Eq. 20; Section 3.3 counts a
+ * K-level code as ceil(log2 K) bits).  tomo_pack_labels writes the n labels as
+ * `bits`-bit codes: value i occupies bits [i*bits, (i+1)*bits) of a stream of
+ * 32-bit words, least significant bit first, stream bit j being bit j mod 32 of
+ * word j / 32; only the low `bits` bits of a label are stored and the last
+ * word is padded with zeros.  A segment's message is this stream plus its
+ * float32 codebook: 4 * ceil(n * bits / 32) + 4 * k bytes.
+ *   labels: uint8 [n];  packed: uint32 [ceil(n*bits/32)], overwritten.
+ * tomo_unpack_labels reads the stream back: labels[i] (nullable) and
+ * a_hat[i] = centroids[code_i] (nullable; a code >= k reads centroids[k-1]).
+ * Errors: TOMO_EINVAL for bits outside [1, 8], n outside [0, 2^31), a null
+ * required pointer, a_hat without centroids or with k outside [1, 256], or an
+ * output overlapping the input.  n == 0 is a no-op.
+ */
+int tomo_pack_labels(tomo_ctx* ctx, const uint8_t* labels, int64_t n, int32_t bits, uint32_t* packed,
+                     void* stream);
+int tomo_unpack_labels(tomo_ctx* ctx, const uint32_t* packed, int64_t n, int32_t bits,
+                       const float* centroids, int32_t k, uint8_t* labels, float* a_hat, void* stream);
+
+/*
  * JPEG-style quantizer of a float32 matrix a[rows][cols] with leading dimension
  * ld (elements): per-matrix level map v = (a-lo)*255/(hi-lo) - 128, orthonormal
  * 8x8 DCT-II per block, codes = round-half-even(F / Qs) with Qs the ITU-T T.81

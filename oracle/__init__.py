@@ -18,6 +18,7 @@ kmeans    Alg. 5: scalar K-means quantizer with a fully specified, bit-exact
 dct       "standard JPEG" quantizer: 8x8 orthonormal DCT-II with the luminance
           table scaled to a quality factor (no entropy coding).
 metrics   Eq. 25-27 (RMSE, PSNR, NSD) and Eq. 19-20 (memory and communication).
+wire      the K-means message on the wire: labels packed at ceil(log2 K) bits.
 stepsize  power iteration for the step size of Alg. 2.
 
 Parity status: every function is pinned by a ``-m "not gpu"`` test in

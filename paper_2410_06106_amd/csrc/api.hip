@@ -24,6 +24,8 @@ __global__ void k_dct(const float*, int, int, int, int, int16_t*, float*, float*
 __global__ void k_avg(Many<AvgJob>, const NodeRef*);
 __global__ void k_dual(Many<NodeRef>);
 __global__ void k_sqdiff(const float*, const float*, long long, double*);
+__global__ void k_pack_labels(const uint8_t*, int, int, unsigned*, long long);
+__global__ void k_unpack_labels(const unsigned*, int, int, const float*, int, uint8_t*, float*);
 }  // namespace tomo
 
 using namespace tomo;
@@ -741,6 +743,38 @@ int quantize_dct(tomo_ctx* ctx, const float* a, int32_t rows, int32_t cols, int3
   hipLaunchKernelGGL(k_dct, dim3(1), dim3(256), 0, (hipStream_t)stream, a, rows, cols, ld, quality, coeffs, a_hat,
                      lohi);
   return launch_status(ctx, "quantize_dct");
+}
+
+int tomo_pack_labels(tomo_ctx* ctx, const uint8_t* labels, int64_t n, int32_t bits, uint32_t* packed,
+                     void* stream) {
+  if (!ctx) return TOMO_EINVAL;
+  if (bits < 1 || bits > 8) return ctx->fail(TOMO_EINVAL, "bits must be in [1, 8]");
+  if (n < 0 || n >= (int64_t(1) << 31)) return ctx->fail(TOMO_EINVAL, "n must be in [0, 2^31)");
+  if (n == 0) return TOMO_OK;
+  if (!labels || !packed) return ctx->fail(TOMO_EINVAL, "null pointer");
+  const long long words = (n * bits + 31) / 32;
+  if (overlaps(labels, (size_t)n, packed, (size_t)words * 4)) return ctx->fail(TOMO_EINVAL, "labels and packed overlap");
+  if (int rc = set_device(ctx)) return rc;
+  hipLaunchKernelGGL(k_pack_labels, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, (hipStream_t)stream, labels,
+                     (int)n, bits, packed, words);
+  return launch_status(ctx, "tomo_pack_labels");
+}
+
+int tomo_unpack_labels(tomo_ctx* ctx, const uint32_t* packed, int64_t n, int32_t bits, const float* centroids,
+                       int32_t k, uint8_t* labels, float* a_hat, void* stream) {
+  if (!ctx) return TOMO_EINVAL;
+  if (bits < 1 || bits > 8) return ctx->fail(TOMO_EINVAL, "bits must be in [1, 8]");
+  if (n < 0 || n >= (int64_t(1) << 31)) return ctx->fail(TOMO_EINVAL, "n must be in [0, 2^31)");
+  if (a_hat && (!centroids || k < 1 || k > 256)) return ctx->fail(TOMO_EINVAL, "a_hat needs centroids and 1 <= k <= 256");
+  if (n == 0 || (!labels && !a_hat)) return TOMO_OK;
+  if (!packed) return ctx->fail(TOMO_EINVAL, "null pointer");
+  const size_t words = (size_t)((n * bits + 31) / 32) * 4;
+  if ((labels && overlaps(packed, words, labels, (size_t)n)) || (a_hat && overlaps(packed, words, a_hat, (size_t)n * 4)))
+    return ctx->fail(TOMO_EINVAL, "outputs overlap the packed stream");
+  if (int rc = set_device(ctx)) return rc;
+  hipLaunchKernelGGL(k_unpack_labels, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, packed,
+                     (int)n, bits, centroids, a_hat ? k : 1, labels, a_hat);
+  return launch_status(ctx, "tomo_unpack_labels");
 }
 
 int tomo_sqdiff(tomo_ctx* ctx, const float* a, const float* b, int64_t n, double* out, void* stream) {

@@ -5,7 +5,11 @@
 * Fig. 5    RMSE as a function of the compression level: K-means with K
             levels (the elbow method of Section 3.3) and the DCT codec at
             several quality factors;
-* Fig. 6-7  robustness to Gaussian measurement noise given as NSD (Eq. 27).
+* Fig. 6-7  robustness to Gaussian measurement noise given as NSD (Eq. 27);
+* Eq. 20    per-node traffic of each run from its real messages (K-means
+            labels packed by ``tomo_pack_labels`` plus the codebook; float32
+            segments without quantizer; the codes' entropy for DCT) next to
+            the formula.
 
 Every iteration runs in the library's kernels (projector pair, consensus,
 quantizers, the centralized step) through the same batched driver as the
@@ -52,6 +56,8 @@ class Run:
     best_rmse: float
     best_iter: int
     bits_per_value: float     # exchanged bits per pixel value
+    traffic_bytes: int        # per node and iteration: messages sent + received (largest node)
+    eq20_bytes: float         # Eq. 20: 2 (M - 1) / M * image bytes * bits / 32
     seconds: float
     trace: list = dataclasses.field(default_factory=list, repr=False)
 
@@ -110,7 +116,7 @@ def run_ctr(ctx, w, truth, th, d, iters: int, c: float = 1.0, tol: float = 1e-6,
     best = int(np.argmin(trace))
     peak = float(truth.max())
     return Run("CTR", "ctr", 1, "none", 0, nsd, len(trace), trace[-1], _psnr(trace[-1], peak),
-               trace[best], best + 1, 32.0, sec, trace)
+               trace[best], best + 1, 32.0, 0, 0.0, sec, trace)
 
 
 def run_dadmm(ctx, w, truth, d, quant: str = "none", level: int = 0, iters: int = 1000, c: float = 0.1,
@@ -126,6 +132,9 @@ def run_dadmm(ctx, w, truth, d, quant: str = "none", level: int = 0, iters: int 
     if quant == "kmeans":
         q = T.tomo_quant(T.TOMO_QUANT_KMEANS, level, 30, 0)
         bits = float(max(1, math.ceil(math.log2(level))))
+        labels = [torch.empty(rows * w.n, dtype=torch.uint8, device="cuda") for _, rows in s.segments]
+        cents = [torch.empty(level, dtype=torch.float32, device="cuda") for _ in s.segments]
+        msgs = T.make_msgs([dict(labels=lb, centroids=ct) for lb, ct in zip(labels, cents)])
     elif quant == "dct":
         q = T.tomo_quant(T.TOMO_QUANT_DCT, 0, 0, level)
         coeffs = [torch.empty((rows, w.n), dtype=torch.int16, device="cuda") for _, rows in s.segments]
@@ -146,17 +155,27 @@ def run_dadmm(ctx, w, truth, d, quant: str = "none", level: int = 0, iters: int 
         if it > 0 and stop.rel_change() < tol:
             break
     sec = time.perf_counter() - t0
+    rows = [r for _, r in s.segments]
     if quant == "dct":
         # zeroth-order entropy of the last exchange's codes: the bits per value
         # an entropy coder would approach (no entropy coder is built)
         _, counts = torch.unique(torch.cat([cf.reshape(-1) for cf in coeffs]), return_counts=True)
         p = counts.double() / counts.sum()
         bits = float(-(p * torch.log2(p)).sum())
+        msg = [math.ceil(bits * r * w.n / 8) + 8 for r in rows]          # codes + the level-map range
+    elif quant == "kmeans":
+        # the wire format: labels packed at ceil(log2 K) bits plus the codebook
+        msg = [4 * T.tomo_pack_labels(ctx, lb, int(bits)).numel() + 4 * level for lb in labels]
+    else:
+        msg = [4 * r * w.n for r in rows]
+    m_nodes = len(msg)
+    traffic = max((m_nodes - 1) * own + sum(msg) - own for own in msg)
+    eq20 = 2.0 * (m_nodes - 1) / m_nodes * 4.0 * w.n * w.n * bits / 32.0
     best = int(np.argmin(trace))
     peak = float(truth.max())
     label = {"none": "dADMM", "kmeans": f"dADMM-K K={level}", "dct": f"dADMM-J q={level}"}[quant]
     return Run(f"{label} M={w.n_nodes}", "dadmm", w.n_nodes, quant, level, nsd, len(trace), trace[-1],
-               _psnr(trace[-1], peak), trace[best], best + 1, bits, sec, trace)
+               _psnr(trace[-1], peak), trace[best], best + 1, bits, traffic, eq20, sec, trace)
 
 
 def study_ctr(ctx, w, iters, nsd=0.0, node_counts=(2, 10)):
@@ -190,11 +209,13 @@ STUDIES = {"ctr": study_ctr, "elbow": study_elbow, "noise": study_noise}
 
 
 def table(runs) -> str:
-    rows = ["| run | NSD % | iterations | RMSE | PSNR dB | best RMSE (iteration) | bits/value | seconds |",
-            "|---|---|---|---|---|---|---|---|"]
+    rows = ["| run | NSD % | iterations | RMSE | PSNR dB | best RMSE (iteration) | bits/value | "
+            "traffic/node/iter B (Eq. 20) | seconds |",
+            "|---|---|---|---|---|---|---|---|---|"]
     for r in runs:
+        traffic = f"{r.traffic_bytes} ({r.eq20_bytes:.0f})" if r.method == "dadmm" else "-"
         rows.append(f"| {r.label} | {r.nsd:g} | {r.iters} | {r.rmse:.4g} | {r.psnr:.2f} | "
-                    f"{r.best_rmse:.4g} ({r.best_iter}) | {r.bits_per_value:.3g} | {r.seconds:.2f} |")
+                    f"{r.best_rmse:.4g} ({r.best_iter}) | {r.bits_per_value:.3g} | {traffic} | {r.seconds:.2f} |")
     return "\n".join(rows)
 
 

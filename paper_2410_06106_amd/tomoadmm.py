@@ -27,7 +27,7 @@ TOMO_OPT_PROJ_JOB_WGS, TOMO_OPT_PROJ_BAND, TOMO_OPT_PROJ_KERNEL = 1, 3, 4
 EXPORTED = ("tomo_create", "tomo_destroy", "tomo_status_string", "tomo_last_error", "tomo_set_option",
             "tomo_project",
             "tomo_backproject", "tomo_ctr_gd", "admm_local_update", "admm_local_phase", "admm_consensus",
-            "quantize_kmeans", "quantize_dct", "tomo_sqdiff")
+            "quantize_kmeans", "quantize_dct", "tomo_pack_labels", "tomo_unpack_labels", "tomo_sqdiff")
 
 
 class TomoError(RuntimeError):
@@ -78,6 +78,8 @@ _lib.quantize_kmeans.argtypes = [_P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.
 _lib.quantize_dct.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                               _P, _P, _P, _P]
 _lib.tomo_sqdiff.argtypes = [_P, _P, _P, ctypes.c_int64, _P, _P]
+_lib.tomo_pack_labels.argtypes = [_P, _P, ctypes.c_int64, ctypes.c_int32, _P, _P]
+_lib.tomo_unpack_labels.argtypes = [_P, _P, ctypes.c_int64, ctypes.c_int32, _P, ctypes.c_int32, _P, _P, _P]
 
 
 def _stream(stream=None):
@@ -233,6 +235,35 @@ def quantize_dct(ctx: Context, a, quality: int, coeffs=None, a_hat=None, lohi=No
                            _opt(lohi, torch.float32, "lohi", (2,)), _stream(stream))
     ctx.check(rc, "quantize_dct")
     return a_hat
+
+
+def packed_words(n: int, bits: int) -> int:
+    return (n * bits + 31) // 32
+
+
+def tomo_pack_labels(ctx: Context, labels, bits: int, out=None, stream=None):
+    """Pack uint8 labels at ``bits`` bits each; returns the words as an int32 tensor
+    holding the uint32 bit patterns."""
+    labels = labels.reshape(-1)
+    n = labels.numel()
+    words = packed_words(n, bits)
+    if out is None:
+        out = torch.empty(words, dtype=torch.int32, device=labels.device)
+    rc = _lib.tomo_pack_labels(ctx.handle, _dev(labels, torch.uint8, "labels"), n, int(bits),
+                               _dev(out, torch.int32, "packed", (words,)), _stream(stream))
+    ctx.check(rc, "tomo_pack_labels")
+    return out
+
+
+def tomo_unpack_labels(ctx: Context, packed, n: int, bits: int, centroids=None, labels=None, a_hat=None,
+                       stream=None):
+    k = 0 if centroids is None else centroids.numel()
+    rc = _lib.tomo_unpack_labels(ctx.handle, _dev(packed, torch.int32, "packed", (packed_words(n, bits),)), n,
+                                 int(bits), _opt(centroids, torch.float32, "centroids"), k,
+                                 _opt(labels, torch.uint8, "labels", (n,)), _opt(a_hat, torch.float32, "a_hat", (n,)),
+                                 _stream(stream))
+    ctx.check(rc, "tomo_unpack_labels")
+    return labels, a_hat
 
 
 def tomo_sqdiff(ctx: Context, a, b, out=None, stream=None):

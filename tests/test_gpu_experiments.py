@@ -12,7 +12,8 @@ import synthdata
 from gpu_common import log, require_gpu
 from oracle import admm as oadmm
 from oracle import joseph, stepsize
-from oracle.metrics import rmse
+from oracle.metrics import comm_per_node, rmse
+from oracle import wire
 
 pytestmark = pytest.mark.gpu
 
@@ -67,6 +68,9 @@ def test_dadmm_kmeans_runs_match_oracle(E, ctx, levels):
     got = np.array(run.trace)
     log(f"  gpu {got} oracle {want}")
     assert run.iters == 6 and run.bits_per_value == max(1, int(np.ceil(np.log2(levels))))
+    # two equal segments: each node sends its message and receives the other's
+    assert run.traffic_bytes == 2 * wire.message_bytes(32 * 64, levels)
+    assert run.eq20_bytes == pytest.approx(comm_per_node(4 * 64 * 64, 2, run.bits_per_value))
     # a value within rounding of a cluster boundary may take either label, so
     # the quantized trajectories are compared to 1e-4 for the first iterations
     # and to 3 % at the end (the per-step pieces are checked exactly elsewhere)
