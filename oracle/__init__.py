@@ -10,6 +10,8 @@ Modules
 -------
 joseph    Eq. 1-4: parallel-beam forward model as a Joseph (linear interpolation)
           system matrix, its transpose, and a dense form for tiny grids.
+chord     Eq. 2 with intersection lengths: the chord of each ray through each
+          pixel square (a trapezoid in the ray offset), its transpose, dense form.
 admm      Alg. 1 (centralized GD), Alg. 2 (local u-update), Alg. 3 (segment
           x-update), Eq. 9 (averaging x-update), Eq. 23-24 (exchange, dual),
           Alg. 4 (driver).
