@@ -77,8 +77,22 @@ const char* tomo_last_error(const tomo_ctx* ctx);
  *                           workgroup per 128 x 128 region holds it in LDS for
  *                           every angle of the node; images up to 2048 x 2048,
  *                           larger ones use kernel 0).  Default 0.
+ *   TOMO_OPT_PROJ_MODEL     system matrix of every projector and backprojector
+ *                           call of the context: 0 (default) the Joseph weights
+ *                           stated above; 1 the intersection lengths Eq. 2 names:
+ *                           P[(theta,b),(r,c)] = length of the line of bin b
+ *                           inside the unit square of pixel (r, c), which with
+ *                           D = t_b - t_rc is the trapezoid
+ *                           h * clamp((w2 - |D|) / (w2 - w1), 0, 1),
+ *                           h = 1 / max(|cos|,|sin|), w1 = ||cos| - |sin|| / 2,
+ *                           w2 = (|cos| + |sin|) / 2.  A cos or sin within 1e-12
+ *                           of zero counts as zero; a line along a pixel edge
+ *                           then belongs to the pixel on its +x (+y) side
+ *                           (half-open pixels).  Model 1 always uses the
+ *                           band-streamed projector and computes positions in
+ *                           float64 (about twice the cost).
  */
-enum { TOMO_OPT_PROJ_JOB_WGS = 1, TOMO_OPT_PROJ_BAND = 3, TOMO_OPT_PROJ_KERNEL = 4 };
+enum { TOMO_OPT_PROJ_JOB_WGS = 1, TOMO_OPT_PROJ_BAND = 3, TOMO_OPT_PROJ_KERNEL = 4, TOMO_OPT_PROJ_MODEL = 5 };
 int tomo_set_option(tomo_ctx* ctx, int32_t option, int64_t value);
 
 typedef struct {

@@ -31,21 +31,22 @@ from .dct import dct_quantize
 from .metrics import rmse
 
 
-def ctr_gd(d, thetas, n, eta, iters):
-    """Alg. 1: u <- u - eta P^T (P u - d), from u = 0."""
+def ctr_gd(d, thetas, n, eta, iters, proj=joseph):
+    """Alg. 1: u <- u - eta P^T (P u - d), from u = 0.  ``proj`` is the system
+    matrix's module (``oracle.joseph`` or ``oracle.chord``)."""
     u = np.zeros((n, n))
     for _ in range(iters):
-        u = u - eta * joseph.backproject(joseph.project(u, thetas, d.shape[1]) - d, thetas, n)
+        u = u - eta * proj.backproject(proj.project(u, thetas, d.shape[1]) - d, thetas, n)
     return u
 
 
-def local_update(u, x, lam, d_m, thetas_m, rho, eta1, e1):
+def local_update(u, x, lam, d_m, thetas_m, rho, eta1, e1, proj=joseph):
     """Alg. 2: E1 gradient steps of node m's u-subproblem, from the given u."""
     n = u.shape[0]
     u = np.array(u, dtype=np.float64)
     for _ in range(e1):
-        resid = joseph.project(u, thetas_m, d_m.shape[1]) - d_m
-        grad = joseph.backproject(resid, thetas_m, n) + rho * (u - (x - lam / rho))
+        resid = proj.project(u, thetas_m, d_m.shape[1]) - d_m
+        grad = proj.backproject(resid, thetas_m, n) + rho * (u - (x - lam / rho))
         u = u - eta1 * grad
     return u
 

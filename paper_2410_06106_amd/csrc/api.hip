@@ -12,11 +12,11 @@
 #include "../../include/tomoadmm.h"
 
 namespace tomo {
-template <int R, class Src> __global__ void k_project(Src);
+template <int R, class Src, bool CHORD> __global__ void k_project(Src);
 template <class Src> __global__ void k_project_reduce(Src);
 template <class Src> __global__ void k_project_res(Src);
 template <class Src> __global__ void k_project_res_reduce(Src);
-template <class Src> __global__ void k_backproject(Src);
+template <class Src, bool CHORD> __global__ void k_backproject(Src);
 __global__ void k_seg_none(const SegJob*, int, int);
 template <bool REG> __global__ void k_kmeans(const KMJob*, KMJob, int, int, int);
 __global__ void k_seg_dct(const SegJob*, int, int, int);
@@ -113,6 +113,7 @@ struct LocalPlan {
   int n_p = 0, p_wgs = 0, n_r = 0, r_wgs = 0, n_b = 0, b_wgs = 0;
   int band = 16;                 // projector band depth (16 or 32)
   bool resident = false;         // region-resident projector (k_project_res)
+  bool chord = false;            // chord-length model
 };
 
 struct ConsPlan {
@@ -144,6 +145,7 @@ struct tomo_ctx {
   int proj_job_wgs = 16;      // TOMO_OPT_PROJ_JOB_WGS
   int proj_band = 32;         // TOMO_OPT_PROJ_BAND
   int proj_kernel = 0;        // TOMO_OPT_PROJ_KERNEL
+  int model = 0;              // TOMO_OPT_PROJ_MODEL (0 Joseph, 1 chord lengths)
   std::string err;
   DevBuf partial;                                // standalone projector workspace
   DevBuf km_work;                                // standalone K-means workspace
@@ -245,7 +247,7 @@ LocalPlan* get_local_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, in
   plan->key.assign(nodes, nodes + n_nodes);
   std::vector<ProjShape> shapes;
   size_t resid_elems = 0, part_elems = 0;
-  bool resident = ctx->proj_kernel == 1;
+  bool resident = ctx->proj_kernel == 1 && ctx->model == 0;
   for (int i = 0; i < n_nodes; ++i) resident = resident && nodes[i].g.n <= QMAXN;
   for (int i = 0; i < n_nodes; ++i) {
     if (resident) {
@@ -275,6 +277,7 @@ LocalPlan* get_local_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, in
   for (int i = 0; i < n_nodes; ++i) {
     const tomo_node& N = nodes[i];
     ProjJob j = make_proj_job(N.u, N.angles, N.d, R + roff[i], N.g.n, N.g.n_bins, N.n_ang, shapes[i]);
+    j.chord = ctx->model;
     j.partial = PP + poff[i];
     j.wg_begin = pw;
     pw += shapes[i].wgs();
@@ -287,6 +290,7 @@ LocalPlan* get_local_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, in
     }
     BPJob b = make_bp_job(R + roff[i], N.angles, N.u, N.g.n, N.g.n_bins, N.n_ang);
     b.mode = BP_ADMM;
+    b.chord = ctx->model;
     b.x = N.x;
     b.lam = N.lam;
     b.rho = N.rho;
@@ -315,6 +319,7 @@ LocalPlan* get_local_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, in
   plan->b_wgs = bw;
   plan->band = ctx->proj_band;
   plan->resident = resident;
+  plan->chord = ctx->model == 1;
   ctx->lindex.emplace(hash_bytes(nodes, sizeof(tomo_node) * n_nodes), plan.get());
   ctx->lplans.push_back(std::move(plan));
   return ctx->lplans.back().get();
@@ -331,10 +336,18 @@ void launch_projection(const LocalPlan* plan, void* stream) {
                        (hipStream_t)stream, rs);
     return;
   }
-  if (plan->band == 32)
-    hipLaunchKernelGGL((k_project<32, Many<ProjJob>>), dim3(plan->p_wgs), dim3(PTHREADS), 0, (hipStream_t)stream, ps);
-  else
-    hipLaunchKernelGGL((k_project<16, Many<ProjJob>>), dim3(plan->p_wgs), dim3(PTHREADS), 0, (hipStream_t)stream, ps);
+  const dim3 grid(plan->p_wgs), block(PTHREADS);
+  if (plan->chord) {
+    if (plan->band == 32)
+      hipLaunchKernelGGL((k_project<32, Many<ProjJob>, true>), grid, block, 0, (hipStream_t)stream, ps);
+    else
+      hipLaunchKernelGGL((k_project<16, Many<ProjJob>, true>), grid, block, 0, (hipStream_t)stream, ps);
+  } else {
+    if (plan->band == 32)
+      hipLaunchKernelGGL((k_project<32, Many<ProjJob>, false>), grid, block, 0, (hipStream_t)stream, ps);
+    else
+      hipLaunchKernelGGL((k_project<16, Many<ProjJob>, false>), grid, block, 0, (hipStream_t)stream, ps);
+  }
   if (plan->n_r > 0) {
     Many<ProjJob> rs{static_cast<const ProjJob*>(plan->rjobs.p), plan->n_r};
     hipLaunchKernelGGL(k_project_reduce<Many<ProjJob>>, dim3(plan->r_wgs), dim3(PTHREADS), 0, (hipStream_t)stream,
@@ -342,12 +355,21 @@ void launch_projection(const LocalPlan* plan, void* stream) {
   }
 }
 
+// The backprojector instantiation for the model (chord lengths or Joseph).
+template <class Src>
+void launch_backproject(Src src, int wgs, int chord, void* stream) {
+  if (chord)
+    hipLaunchKernelGGL((k_backproject<Src, true>), dim3(wgs), dim3(BTHREADS), 0, (hipStream_t)stream, src);
+  else
+    hipLaunchKernelGGL((k_backproject<Src, false>), dim3(wgs), dim3(BTHREADS), 0, (hipStream_t)stream, src);
+}
+
 // out = P img (- d when d is not null) for one job, on the context's
 // standalone workspace: the projector the options select, then the region
 // reduction when the image is split.  Arguments are checked by the caller.
 int project_one(tomo_ctx* ctx, tomo_geom g, const double* angles, int n_ang, const float* img,
                 const float* d, float* out, void* stream) {
-  if (ctx->proj_kernel == 1 && g.n <= QMAXN) {
+  if (ctx->proj_kernel == 1 && ctx->model == 0 && g.n <= QMAXN) {
     const ProjShape rs = resident_shape(g.n);
     ProjJob j = make_proj_job(img, angles, d, out, g.n, g.n_bins, n_ang, rs);
     if (!ctx->partial.ensure((size_t)n_ang * rs.regions() * QACC * 4)) return ctx->fail(TOMO_ENOMEM, "workspace");
@@ -365,12 +387,20 @@ int project_one(tomo_ctx* ctx, tomo_geom g, const double* angles, int n_ang, con
     if (!ctx->partial.ensure((size_t)sh.wgs() * PA * PACC * 4)) return ctx->fail(TOMO_ENOMEM, "workspace");
     j.partial = static_cast<float*>(ctx->partial.p);
   }
-  if (ctx->proj_band == 32)
-    hipLaunchKernelGGL((k_project<32, Single<ProjJob>>), dim3(sh.wgs()), dim3(PTHREADS), 0, (hipStream_t)stream,
-                       Single<ProjJob>{j});
-  else
-    hipLaunchKernelGGL((k_project<16, Single<ProjJob>>), dim3(sh.wgs()), dim3(PTHREADS), 0, (hipStream_t)stream,
-                       Single<ProjJob>{j});
+  j.chord = ctx->model;
+  const dim3 grid(sh.wgs()), block(PTHREADS);
+  const Single<ProjJob> src{j};
+  if (ctx->model == 1) {
+    if (ctx->proj_band == 32)
+      hipLaunchKernelGGL((k_project<32, Single<ProjJob>, true>), grid, block, 0, (hipStream_t)stream, src);
+    else
+      hipLaunchKernelGGL((k_project<16, Single<ProjJob>, true>), grid, block, 0, (hipStream_t)stream, src);
+  } else {
+    if (ctx->proj_band == 32)
+      hipLaunchKernelGGL((k_project<32, Single<ProjJob>, false>), grid, block, 0, (hipStream_t)stream, src);
+    else
+      hipLaunchKernelGGL((k_project<16, Single<ProjJob>, false>), grid, block, 0, (hipStream_t)stream, src);
+  }
   if (sh.regions() > 1)
     hipLaunchKernelGGL(k_project_reduce<Single<ProjJob>>, dim3(reduce_wgs(sh, g.n_bins)), dim3(PTHREADS), 0,
                        (hipStream_t)stream, Single<ProjJob>{j});
@@ -542,6 +572,10 @@ int tomo_set_option(tomo_ctx* ctx, int32_t option, int64_t value) {
       if (value != 0 && value != 1) return ctx->fail(TOMO_EINVAL, "projector kernel must be 0 or 1");
       ctx->proj_kernel = (int)value;
       break;
+    case TOMO_OPT_PROJ_MODEL:
+      if (value != 0 && value != 1) return ctx->fail(TOMO_EINVAL, "projector model must be 0 or 1");
+      ctx->model = (int)value;
+      break;
     default:
       return ctx->fail(TOMO_EINVAL, "unknown option");
   }
@@ -581,8 +615,8 @@ int tomo_backproject(tomo_ctx* ctx, tomo_geom g, const double* angles, int32_t n
   j.mode = BP_PLAIN;
   j.alpha = alpha;
   j.beta = beta;
-  hipLaunchKernelGGL(k_backproject<Single<BPJob>>, dim3(j.tiles_x * j.tiles_x), dim3(BTHREADS), 0,
-                     (hipStream_t)stream, Single<BPJob>{j});
+  j.chord = ctx->model;
+  launch_backproject(Single<BPJob>{j}, j.tiles_x * j.tiles_x, j.chord, stream);
   return launch_status(ctx, "tomo_backproject");
 }
 
@@ -604,10 +638,10 @@ int tomo_ctr_gd(tomo_ctx* ctx, tomo_geom g, const double* angles, int32_t n_ang,
   b.mode = BP_PLAIN;
   b.alpha = -eta;
   b.beta = 1.f;
+  b.chord = ctx->model;
   for (int it = 0; it < iters; ++it) {
     if (int rc = project_one(ctx, g, angles, n_ang, u, d, r, stream)) return rc;     // r = P u - d
-    hipLaunchKernelGGL(k_backproject<Single<BPJob>>, dim3(b.tiles_x * b.tiles_x), dim3(BTHREADS), 0,
-                       (hipStream_t)stream, Single<BPJob>{b});                        // u -= eta P^T r
+    launch_backproject(Single<BPJob>{b}, b.tiles_x * b.tiles_x, b.chord, stream);   // u -= eta P^T r
   }
   return launch_status(ctx, "tomo_ctr_gd");
 }
@@ -627,7 +661,7 @@ int admm_local_update(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, in
   Many<BPJob> bs{static_cast<const BPJob*>(plan->bjobs.p), plan->n_b};
   for (int e = 0; e < e1; ++e) {
     launch_projection(plan, stream);
-    hipLaunchKernelGGL(k_backproject<Many<BPJob>>, dim3(plan->b_wgs), dim3(BTHREADS), 0, (hipStream_t)stream, bs);
+    launch_backproject(bs, plan->b_wgs, plan->chord, stream);
   }
   return launch_status(ctx, "admm_local_update");
 }
@@ -648,7 +682,7 @@ int admm_local_phase(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, int
     launch_projection(plan, stream);
   } else {
     Many<BPJob> bs{static_cast<const BPJob*>(plan->bjobs.p), plan->n_b};
-    hipLaunchKernelGGL(k_backproject<Many<BPJob>>, dim3(plan->b_wgs), dim3(BTHREADS), 0, (hipStream_t)stream, bs);
+    launch_backproject(bs, plan->b_wgs, plan->chord, stream);
   }
   return launch_status(ctx, "admm_local_phase");
 }

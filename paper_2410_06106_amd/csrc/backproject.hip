@@ -4,18 +4,27 @@
 // form: weight max(0, 1 - |t_b - t_rc| / c) / c on bins floor(s), floor(s)+1)
 // are read from a 48-bin window of the sinogram row staged in LDS and pre-scaled
 // by 1/c, so a pixel-angle update costs two clamped weights and two FMAs.
-// Gather only: no atomics, bit-reproducible.  Epilogues: plain
+// Gather only: no atomics, bit-reproducible.  The chord-length model (CHORD)
+// uses the same two bins with the trapezoid weight of the pixel's chord
+// instead of the triangle, positions in float64.  Epilogues: plain
 // (image = alpha P^T s + beta image) or the u-step of Alg. 2
 // (u -= eta1 (P^T r + rho (u - x) + lambda)).
 #include "common.h"
 
 namespace tomo {
 
-template <class Src>
+template <class Src, bool CHORD>
 __global__ __launch_bounds__(BTHREADS) void k_backproject(Src src) {
   __shared__ float sw[BAC * BW];
   __shared__ float4 aprm[BAC];
   __shared__ int wbase[BAC];
+  // chord lengths only: cos, sin, the tile origin's window coordinate and the
+  // trapezoid's outer half-width w2 in float64 (the ramp can be far narrower
+  // than a float32 rounding of w2), 1 / (w2 - w1), and for an axis-aligned
+  // angle the orientation of the half-open pixel convention
+  __shared__ double4 cprm[CHORD ? BAC : 1];
+  __shared__ float tprm[CHORD ? BAC : 1];
+  __shared__ int axis[CHORD ? BAC : 1];
 
   int lid;
   const BPJob J = src.get(blockIdx.x, lid);
@@ -31,14 +40,21 @@ __global__ __launch_bounds__(BTHREADS) void k_backproject(Src src) {
     const int nac = min(BAC, J.n_ang - ac);
     __syncthreads();
     if (tid < nac) {
-      double th = J.ang[ac + tid];
-      double cs = cos(th), sn = sin(th);
+      double cs, sn;
+      angle_trig(J.ang[ac + tid], CHORD, cs, sn);
       double s00 = (c0 - h) * cs + (r0 - h) * sn + hb;     // bin coordinate of the tile origin
       double dc = (BT - 1) * cs, dr = (BT - 1) * sn;
       int wb = (int)floor(s00 + fmin(0.0, dc) + fmin(0.0, dr)) - 1;
       double c = fmax(fabs(cs), fabs(sn));
       aprm[tid] = make_float4((float)cs, (float)sn, (float)(s00 - wb), (float)(1.0 / c));
       wbase[tid] = wb;
+      if (CHORD) {
+        const double w1 = 0.5 * fabs(fabs(cs) - fabs(sn)), w2 = 0.5 * (fabs(cs) + fabs(sn));
+        cprm[tid] = make_double4(cs, sn, s00 - wb, w2);
+        tprm[tid] = w2 > w1 ? (float)(1.0 / (w2 - w1)) : 0.f;
+        // axis-aligned: +1 when the line's coordinate grows with t, else -1
+        axis[tid] = sn == 0.0 ? (cs > 0.0 ? 1 : -1) : (cs == 0.0 ? (sn > 0.0 ? 1 : -1) : 0);
+      }
     }
     __syncthreads();
     for (int idx = tid; idx < nac * BW; idx += BTHREADS) {
@@ -48,6 +64,33 @@ __global__ __launch_bounds__(BTHREADS) void k_backproject(Src src) {
       sw[idx] = v * aprm[a].w;
     }
     __syncthreads();
+    if (CHORD) {
+      for (int a = 0; a < nac; ++a) {
+        const double4 p = cprm[a];
+        const float invr = tprm[a];
+        const int ax = axis[a];
+        const float* row = sw + a * BW;
+        const double sb = fma((double)dy, p.y, fma((double)dx0, p.x, p.z));
+        float* accs[4] = {&acc0, &acc1, &acc2, &acc3};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double sd = q == 0 ? sb : fma((double)q, p.x, sb);
+          const int b0 = (int)sd;                        // window coordinates are >= 0
+          const double f = sd - (double)b0;              // |D| to bin b0; 1 - f to bin b0 + 1
+          float w0, w1;
+          if (ax != 0) {                                 // half-open pixels
+            w0 = (ax > 0 ? f <= 0.5 : f < 0.5) ? 1.f : 0.f;
+            w1 = 1.f - w0;
+          } else {
+            w0 = __builtin_amdgcn_fmed3f((float)(p.w - f) * invr, 0.f, 1.f);
+            w1 = __builtin_amdgcn_fmed3f((float)(p.w - 1.0 + f) * invr, 0.f, 1.f);
+          }
+          *accs[q] = fmaf(w0, row[b0], *accs[q]);
+          *accs[q] = fmaf(w1, row[b0 + 1], *accs[q]);
+        }
+      }
+      continue;
+    }
     for (int a = 0; a < nac; ++a) {
       const float4 p = aprm[a];
       const float gam = p.w, omg = 1.f - p.w;
@@ -99,7 +142,9 @@ __global__ __launch_bounds__(BTHREADS) void k_backproject(Src src) {
   }
 }
 
-template __global__ void k_backproject<Single<BPJob>>(Single<BPJob>);
-template __global__ void k_backproject<Many<BPJob>>(Many<BPJob>);
+template __global__ void k_backproject<Single<BPJob>, false>(Single<BPJob>);
+template __global__ void k_backproject<Many<BPJob>, false>(Many<BPJob>);
+template __global__ void k_backproject<Single<BPJob>, true>(Single<BPJob>);
+template __global__ void k_backproject<Many<BPJob>, true>(Many<BPJob>);
 
 }  // namespace tomo

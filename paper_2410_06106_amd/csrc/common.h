@@ -71,6 +71,7 @@ struct ProjJob {
   int n_rr, n_rc;       // regions down / across
   int wg_begin;         // first workgroup of this job in its launch
   float scale;
+  int chord;            // 0: Joseph weights; 1: chord lengths (intersection lengths)
 };
 
 // ---------------------------------------------------------------------------
@@ -95,7 +96,25 @@ struct BPJob {
   int mode;
   float alpha, beta;    // plain: img = alpha * P^T sino + beta * img
   float rho, eta1;      // ADMM:  u -= eta1 * (P^T sino + rho (u - x) + lam)
+  int chord;            // 0: Joseph weights; 1: chord lengths
 };
+
+// cos and sin of a projection angle.  The chord-length model takes a cosine
+// or sine within 1e-12 of zero as exactly zero (the angle is axis-aligned and
+// lines on pixel edges follow the half-open pixel convention); the Joseph
+// model uses the values as computed.
+__device__ __forceinline__ void angle_trig(double th, int chord, double& cs, double& sn) {
+  double c = cos(th), s = sin(th);
+  if (chord) {
+    const bool zc = fabs(c) < 1e-12, zs = fabs(s) < 1e-12;
+    const double c1 = zs ? (c > 0.0 ? 1.0 : -1.0) : (zc ? 0.0 : c);
+    const double s1 = zc ? (s > 0.0 ? 1.0 : -1.0) : (zs ? 0.0 : s);
+    c = c1;
+    s = s1;
+  }
+  cs = c;
+  sn = s;
+}
 
 // ---------------------------------------------------------------------------
 // Consensus / quantization: one job = one segment of one node.

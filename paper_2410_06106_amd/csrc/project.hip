@@ -13,6 +13,12 @@
 // the regions' partials in region order: no atomics and no cross-workgroup
 // handshakes inside a launch, results are bit-reproducible.
 //
+// The same kernel evaluates the chord-length model of Eq. 2 (CHORD): in each
+// line a ray's segment covers |gamma| samples and is split between the two
+// samples it crosses in proportion to the lengths inside them (the same two
+// LDS reads, a different fraction); positions are then kept in float64 because
+// those weights are steep near axis-aligned angles.
+//
 // LDS rows are 16-byte aligned so whole float4s are staged with one store, and
 // transposed staging assigns consecutive image rows to consecutive lanes, so
 // neither staging pattern has bank conflicts.  With 32-line bands (whose LDS
@@ -42,6 +48,7 @@ struct AngleParam {
   float scale;    // path length per step: 1/|cos| or 1/|sin|
   int cls;        // 0 row-driven, 1 column-driven, -1 inactive
   int bbase;      // detector bin of ray j = 0 for this region
+  float inv_tau;  // chord lengths: 1 / |gamma| (1e30 for an axis-aligned angle)
 };
 
 // Lowest bin whose ray can meet a pixel of the region: floor of the smallest
@@ -64,7 +71,7 @@ __device__ __forceinline__ void region_of(const ProjJob& J, int region, int& gr0
 
 }  // namespace
 
-template <int R, class Src>
+template <int R, class Src, bool CHORD>
 __global__ __launch_bounds__(PTHREADS) void k_project(Src src) {
   using B = Band<R>;
   __shared__ __align__(16) float band[R * B::LS];
@@ -93,9 +100,10 @@ __global__ __launch_bounds__(PTHREADS) void k_project(Src src) {
     p.xi0 = p.beta = p.gamma = p.rlo0 = p.rhi0 = p.rsl = 0.0;
     p.scale = p.g32 = 0.f;
     p.bbase = 0;
+    p.inv_tau = 0.f;
     if (tid < na) {
-      double th = J.ang[a0 + tid];
-      double cs = cos(th), sn = sin(th);
+      double cs, sn;
+      angle_trig(J.ang[a0 + tid], CHORD, cs, sn);
       p.bbase = region_bbase(cs, sn, h, hb, gr0, gc0, gh, gw);
       double ib, W;
       if (fabs(cs) >= fabs(sn)) {   // walk rows, interpolate across columns
@@ -124,6 +132,15 @@ __global__ __launch_bounds__(PTHREADS) void k_project(Src src) {
       p.rhi0 = fmax(t1, t2);
       p.rsl = -p.gamma * ib;
       p.g32 = (float)p.gamma;
+      if (CHORD) {
+        // chord lengths: the ray's segment in a line spans |gamma| samples
+        // centred on xi; it is split between the samples floor(xi + (1-|gamma|)/2)
+        // and the next one, the next one taking max(0, 1 - q / |gamma|) of it,
+        // q = the distance from that point to the next sample boundary
+        const double tau = fabs(p.gamma);
+        p.xi0 += 0.5 * (1.0 - tau);
+        p.inv_tau = tau > 0.0 ? (float)(1.0 / tau) : 1e30f;
+      }
     }
     prm[tid] = p;
   }
@@ -281,18 +298,36 @@ __global__ __launch_bounds__(PTHREADS) void k_project(Src src) {
         }
         const int j = q + jo;
         const AngleParam& p = prm[a];
-        const float xi = (float)(p.xi0 + db * p.gamma + (double)j * p.beta);
-        const float g = p.g32;
         float s0 = 0.f, s1 = 0.f;
+        if (CHORD) {
+          // positions in float64: the weights are steep in the position near
+          // axis-aligned angles (slope 1 / |gamma|)
+          const double xd = p.xi0 + db * p.gamma + (double)j * p.beta;
+          const float inv = p.inv_tau;
 #pragma unroll
-        for (int i = 0; i < R; ++i) {
-          float xx = i == 0 ? xi : fmaf((float)i, g, xi);
-          float f = __builtin_amdgcn_fractf(xx);   // xx > 0: truncation is the floor
-          int c0 = (int)xx;
-          float v0 = band[i * B::LS + c0];
-          float v1 = band[i * B::LS + c0 + 1];
-          s0 += v0;
-          s1 = fmaf(f, v1 - v0, s1);
+          for (int i = 0; i < R; ++i) {
+            const double xx = i == 0 ? xd : fma((double)i, p.gamma, xd);
+            const int c0 = (int)xx;                           // xx > 0
+            const float q = (float)((double)(c0 + 1) - xx);   // in (0, 1]
+            const float f = fmaxf(0.f, fmaf(-q, inv, 1.f));
+            const float v0 = band[i * B::LS + c0];
+            const float v1 = band[i * B::LS + c0 + 1];
+            s0 += v0;
+            s1 = fmaf(f, v1 - v0, s1);
+          }
+        } else {
+          const float xi = (float)(p.xi0 + db * p.gamma + (double)j * p.beta);
+          const float g = p.g32;
+#pragma unroll
+          for (int i = 0; i < R; ++i) {
+            float xx = i == 0 ? xi : fmaf((float)i, g, xi);
+            float f = __builtin_amdgcn_fractf(xx);   // xx > 0: truncation is the floor
+            int c0 = (int)xx;
+            float v0 = band[i * B::LS + c0];
+            float v1 = band[i * B::LS + c0 + 1];
+            s0 += v0;
+            s1 = fmaf(f, v1 - v0, s1);
+          }
         }
         acc[a * PACC + j] += s0 + s1;
       }
@@ -343,7 +378,9 @@ __global__ __launch_bounds__(PTHREADS) void k_project_reduce(Src src) {
       int r0, c0, rh, rw;
       region_of(J, g, r0, c0, rh, rw);
       double th = J.ang[a0 + a];
-      bb = region_bbase(cos(th), sin(th), h, hb, r0, c0, rh, rw);
+      double cs, sn;
+      angle_trig(th, J.chord, cs, sn);
+      bb = region_bbase(cs, sn, h, hb, r0, c0, rh, rw);
     }
     fin_bbase[i] = bb;
   }
@@ -368,10 +405,14 @@ __global__ __launch_bounds__(PTHREADS) void k_project_reduce(Src src) {
   }
 }
 
-template __global__ void k_project<16, Single<ProjJob>>(Single<ProjJob>);
-template __global__ void k_project<16, Many<ProjJob>>(Many<ProjJob>);
-template __global__ void k_project<32, Single<ProjJob>>(Single<ProjJob>);
-template __global__ void k_project<32, Many<ProjJob>>(Many<ProjJob>);
+template __global__ void k_project<16, Single<ProjJob>, false>(Single<ProjJob>);
+template __global__ void k_project<16, Many<ProjJob>, false>(Many<ProjJob>);
+template __global__ void k_project<32, Single<ProjJob>, false>(Single<ProjJob>);
+template __global__ void k_project<32, Many<ProjJob>, false>(Many<ProjJob>);
+template __global__ void k_project<16, Single<ProjJob>, true>(Single<ProjJob>);
+template __global__ void k_project<16, Many<ProjJob>, true>(Many<ProjJob>);
+template __global__ void k_project<32, Single<ProjJob>, true>(Single<ProjJob>);
+template __global__ void k_project<32, Many<ProjJob>, true>(Many<ProjJob>);
 template __global__ void k_project_reduce<Single<ProjJob>>(Single<ProjJob>);
 template __global__ void k_project_reduce<Many<ProjJob>>(Many<ProjJob>);
 
