@@ -73,14 +73,16 @@ def _traffic(kernel: str, workload: str, tiles):
     return entry.get("hbm_bytes_per_launch") if entry else None
 
 
-def cpu_baseline(slices_info, sample_nodes):
+def cpu_baseline(slices_info, sample_nodes, model="joseph"):
     """The oracle's Alg. 2 local update (E1 steps of P and P^T) on a sample of
     nodes, timed on the host; returns ray-voxel updates/s and seconds."""
     import numpy as np
 
     import synthdata
     from oracle import admm as oadmm
-    from oracle import joseph
+    from oracle import chord, joseph
+
+    proj = chord if model == "chord" else joseph
 
     rng = np.random.default_rng(0)
     upd = 0
@@ -89,9 +91,10 @@ def cpu_baseline(slices_info, sample_nodes):
         th = synthdata.angles(w.n_angles)
         part = synthdata.partition_angles(w.n_angles, w.n_nodes, w.split)[m]
         truth = synthdata.phantom(w, si)
-        d = joseph.project(truth, th[part], w.n_bins)
+        d = proj.project(truth, th[part], w.n_bins)
         u = rng.random((w.n, w.n))
-        oadmm.local_update(u, np.zeros((w.n, w.n)), np.zeros((w.n, w.n)), d, th[part], 1.0, 1e-5, w.inner_iters)
+        oadmm.local_update(u, np.zeros((w.n, w.n)), np.zeros((w.n, w.n)), d, th[part], 1.0, 1e-5, w.inner_iters,
+                           proj=proj)
         upd += 2 * w.inner_iters * len(part) * w.n * w.n
     dt = time.perf_counter() - t0
     return upd / dt, dt
@@ -254,6 +257,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tiles", default=None,
                     help="projector choice instead of autotuning: BAND/JOB_WGS (band kernel) or 'resident'")
+    ap.add_argument("--model", default="joseph", choices=("joseph", "chord"),
+                    help="system matrix: Joseph interpolation (default) or the chord lengths of Eq. 2")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only launch the projector and backprojector of the workload a few times, and a "
@@ -280,6 +285,8 @@ def main():
 
     torch.cuda.set_device(0)
     ctx = T.Context(0)
+    if args.model == "chord":
+        T.tomo_set_option(ctx, T.TOMO_OPT_PROJ_MODEL, 1)
     if args.workload == "diff":
         return bench_diff(args, steps, ctx, log)
     t_setup = time.perf_counter()
@@ -305,7 +312,7 @@ def main():
     elif args.no_autotune:
         tiles = {"kernel": 0, "band": 32, "job_wgs": 16}       # the context's defaults
     else:
-        choice = autotune.tune(ctx, run.nodes)
+        choice = autotune.tune(ctx, run.nodes, resident=args.model == "joseph")
         tiles = {"kernel": choice["kernel"], "band": choice["band"], "job_wgs": choice["job_wgs"]}
         kind = ("region-resident kernel" if choice["kernel"] == 1 else
                 f"band kernel, band {choice['band']}, {choice['job_wgs']} workgroups per node")
@@ -402,14 +409,14 @@ def main():
     dom = max(kern, key=kern.get)
     dur_s = kern[dom] * 1e-3
     achieved = ALGO_FLOPS_PER_UPDATE * upd_per_launch / dur_s / 1e12
-    traffic = _traffic(dom, args.workload, tiles)
+    traffic = _traffic(dom, args.workload, tiles) if args.model == "joseph" else None
     log("phases: " + ", ".join(f"{k} {v * 1e3:.1f} us ({upd_per_launch / (v * 1e-3):.3g} upd/s)"
                                 for k, v in kern.items()))
 
     cpu = None
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle local update on {sample_desc} ...")
-        v_cpu, dt = cpu_baseline(ws, sample)
+        v_cpu, dt = cpu_baseline(ws, sample, args.model)
         cpu = {"value": v_cpu, "unit": "updates/s", "cores": 1, "kind": "oracle",
                "sample": f"Alg. 2 local update (E1=5: P and P^T) of {sample_desc}, float64 NumPy, {dt:.1f} s"}
 
@@ -431,7 +438,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": dict({"workload": desc}, **cfg),
+        "config": dict({"workload": desc}, **cfg, system_matrix=args.model),
         "admm_iters_per_s": {"batched_graph": n_slices * 1e3 / ms_per_step, "plain_loop": n_slices / plain_s,
                              "unit": "slice-iterations/s"},
         "equal_rmse": {"iterations": n_eq, "bit_identical": identical, "max_rel_rmse_diff": max(rel),

@@ -56,11 +56,13 @@ def apply(ctx, choice: dict):
     T.tomo_set_option(ctx, T.TOMO_OPT_PROJ_JOB_WGS, int(choice["job_wgs"]))
 
 
-def tune(ctx, nodes, cache_path: str | None = None, reps: int = 5, bands=BANDS, job_wgs=JOB_WGS) -> dict:
+def tune(ctx, nodes, cache_path: str | None = None, reps: int = 5, bands=BANDS, job_wgs=JOB_WGS,
+         resident: bool = True) -> dict:
     """Pick and set the fastest projector (kernel, band, job_wgs) for ``nodes``
-    (a ``make_nodes`` array).  Returns {"kernel", "band", "job_wgs", "us",
-    "tried": {...}, "cached": bool}."""
-    key = signature(nodes)
+    (a ``make_nodes`` array).  ``resident`` offers the region-resident kernel too
+    (it serves the Joseph model only).  Returns {"kernel", "band", "job_wgs",
+    "us", "tried": {...}, "cached": bool}."""
+    key = signature(nodes) + ("" if resident else "|band-only")
     cache = {}
     if cache_path and os.path.exists(cache_path):
         with open(cache_path) as fh:
@@ -74,7 +76,7 @@ def tune(ctx, nodes, cache_path: str | None = None, reps: int = 5, bands=BANDS, 
         for jw in job_wgs:
             apply(ctx, {"kernel": 0, "band": band, "job_wgs": jw})
             tried[f"0/{band}/{jw}"] = _time_phase(ctx, nodes, reps)
-    if all(int(nd.g.n) <= MAX_RESIDENT_N for nd in nodes):
+    if resident and all(int(nd.g.n) <= MAX_RESIDENT_N for nd in nodes):
         apply(ctx, {"kernel": 1, "band": bands[-1], "job_wgs": job_wgs[0]})
         tried[f"1/{bands[-1]}/{job_wgs[0]}"] = _time_phase(ctx, nodes, reps)
     best = min(tried, key=tried.get)

@@ -48,7 +48,6 @@ struct AngleParam {
   float scale;    // path length per step: 1/|cos| or 1/|sin|
   int cls;        // 0 row-driven, 1 column-driven, -1 inactive
   int bbase;      // detector bin of ray j = 0 for this region
-  float inv_tau;  // chord lengths: 1 / |gamma| (1e30 for an axis-aligned angle)
 };
 
 // Lowest bin whose ray can meet a pixel of the region: floor of the smallest
@@ -77,6 +76,7 @@ __global__ __launch_bounds__(PTHREADS) void k_project(Src src) {
   __shared__ __align__(16) float band[R * B::LS];
   __shared__ float acc[PA * PACC];
   __shared__ AngleParam prm[PA];
+  __shared__ float inv_tau[CHORD ? PA : 1];   // chord lengths: 1 / |gamma| (1e30 when axis-aligned)
 
   int lid;
   const ProjJob J = src.get(blockIdx.x, lid);
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(PTHREADS) void k_project(Src src) {
     p.xi0 = p.beta = p.gamma = p.rlo0 = p.rhi0 = p.rsl = 0.0;
     p.scale = p.g32 = 0.f;
     p.bbase = 0;
-    p.inv_tau = 0.f;
+    float it = 0.f;
     if (tid < na) {
       double cs, sn;
       angle_trig(J.ang[a0 + tid], CHORD, cs, sn);
@@ -139,10 +139,11 @@ __global__ __launch_bounds__(PTHREADS) void k_project(Src src) {
         // q = the distance from that point to the next sample boundary
         const double tau = fabs(p.gamma);
         p.xi0 += 0.5 * (1.0 - tau);
-        p.inv_tau = tau > 0.0 ? (float)(1.0 / tau) : 1e30f;
+        it = tau > 0.0 ? (float)(1.0 / tau) : 1e30f;
       }
     }
     prm[tid] = p;
+    if (CHORD) inv_tau[tid] = it;
   }
   for (int i = tid; i < PA * PACC; i += PTHREADS) acc[i] = 0.f;
   __syncthreads();
@@ -303,7 +304,7 @@ __global__ __launch_bounds__(PTHREADS) void k_project(Src src) {
           // positions in float64: the weights are steep in the position near
           // axis-aligned angles (slope 1 / |gamma|)
           const double xd = p.xi0 + db * p.gamma + (double)j * p.beta;
-          const float inv = p.inv_tau;
+          const float inv = inv_tau[a];
 #pragma unroll
           for (int i = 0; i < R; ++i) {
             const double xx = i == 0 ? xd : fma((double)i, p.gamma, xd);

@@ -227,6 +227,8 @@ def main(argv=None):
     ap.add_argument("--iters", type=int, default=None, help="outer iterations (default: the workload's)")
     ap.add_argument("--nsd", type=float, default=0.0, help="noise of the ctr and elbow studies, percent")
     ap.add_argument("--json", default=None, help="write every run, traces included, to this file")
+    ap.add_argument("--model", default="joseph", choices=("joseph", "chord"),
+                    help="system matrix: Joseph interpolation or the chord lengths of Eq. 2")
     args = ap.parse_args(argv)
     if not torch.cuda.is_available():
         sys.exit("experiments: no GPU visible; this module runs the library's kernels only")
@@ -237,10 +239,12 @@ def main(argv=None):
                                 n_bins=math.ceil(math.sqrt(2.0) * args.n))
     iters = args.iters or w.outer_iters
     ctx = T.Context()
+    if args.model == "chord":
+        T.tomo_set_option(ctx, T.TOMO_OPT_PROJ_MODEL, 1)
     runs = []
     for name in (sorted(STUDIES) if args.study == "all" else [args.study]):
-        print(f"== {name}: {w.n}x{w.n}, {w.n_angles} angles, {w.n_bins} bins, up to {iters} iterations",
-              flush=True)
+        print(f"== {name}: {w.n}x{w.n}, {w.n_angles} angles, {w.n_bins} bins, up to {iters} iterations, "
+              f"{args.model} system matrix", flush=True)
         kw = {} if name == "noise" else {"nsd": args.nsd}
         res = STUDIES[name](ctx, w, iters, **kw)
         print(table(res), flush=True)
