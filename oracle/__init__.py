@@ -21,6 +21,8 @@ dct       "standard JPEG" quantizer: 8x8 orthonormal DCT-II with the luminance
           table scaled to a quality factor (no entropy coding).
 metrics   Eq. 25-27 (RMSE, PSNR, NSD) and Eq. 19-20 (memory and communication).
 wire      the K-means message on the wire: labels packed at ceil(log2 K) bits.
+entropy   the DCT message on the wire: zigzag run-length codes with Exp-Golomb
+          numbers and restart intervals of 64 blocks.
 stepsize  power iteration for the step size of Alg. 2.
 
 Parity status: every function is pinned by a ``-m "not gpu"`` test in
