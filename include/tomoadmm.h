@@ -253,6 +253,41 @@ int tomo_unpack_labels(tomo_ctx* ctx, const uint32_t* packed, int64_t n, int32_t
                        const float* centroids, int32_t k, uint8_t* labels, float* a_hat, void* stream);
 
 /*
+ * Entropy code of DCT codes (the DCT message on the wire, Section 2.6 / Eq. 20):
+ * 8x8 blocks in row-major order; in a block the 64 int16 codes in zigzag order
+ * (the scan order of baseline JPEG); the DC code sent as the difference from
+ * the previous block's DC, differenced from 0 at the first block of every
+ * restart interval of 64 blocks; the AC codes as pairs EG(zeros skipped + 1),
+ * EG(2(|v| - 1) + (v < 0)) for every nonzero v, then EG(0) for the end of the
+ * block; DC difference d as EG(2d) (d >= 0) or EG(-2d - 1) (d < 0).  EG(x) is
+ * the order-0 Exp-Golomb code: floor(log2(x+1)) zero bits, then x + 1 in
+ * binary.  Bits are packed most significant first: stream bit j is bit
+ * 31 - (j mod 32) of words[j / 32]; unused bits are zero.
+ *   coeffs: int16 [rows][ld] (row r, column c = coefficient (r mod 8, c mod 8)
+ *   of block (r / 8, c / 8), as quantize_dct writes them); rows, cols
+ *   multiples of 8.
+ * tomo_dct_encode writes words (capacity max_words >= tomo_dct_encode_words,
+ * all of it overwritten), restart: uint32 [ceil(blocks / 64)] bit offset of
+ * each interval, and *total_bits (device uint32).  A message is the words in
+ * use, the restart table and the level-map range: 4 ceil(total / 32) +
+ * 4 ceil(blocks / 64) + 8 bytes.  Block offsets live in a context workspace
+ * (4 bytes per block, allocated on first need).
+ * tomo_dct_decode writes coeffs back from words[n_words], restart and
+ * *total_bits (device), one thread per interval; a malformed stream ORs 1
+ * into *status (device int32, nullable; it is not cleared).
+ * Errors: TOMO_EINVAL for sizes that are not positive multiples of 8,
+ * ld < cols, a null pointer, too small a words capacity or overlapping
+ * arrays; TOMO_EUNSUPPORTED when blocks * 2302 >= 2^32.
+ */
+int64_t tomo_dct_encode_words(int32_t rows, int32_t cols);   /* ceil(blocks * 2302 / 32); 0 if invalid */
+int tomo_dct_encode(tomo_ctx* ctx, const int16_t* coeffs, int32_t rows, int32_t cols, int32_t ld,
+                    uint32_t* words, int64_t max_words, uint32_t* restart, uint32_t* total_bits,
+                    void* stream);
+int tomo_dct_decode(tomo_ctx* ctx, const uint32_t* words, int64_t n_words, const uint32_t* restart,
+                    const uint32_t* total_bits, int32_t rows, int32_t cols, int32_t ld, int16_t* coeffs,
+                    int32_t* status, void* stream);
+
+/*
  * JPEG-style quantizer of a float32 matrix a[rows][cols] with leading dimension
  * ld (elements): per-matrix level map v = (a-lo)*255/(hi-lo) - 128, orthonormal
  * 8x8 DCT-II per block, codes = round-half-even(F / Qs) with Qs the ITU-T T.81

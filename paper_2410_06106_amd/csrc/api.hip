@@ -25,6 +25,12 @@ __global__ void k_avg(Many<AvgJob>, const NodeRef*);
 __global__ void k_dual(Many<NodeRef>);
 __global__ void k_sqdiff(const float*, const float*, long long, double*);
 __global__ void k_pack_labels(const uint8_t*, int, int, unsigned*, long long);
+__global__ void k_ecode_bits(const int16_t*, int, int, int, unsigned*);
+__global__ void k_ecode_scan(unsigned*, int, unsigned*, unsigned*);
+__global__ void k_ecode_zero(unsigned*, long long);
+__global__ void k_ecode_write(const int16_t*, int, int, int, const unsigned*, unsigned*);
+__global__ void k_ecode_decode(const unsigned*, long long, const unsigned*, const unsigned*, int, int, int16_t*, int,
+                               int*);
 __global__ void k_unpack_labels(const unsigned*, int, int, const float*, int, uint8_t*, float*);
 }  // namespace tomo
 
@@ -150,6 +156,7 @@ struct tomo_ctx {
   DevBuf partial;                                // standalone projector workspace
   DevBuf km_work;                                // standalone K-means workspace
   DevBuf ctr_resid;                              // residual of tomo_ctr_gd
+  DevBuf ecode_off;                              // block offsets of tomo_dct_encode
   std::vector<std::unique_ptr<LocalPlan>> lplans;
   std::vector<std::unique_ptr<ConsPlan>> cplans;
   std::unordered_multimap<uint64_t, LocalPlan*> lindex;   // hash of the node array -> plan
@@ -809,6 +816,56 @@ int tomo_unpack_labels(tomo_ctx* ctx, const uint32_t* packed, int64_t n, int32_t
   hipLaunchKernelGGL(k_unpack_labels, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, packed,
                      (int)n, bits, centroids, a_hat ? k : 1, labels, a_hat);
   return launch_status(ctx, "tomo_unpack_labels");
+}
+
+int64_t tomo_dct_encode_words(int32_t rows, int32_t cols) {
+  if (rows <= 0 || cols <= 0 || rows % 8 || cols % 8) return 0;
+  const int64_t blocks = (int64_t)(rows / 8) * (cols / 8);
+  return (blocks * ECODE_MAX_BITS + 31) / 32;
+}
+
+int tomo_dct_encode(tomo_ctx* ctx, const int16_t* coeffs, int32_t rows, int32_t cols, int32_t ld, uint32_t* words,
+                    int64_t max_words, uint32_t* restart, uint32_t* total_bits, void* stream) {
+  if (!ctx) return TOMO_EINVAL;
+  if (rows <= 0 || cols <= 0 || rows % 8 || cols % 8 || ld < cols)
+    return ctx->fail(TOMO_EINVAL, "rows and cols must be positive multiples of 8 and ld >= cols");
+  if (!coeffs || !words || !restart || !total_bits) return ctx->fail(TOMO_EINVAL, "null pointer");
+  const int64_t blocks = (int64_t)(rows / 8) * (cols / 8);
+  if (blocks * ECODE_MAX_BITS >= (int64_t(1) << 32))
+    return ctx->fail(TOMO_EUNSUPPORTED, "segment too large for 32-bit bit offsets");
+  const int64_t need = tomo_dct_encode_words(rows, cols);
+  if (max_words < need) return ctx->fail(TOMO_EINVAL, "words holds fewer than tomo_dct_encode_words(rows, cols)");
+  if (overlaps(coeffs, (size_t)rows * ld * 2, words, (size_t)need * 4))
+    return ctx->fail(TOMO_EINVAL, "coeffs and words overlap");
+  if (int rc = set_device(ctx)) return rc;
+  if (!ctx->ecode_off.ensure((size_t)blocks * 4)) return ctx->fail(TOMO_ENOMEM, "workspace");
+  unsigned* off = static_cast<unsigned*>(ctx->ecode_off.p);
+  const int nb = (int)blocks, n_bc = cols / 8, grid = (nb + 255) / 256;
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_ecode_zero, dim3((unsigned)std::min<int64_t>((need + 255) / 256, 4096)), dim3(256), 0, s, words,
+                     (long long)need);
+  hipLaunchKernelGGL(k_ecode_bits, dim3(grid), dim3(256), 0, s, coeffs, ld, n_bc, nb, off);
+  hipLaunchKernelGGL(k_ecode_scan, dim3(1), dim3(1024), 0, s, off, nb, restart, total_bits);
+  hipLaunchKernelGGL(k_ecode_write, dim3(grid), dim3(256), 0, s, coeffs, ld, n_bc, nb, off, words);
+  return launch_status(ctx, "tomo_dct_encode");
+}
+
+int tomo_dct_decode(tomo_ctx* ctx, const uint32_t* words, int64_t n_words, const uint32_t* restart,
+                    const uint32_t* total_bits, int32_t rows, int32_t cols, int32_t ld, int16_t* coeffs,
+                    int32_t* status, void* stream) {
+  if (!ctx) return TOMO_EINVAL;
+  if (rows <= 0 || cols <= 0 || rows % 8 || cols % 8 || ld < cols)
+    return ctx->fail(TOMO_EINVAL, "rows and cols must be positive multiples of 8 and ld >= cols");
+  if (!words || !restart || !total_bits || !coeffs) return ctx->fail(TOMO_EINVAL, "null pointer");
+  if (n_words < 0) return ctx->fail(TOMO_EINVAL, "n_words < 0");
+  if (overlaps(coeffs, (size_t)rows * ld * 2, words, (size_t)n_words * 4))
+    return ctx->fail(TOMO_EINVAL, "coeffs and words overlap");
+  if (int rc = set_device(ctx)) return rc;
+  const int64_t blocks = (int64_t)(rows / 8) * (cols / 8);
+  const int64_t intervals = (blocks + ECODE_INTERVAL - 1) / ECODE_INTERVAL;
+  hipLaunchKernelGGL(k_ecode_decode, dim3((unsigned)((intervals + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                     words, (long long)n_words, restart, total_bits, cols / 8, (int)blocks, coeffs, ld, status);
+  return launch_status(ctx, "tomo_dct_decode");
 }
 
 int tomo_sqdiff(tomo_ctx* ctx, const float* a, const float* b, int64_t n, double* out, void* stream) {

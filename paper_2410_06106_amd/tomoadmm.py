@@ -27,7 +27,8 @@ TOMO_OPT_PROJ_JOB_WGS, TOMO_OPT_PROJ_BAND, TOMO_OPT_PROJ_KERNEL, TOMO_OPT_PROJ_M
 EXPORTED = ("tomo_create", "tomo_destroy", "tomo_status_string", "tomo_last_error", "tomo_set_option",
             "tomo_project",
             "tomo_backproject", "tomo_ctr_gd", "admm_local_update", "admm_local_phase", "admm_consensus",
-            "quantize_kmeans", "quantize_dct", "tomo_pack_labels", "tomo_unpack_labels", "tomo_sqdiff")
+            "quantize_kmeans", "quantize_dct", "tomo_pack_labels", "tomo_unpack_labels",
+            "tomo_dct_encode_words", "tomo_dct_encode", "tomo_dct_decode", "tomo_sqdiff")
 
 
 class TomoError(RuntimeError):
@@ -79,6 +80,12 @@ _lib.quantize_dct.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_i
                               _P, _P, _P, _P]
 _lib.tomo_sqdiff.argtypes = [_P, _P, _P, ctypes.c_int64, _P, _P]
 _lib.tomo_pack_labels.argtypes = [_P, _P, ctypes.c_int64, ctypes.c_int32, _P, _P]
+_lib.tomo_dct_encode_words.argtypes = [ctypes.c_int32, ctypes.c_int32]
+_lib.tomo_dct_encode_words.restype = ctypes.c_int64
+_lib.tomo_dct_encode.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int64, _P, _P,
+                                 _P]
+_lib.tomo_dct_decode.argtypes = [_P, _P, ctypes.c_int64, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P,
+                                 _P, _P]
 _lib.tomo_unpack_labels.argtypes = [_P, _P, ctypes.c_int64, ctypes.c_int32, _P, ctypes.c_int32, _P, _P, _P]
 
 
@@ -264,6 +271,37 @@ def tomo_unpack_labels(ctx: Context, packed, n: int, bits: int, centroids=None, 
                                  _stream(stream))
     ctx.check(rc, "tomo_unpack_labels")
     return labels, a_hat
+
+
+def tomo_dct_encode_words(rows: int, cols: int) -> int:
+    return int(_lib.tomo_dct_encode_words(int(rows), int(cols)))
+
+
+def tomo_dct_encode(ctx: Context, coeffs, stream=None):
+    """Entropy-code int16 DCT codes [rows][cols]; returns (words, restart, total_bits)
+    as int32 tensors holding uint32 bit patterns (total_bits on the device, [1])."""
+    rows, cols = coeffs.shape
+    cap = tomo_dct_encode_words(rows, cols)
+    blocks = (rows // 8) * (cols // 8)
+    words = torch.empty(max(cap, 1), dtype=torch.int32, device=coeffs.device)
+    restart = torch.empty(max((blocks + 63) // 64, 1), dtype=torch.int32, device=coeffs.device)
+    total = torch.empty(1, dtype=torch.int32, device=coeffs.device)
+    rc = _lib.tomo_dct_encode(ctx.handle, _dev(coeffs, torch.int16, "coeffs"), rows, cols, cols,
+                              _dev(words, torch.int32, "words"), words.numel(), _dev(restart, torch.int32, "restart"),
+                              _dev(total, torch.int32, "total_bits"), _stream(stream))
+    ctx.check(rc, "tomo_dct_encode")
+    return words, restart, total
+
+
+def tomo_dct_decode(ctx: Context, words, restart, total, rows: int, cols: int, out=None, status=None, stream=None):
+    if out is None:
+        out = torch.empty((rows, cols), dtype=torch.int16, device=words.device)
+    rc = _lib.tomo_dct_decode(ctx.handle, _dev(words, torch.int32, "words"), words.numel(),
+                              _dev(restart, torch.int32, "restart"), _dev(total, torch.int32, "total_bits"),
+                              int(rows), int(cols), int(cols), _dev(out, torch.int16, "coeffs", (rows, cols)),
+                              _opt(status, torch.int32, "status", (1,)), _stream(stream))
+    ctx.check(rc, "tomo_dct_decode")
+    return out
 
 
 def tomo_sqdiff(ctx: Context, a, b, out=None, stream=None):
