@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "common.h"
+#include "codec.h"
 #include "../../include/tomoadmm.h"
 
 namespace tomo {

@@ -50,8 +50,6 @@ constexpr int PTHREADS = 256;
 
 // Region-resident projector: 128 x 128 regions held in LDS for all angles of
 // a node; one workgroup per region, partials [n_ang][G][QACC].
-constexpr int ECODE_INTERVAL = 64;     // DCT entropy code: blocks per restart interval
-constexpr int ECODE_MAX_BITS = 2302;   // longest code of one block: DC 33 + 63 x (3 + 33) + 1 bits
 constexpr int QR = 128;        // region side
 constexpr int QOFF = 2;        // zero samples before each LDS line
 constexpr int QLS = QR + 4;    // LDS line stride (zero samples on both sides)

@@ -12,6 +12,7 @@
 // with atomic ORs (a block shares its first and last words with its
 // neighbours).  Decoding runs one thread per restart interval.
 #include "common.h"
+#include "codec.h"
 
 namespace tomo {
 

@@ -7,9 +7,9 @@
             several quality factors;
 * Fig. 6-7  robustness to Gaussian measurement noise given as NSD (Eq. 27);
 * Eq. 20    per-node traffic of each run from its real messages (K-means
-            labels packed by ``tomo_pack_labels`` plus the codebook; float32
-            segments without quantizer; the codes' entropy for DCT) next to
-            the formula.
+            labels packed by ``tomo_pack_labels`` plus the codebook; DCT codes
+            entropy-coded by ``tomo_dct_encode``; float32 segments without
+            quantizer) next to the formula.
 
 Every iteration runs in the library's kernels (projector pair, consensus,
 quantizers, the centralized step) through the same batched driver as the
@@ -157,12 +157,15 @@ def run_dadmm(ctx, w, truth, d, quant: str = "none", level: int = 0, iters: int 
     sec = time.perf_counter() - t0
     rows = [r for _, r in s.segments]
     if quant == "dct":
-        # zeroth-order entropy of the last exchange's codes: the bits per value
-        # an entropy coder would approach (no entropy coder is built)
-        _, counts = torch.unique(torch.cat([cf.reshape(-1) for cf in coeffs]), return_counts=True)
-        p = counts.double() / counts.sum()
-        bits = float(-(p * torch.log2(p)).sum())
-        msg = [math.ceil(bits * r * w.n / 8) + 8 for r in rows]          # codes + the level-map range
+        # the wire format: the last exchange's codes entropy-coded by
+        # tomo_dct_encode, plus the restart table and the level-map range
+        msg = []
+        for cf, r in zip(coeffs, rows):
+            _, _, total = T.tomo_dct_encode(ctx, cf)
+            tb = int(total.item()) & 0xFFFFFFFF
+            blocks = (r // 8) * (w.n // 8)
+            msg.append(4 * ((tb + 31) // 32) + 4 * ((blocks + 63) // 64) + 8)
+        bits = 8.0 * sum(msg) / (w.n * w.n)
     elif quant == "kmeans":
         # the wire format: labels packed at ceil(log2 K) bits plus the codebook
         msg = [4 * T.tomo_pack_labels(ctx, lb, int(bits)).numel() + 4 * level for lb in labels]

@@ -96,6 +96,10 @@ def test_dadmm_dct_runs_match_oracle(E, ctx):
     log(f"  gpu {np.array(run.trace)} oracle {want}")
     np.testing.assert_allclose(run.trace, want, rtol=1e-3)
     assert 0.0 < run.bits_per_value < 16.0
+    # traffic from the entropy-coded messages: at least the restart tables and ranges
+    # two nodes: each sends its message and receives the other's, so the traffic
+    # is both messages, which is what bits_per_value counts over the image
+    assert run.traffic_bytes == pytest.approx(run.bits_per_value * 64 * 64 / 8, rel=1e-12)
 
 
 def test_ctr_run_matches_oracle(E, ctx):
