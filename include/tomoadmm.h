@@ -58,6 +58,16 @@ int tomo_destroy(tomo_ctx* ctx);
 const char* tomo_status_string(int status);
 /* Text of the latest error recorded on `ctx` ("" if none). */
 const char* tomo_last_error(const tomo_ctx* ctx);
+/*
+ * Free the context's cached plans (one per node list seen by
+ * admm_local_update / admm_consensus, kept so later calls and captured graphs
+ * reuse them) and its standalone workspaces.  Waits for the device first.
+ * Graphs captured before this call must not be replayed afterwards; the next
+ * call of each kind allocates again.  Workspaces otherwise only grow: an
+ * allocation a larger request replaces is kept until tomo_release or
+ * tomo_destroy, so earlier captured graphs stay valid.
+ */
+int tomo_release(tomo_ctx* ctx);
 
 /*
  * Launch-shape options of a context (the tile choices an autotuner varies).

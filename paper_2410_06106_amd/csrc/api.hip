@@ -44,16 +44,32 @@ namespace {
 
 constexpr int kMaxRegions = PMAXREG;  // regions per projector job (finalizer table size)
 
+// Device buffer that only grows.  A smaller allocation it replaces is kept
+// until release() or destruction, so work captured into a graph earlier still
+// finds its memory.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
-  ~DevBuf() { if (p) (void)hipFree(p); }
+  std::vector<void*> old;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
   bool ensure(size_t want) {
     if (want <= bytes) return true;
-    if (p) { (void)hipFree(p); p = nullptr; bytes = 0; }
-    if (hipMalloc(&p, want) != hipSuccess) { p = nullptr; return false; }
+    void* q = nullptr;
+    if (hipMalloc(&q, want) != hipSuccess) return false;
+    if (p) old.push_back(p);
+    p = q;
     bytes = want;
     return true;
+  }
+  void release() {
+    for (void* q : old) (void)hipFree(q);
+    old.clear();
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
   }
 };
 
@@ -593,6 +609,20 @@ int tomo_set_option(tomo_ctx* ctx, int32_t option, int64_t value) {
   ctx->cplans.clear();
   ctx->lindex.clear();
   ctx->cindex.clear();
+  return TOMO_OK;
+}
+
+int tomo_release(tomo_ctx* ctx) {
+  if (!ctx) return TOMO_EINVAL;
+  if (int rc = set_device(ctx)) return rc;
+  if (hipDeviceSynchronize() != hipSuccess) return ctx->fail(TOMO_EDEVICE, "hipDeviceSynchronize failed");
+  ctx->lplans.clear();
+  ctx->cplans.clear();
+  ctx->retired_l.clear();
+  ctx->retired_c.clear();
+  ctx->lindex.clear();
+  ctx->cindex.clear();
+  for (DevBuf* b : {&ctx->partial, &ctx->km_work, &ctx->ctr_resid, &ctx->ecode_off}) b->release();
   return TOMO_OK;
 }
 

@@ -24,7 +24,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 TOMO_XUPDATE_SEGMENT, TOMO_XUPDATE_AVERAGE = 0, 1
 TOMO_QUANT_NONE, TOMO_QUANT_KMEANS, TOMO_QUANT_DCT = 0, 1, 2
 TOMO_OPT_PROJ_JOB_WGS, TOMO_OPT_PROJ_BAND, TOMO_OPT_PROJ_KERNEL, TOMO_OPT_PROJ_MODEL = 1, 3, 4, 5
-EXPORTED = ("tomo_create", "tomo_destroy", "tomo_status_string", "tomo_last_error", "tomo_set_option",
+EXPORTED = ("tomo_create", "tomo_destroy", "tomo_status_string", "tomo_last_error", "tomo_release", "tomo_set_option",
             "tomo_project",
             "tomo_backproject", "tomo_ctr_gd", "admm_local_update", "admm_local_phase", "admm_consensus",
             "quantize_kmeans", "quantize_dct", "tomo_pack_labels", "tomo_unpack_labels",
@@ -66,6 +66,7 @@ _lib.tomo_status_string.argtypes = [ctypes.c_int]
 _lib.tomo_status_string.restype = ctypes.c_char_p
 _lib.tomo_last_error.argtypes = [_P]
 _lib.tomo_last_error.restype = ctypes.c_char_p
+_lib.tomo_release.argtypes = [_P]
 _lib.tomo_set_option.argtypes = [_P, ctypes.c_int32, ctypes.c_int64]
 _lib.tomo_project.argtypes = [_P, tomo_geom, _P, ctypes.c_int32, _P, _P, _P]
 _lib.tomo_backproject.argtypes = [_P, tomo_geom, _P, ctypes.c_int32, _P, _P, ctypes.c_float,
@@ -151,6 +152,11 @@ def default_context(device: int | None = None) -> Context:
     if device not in _default_ctx:
         _default_ctx[device] = Context(device)
     return _default_ctx[device]
+
+
+def tomo_release(ctx: Context):
+    """Free the context's cached plans and workspaces (graphs captured earlier become invalid)."""
+    ctx.check(_lib.tomo_release(ctx.handle), "tomo_release")
 
 
 def tomo_set_option(ctx: Context, option: int, value: int):
