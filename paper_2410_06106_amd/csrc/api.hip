@@ -132,7 +132,7 @@ bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
 
 struct LocalPlan {
   std::vector<tomo_node> key;
-  DevBuf pjobs, rjobs, bjobs, resid, partial;
+  DevBuf pjobs, rjobs, bjobs, resid, partial, bbase;
   int n_p = 0, p_wgs = 0, n_r = 0, r_wgs = 0, n_b = 0, b_wgs = 0;
   int band = 16;                 // projector band depth (16 or 32)
   bool resident = false;         // region-resident projector (k_project_res)
@@ -171,6 +171,7 @@ struct tomo_ctx {
   int model = 0;              // TOMO_OPT_PROJ_MODEL (0 Joseph, 1 chord lengths)
   std::string err;
   DevBuf partial;                                // standalone projector workspace
+  DevBuf pbbase;                                 // standalone projector: region bin bases
   DevBuf km_work;                                // standalone K-means workspace
   DevBuf ctr_resid;                              // residual of tomo_ctr_gd
   DevBuf ecode_off;                              // block offsets of tomo_dct_encode
@@ -281,15 +282,22 @@ LocalPlan* get_local_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, in
       split_for_parallelism(shapes.back(), nodes[i].g.n, ctx->proj_job_wgs);
     }
   }
-  std::vector<size_t> roff(n_nodes), poff(n_nodes);
+  std::vector<size_t> roff(n_nodes), poff(n_nodes), boff(n_nodes);
+  size_t bb_elems = 0;
   for (int i = 0; i < n_nodes; ++i) {
     roff[i] = resid_elems;
     resid_elems += (size_t)nodes[i].n_ang * nodes[i].g.n_bins;
     poff[i] = part_elems;
-    if (resident) part_elems += (size_t)nodes[i].n_ang * shapes[i].regions() * QACC;
-    else if (shapes[i].regions() > 1) part_elems += (size_t)shapes[i].wgs() * PA * PACC;
+    boff[i] = bb_elems;
+    if (resident) {
+      part_elems += (size_t)nodes[i].n_ang * shapes[i].regions() * QACC;
+    } else if (shapes[i].regions() > 1) {
+      part_elems += (size_t)shapes[i].wgs() * PA * PACC;
+      bb_elems += (size_t)shapes[i].wgs() * PA;
+    }
   }
-  if (!plan->resid.ensure(resid_elems * 4) || !plan->partial.ensure(std::max<size_t>(part_elems, 1) * 4)) {
+  if (!plan->resid.ensure(resid_elems * 4) || !plan->partial.ensure(std::max<size_t>(part_elems, 1) * 4) ||
+      !plan->bbase.ensure(std::max<size_t>(bb_elems, 1) * 4)) {
     rc = ctx->fail(TOMO_ENOMEM, "plan workspace allocation failed");
     return nullptr;
   }
@@ -303,6 +311,7 @@ LocalPlan* get_local_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, in
     ProjJob j = make_proj_job(N.u, N.angles, N.d, R + roff[i], N.g.n, N.g.n_bins, N.n_ang, shapes[i]);
     j.chord = ctx->model;
     j.partial = PP + poff[i];
+    j.bbase = static_cast<int*>(plan->bbase.p) + boff[i];
     j.wg_begin = pw;
     pw += shapes[i].wgs();
     pj.push_back(j);
@@ -408,8 +417,10 @@ int project_one(tomo_ctx* ctx, tomo_geom g, const double* angles, int n_ang, con
   split_for_parallelism(sh, g.n, ctx->proj_job_wgs);
   ProjJob j = make_proj_job(img, angles, d, out, g.n, g.n_bins, n_ang, sh);
   if (sh.regions() > 1) {
-    if (!ctx->partial.ensure((size_t)sh.wgs() * PA * PACC * 4)) return ctx->fail(TOMO_ENOMEM, "workspace");
+    if (!ctx->partial.ensure((size_t)sh.wgs() * PA * PACC * 4) || !ctx->pbbase.ensure((size_t)sh.wgs() * PA * 4))
+      return ctx->fail(TOMO_ENOMEM, "workspace");
     j.partial = static_cast<float*>(ctx->partial.p);
+    j.bbase = static_cast<int*>(ctx->pbbase.p);
   }
   j.chord = ctx->model;
   const dim3 grid(sh.wgs()), block(PTHREADS);
@@ -622,7 +633,7 @@ int tomo_release(tomo_ctx* ctx) {
   ctx->retired_c.clear();
   ctx->lindex.clear();
   ctx->cindex.clear();
-  for (DevBuf* b : {&ctx->partial, &ctx->km_work, &ctx->ctr_resid, &ctx->ecode_off}) b->release();
+  for (DevBuf* b : {&ctx->partial, &ctx->pbbase, &ctx->km_work, &ctx->ctr_resid, &ctx->ecode_off}) b->release();
   return TOMO_OK;
 }
 

@@ -65,6 +65,7 @@ struct ProjJob {
   const float* d;       // [n_ang][nb] or null: out = scale * P img - d
   float* out;           // [n_ang][nb]
   float* partial;       // band kernel: [n_achunk][G][PA][PACC]; region-resident: [n_ang][G][QACC]
+  int* bbase;           // band kernel, G > 1: [n_achunk][G][PA] first bin of each region's partials
   int n, nb, n_ang;
   int n_achunk;
   int reg_h, reg_w;     // region size (<= PREG)

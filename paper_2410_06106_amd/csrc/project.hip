@@ -355,6 +355,7 @@ __global__ __launch_bounds__(PTHREADS) void k_project(Src src) {
     int a = i / PACC;
     part[i] = a < na ? acc[i] * prm[a].scale : 0.f;
   }
+  if (tid < PA) J.bbase[((size_t)achunk * G + region) * PA + tid] = prm[tid].bbase;
 }
 
 // Sum of the regions' partial ray sums, one thread per (angle chunk, bin):
@@ -371,37 +372,39 @@ __global__ __launch_bounds__(PTHREADS) void k_project_reduce(Src src) {
   const int b = (lid - achunk * nbb) * PTHREADS + threadIdx.x;
   const int a0 = achunk * PA;
   const int na = min(PA, J.n_ang - a0);
-  const double h = 0.5 * (J.n - 1), hb = 0.5 * (J.nb - 1);
-  for (int i = threadIdx.x; i < G * PA; i += PTHREADS) {
-    int g = i / PA, a = i - g * PA;
-    int bb = 0;
-    if (a < na) {
-      int r0, c0, rh, rw;
-      region_of(J, g, r0, c0, rh, rw);
-      double th = J.ang[a0 + a];
-      double cs, sn;
-      angle_trig(th, J.chord, cs, sn);
-      bb = region_bbase(cs, sn, h, hb, r0, c0, rh, rw);
-    }
-    fin_bbase[i] = bb;
-  }
+  // first bins of the regions' partials, as the projector computed them
+  const int* bb = J.bbase + (size_t)achunk * G * PA;
+  for (int i = threadIdx.x; i < G * PA; i += PTHREADS) fin_bbase[i] = bb[i];
   __syncthreads();
   if (b >= J.nb) return;
   const float* pbase = J.partial + (size_t)achunk * G * (PA * PACC);
+  // every region wrote all PA * PACC of its partials (zeros past its rays), so
+  // the loads are clamped into range and issued unconditionally, all of a
+  // region at once; the range test only selects what is added
   float s[PA] = {};
   for (int g = 0; g < G; ++g) {
+    float v[PA];
+    bool ok[PA];
 #pragma unroll
     for (int a = 0; a < PA; ++a) {
-      int j = b - fin_bbase[g * PA + a];
-      if (a < na && j >= 0 && j < PACC) s[a] += pbase[((size_t)g * PA + a) * PACC + j];
+      const int j = b - fin_bbase[g * PA + a];
+      ok[a] = j >= 0 && j < PACC;
+      v[a] = pbase[((size_t)g * PA + a) * PACC + min(max(j, 0), PACC - 1)];
     }
+#pragma unroll
+    for (int a = 0; a < PA; ++a)
+      if (ok[a]) s[a] += v[a];
+  }
+  float dv[PA] = {};
+  if (J.d) {
+#pragma unroll
+    for (int a = 0; a < PA; ++a) dv[a] = J.d[(size_t)(a0 + min(a, na - 1)) * J.nb + b];
   }
 #pragma unroll
   for (int a = 0; a < PA; ++a) {
     if (a < na) {
-      size_t o = (size_t)(a0 + a) * J.nb + b;
-      float v = s[a] * J.scale;
-      J.out[o] = J.d ? v - J.d[o] : v;
+      const float v = s[a] * J.scale;
+      J.out[(size_t)(a0 + a) * J.nb + b] = J.d ? v - dv[a] : v;
     }
   }
 }
