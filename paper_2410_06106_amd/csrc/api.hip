@@ -475,7 +475,7 @@ ConsPlan* get_cons_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, cons
     NodeRef r{};
     r.u = N.u; r.lam = N.lam; r.x = N.x; r.n = N.g.n; r.rho = N.rho;
     r.wg_begin = dw;
-    dw += (int)(((long long)N.g.n * N.g.n + 255) / 256);
+    dw += (int)(((long long)N.g.n * N.g.n + 1023) / 1024);      // k_dual: four values per thread
     refs.push_back(r);
     if (i == 0 || nodes[i - 1].slice != N.slice) {
       AvgJob a{};

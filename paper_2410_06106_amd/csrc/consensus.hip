@@ -202,14 +202,28 @@ __global__ __launch_bounds__(256) void k_avg(Many<AvgJob> src, const NodeRef* no
   A.x[i] = s / (float)A.n_nodes;
 }
 
-// Eq. 24 for every node: lambda_m += rho (u_m - x)
+// Eq. 24 for every node: lambda_m += rho (u_m - x); four values per thread,
+// as float4 when the three images are 16-byte aligned
 __global__ __launch_bounds__(256) void k_dual(Many<NodeRef> src) {
   int lid;
   const NodeRef R = src.get(blockIdx.x, lid);
-  const size_t i = (size_t)lid * 256 + threadIdx.x;
   const size_t cnt = (size_t)R.n * R.n;
-  if (i >= cnt) return;
-  R.lam[i] = fmaf(R.rho, R.u[i] - R.x[i], R.lam[i]);
+  const size_t i0 = ((size_t)lid * 256 + threadIdx.x) * 4;
+  if (i0 >= cnt) return;
+  const bool vec = ((reinterpret_cast<uintptr_t>(R.u) | reinterpret_cast<uintptr_t>(R.x) |
+                     reinterpret_cast<uintptr_t>(R.lam)) & 15) == 0;
+  if (vec && i0 + 4 <= cnt) {
+    const float4 u = *reinterpret_cast<const float4*>(R.u + i0);
+    const float4 x = *reinterpret_cast<const float4*>(R.x + i0);
+    float4 l = *reinterpret_cast<const float4*>(R.lam + i0);
+    l.x = fmaf(R.rho, u.x - x.x, l.x);
+    l.y = fmaf(R.rho, u.y - x.y, l.y);
+    l.z = fmaf(R.rho, u.z - x.z, l.z);
+    l.w = fmaf(R.rho, u.w - x.w, l.w);
+    *reinterpret_cast<float4*>(R.lam + i0) = l;
+  } else {
+    for (size_t i = i0; i < cnt && i < i0 + 4; ++i) R.lam[i] = fmaf(R.rho, R.u[i] - R.x[i], R.lam[i]);
+  }
 }
 
 // sum of squared differences in float64 (one workgroup, fixed reduction order)
