@@ -127,6 +127,35 @@ int tomo_backproject(tomo_ctx* ctx, tomo_geom g, const double* angles, int32_t n
                      const float* sino, float* image, float alpha, float beta, void* stream);
 
 /*
+ * Batches of independent projections / backprojections, one launch per kernel
+ * for the whole batch (for example the per-node operators of an unrolled,
+ * differentiated ADMM).  Each item has its own geometry, angles, image and
+ * sinogram:
+ *   tomo_project_many:      items[i].sino  = P_i items[i].image
+ *   tomo_backproject_many:  items[i].image = alpha P_i^T items[i].sino + beta items[i].image
+ * with the layouts of tomo_project.  Results are bit-identical to one
+ * tomo_project / tomo_backproject call per item.  Nothing is cached: every call
+ * builds the batch's job table on the host and copies it to the device on
+ * `stream` through pinned staging memory of the context (the item pointers
+ * may change from call to call, as they do in an autograd graph); because of
+ * that copy, do not capture these two calls into a HIP graph.
+ * Errors: TOMO_EINVAL for an empty list, an invalid item (geometry, n_ang < 1,
+ * null pointer) or an output overlapping any item's input or another output.
+ */
+typedef struct {
+  tomo_geom g;
+  const double* angles;   /* float64 [n_ang]                                   */
+  int32_t n_ang;          /* >= 1                                              */
+  int32_t reserved;       /* must be 0 (keeps the struct free of padding)       */
+  float* image;           /* float32 [n][n]                                    */
+  float* sino;            /* float32 [n_ang][n_bins]                           */
+} tomo_proj_item;
+
+int tomo_project_many(tomo_ctx* ctx, const tomo_proj_item* items, int32_t n_items, void* stream);
+int tomo_backproject_many(tomo_ctx* ctx, const tomo_proj_item* items, int32_t n_items, float alpha,
+                          float beta, void* stream);
+
+/*
  * Centralized tomographic reconstruction by gradient descent (Section 2.2,
  * Alg. 1, minimising 0.5 ||P u - d||^2 of Eq. 5):
  *   repeat `iters` times:  u <- u - eta * P^T (P u - d)

@@ -1,14 +1,20 @@
 """Differentiable decentralized ADMM.
 
-* ``Project``      torch.autograd.Function  s = P u  (Eq. 2-4); backward = P^T
-* ``Backproject``  torch.autograd.Function  u = P^T s;           backward = P
-Both run the hand-written gfx950 kernels through the C ABI (float32).
+* ``Project``          torch.autograd.Function  s = P u  (Eq. 2-4); backward = P^T
+* ``Backproject``      torch.autograd.Function  u = P^T s;           backward = P
+* ``ProjectMany``      the same for all nodes at once: U [M][n][n] -> the
+                       nodes' sinograms stacked along the angle axis, one
+                       launch (tomo_project_many); backward one launch of P^T
+* ``BackprojectMany``  its transpose
+All run the hand-written gfx950 kernels through the C ABI (float32).
 
 ``UnrolledADMM`` unrolls K iterations of Alg. 4 (without the quantizer, which
 has no useful gradient) with a learnable penalty rho_k and local step eta_k per
 iteration (2K scalars), and checkpoints the iterates (x, u_m, lambda_m) every
 ``ckpt`` iterations: only the checkpointed states are kept for the backward
-pass, the iterations in between are recomputed.
+pass, the iterations in between are recomputed.  The nodes' u_m and lambda_m
+are stacked into [M][n][n] tensors, so every operator and every elementwise
+step of an iteration is one launch for all nodes.
 """
 from __future__ import annotations
 
@@ -56,6 +62,61 @@ def backproject(tctx, sino, angles, n):
     return Backproject.apply(sino, angles, n, tctx)
 
 
+def _items(angles, images, sinos, sizes):
+    """tomo_proj_item array: node m's image images[m] and its rows of sinos."""
+    ents, row = [], 0
+    for m, (a, k) in enumerate(zip(angles, sizes)):
+        ents.append(dict(angles=a, image=images[m], sino=sinos[row:row + k]))
+        row += k
+    return T.make_items(ents)
+
+
+class ProjectMany(torch.autograd.Function):
+    @staticmethod
+    def forward(fctx, images, tctx, angles, n_bins):
+        images = images.contiguous()
+        sizes = [int(a.numel()) for a in angles]
+        sinos = torch.empty((sum(sizes), n_bins), dtype=torch.float32, device=images.device)
+        T.tomo_project_many(tctx, _items(angles, images, sinos, sizes))
+        fctx.tctx, fctx.angles, fctx.sizes, fctx.n = tctx, angles, sizes, images.shape[-1]
+        return sinos
+
+    @staticmethod
+    def backward(fctx, grad):
+        grad = grad.contiguous()
+        gi = torch.empty((len(fctx.angles), fctx.n, fctx.n), dtype=torch.float32, device=grad.device)
+        T.tomo_backproject_many(fctx.tctx, _items(fctx.angles, gi, grad, fctx.sizes), 1.0, 0.0)
+        return gi, None, None, None
+
+
+class BackprojectMany(torch.autograd.Function):
+    @staticmethod
+    def forward(fctx, sinos, tctx, angles, n):
+        sinos = sinos.contiguous()
+        sizes = [int(a.numel()) for a in angles]
+        images = torch.empty((len(angles), n, n), dtype=torch.float32, device=sinos.device)
+        T.tomo_backproject_many(tctx, _items(angles, images, sinos, sizes), 1.0, 0.0)
+        fctx.tctx, fctx.angles, fctx.sizes, fctx.n_bins = tctx, angles, sizes, sinos.shape[1]
+        return images
+
+    @staticmethod
+    def backward(fctx, grad):
+        grad = grad.contiguous()
+        out = torch.empty((sum(fctx.sizes), fctx.n_bins), dtype=torch.float32, device=grad.device)
+        T.tomo_project_many(fctx.tctx, _items(fctx.angles, grad, out, fctx.sizes))
+        return out, None, None, None
+
+
+def project_many(tctx, images, angles, n_bins):
+    """images [M][n][n] -> sinograms of all nodes stacked along the angle axis."""
+    return ProjectMany.apply(images, tctx, angles, n_bins)
+
+
+def backproject_many(tctx, sinos, angles, n):
+    """Stacked sinograms -> [M][n][n] backprojections."""
+    return BackprojectMany.apply(sinos, tctx, angles, n)
+
+
 class UnrolledADMM(torch.nn.Module):
     """K unrolled iterations of Alg. 4 with learnable (rho_k, eta_k).
 
@@ -72,53 +133,55 @@ class UnrolledADMM(torch.nn.Module):
         self.iters, self.e1, self.e2, self.eta2, self.mode, self.ckpt = iters, e1, e2, eta2, mode, ckpt
         self.log_rho = torch.nn.Parameter(torch.full((iters,), float(torch.log(torch.tensor(rho0)))))
         self.log_eta = torch.nn.Parameter(torch.full((iters,), float(torch.log(torch.tensor(eta0)))))
+        # owner node of every image row (segments are disjoint row strips covering x)
+        owner = torch.empty(n, dtype=torch.long)
+        for m, (r0, nr) in enumerate(segments):
+            owner[r0:r0 + nr] = m
+        self.owner = owner
+        self.rows = torch.arange(n)
 
-    def _iteration(self, k, d, x, us, lams):
+    def _iteration(self, k, D, x, U, L):
+        """One iteration for all nodes: U, L [M][n][n], D the stacked data."""
         rho = torch.exp(self.log_rho[k])
         eta = torch.exp(self.log_eta[k])
-        new_u = []
-        for m, a in enumerate(self.angles):
-            u = us[m]
-            for _ in range(self.e1):                                   # Alg. 2
-                r = project(self.tctx, u, a, self.n_bins) - d[m]
-                g = backproject(self.tctx, r, a, self.n) + rho * (u - x) + lams[m]
-                u = u - eta * g
-            new_u.append(u)
-        if self.mode == "seg":                                          # Alg. 3
-            parts = []
-            for m, (r0, nr) in enumerate(self.segments):
-                xs = x[r0:r0 + nr]
-                t = new_u[m][r0:r0 + nr] + lams[m][r0:r0 + nr] / rho
-                for _ in range(self.e2):
-                    xs = xs - self.eta2 * rho * (xs - t)
-                parts.append(xs)
-            x_new = torch.cat(parts, dim=0)                             # Eq. 17
+        for _ in range(self.e1):                                                # Alg. 2
+            R = project_many(self.tctx, U, self.angles, self.n_bins) - D
+            G = backproject_many(self.tctx, R, self.angles, self.n) + rho * (U - x) + L
+            U = U - eta * G
+        if self.mode == "seg":                                                  # Alg. 3
+            # row r of x belongs to the node whose segment holds it
+            t = (U + L / rho)[self.owner, self.rows]
+            xs = x
+            for _ in range(self.e2):
+                xs = xs - self.eta2 * rho * (xs - t)
+            x_new = xs                                                          # Eq. 17
         else:
-            x_new = sum(u + l / rho for u, l in zip(new_u, lams)) / len(new_u)   # Eq. 9
-        new_l = [l + rho * (u - x_new) for u, l in zip(new_u, lams)]    # Eq. 18
-        return x_new, new_u, new_l
+            x_new = (U + L / rho).sum(dim=0) / U.shape[0]                       # Eq. 9
+        L = L + rho * (U - x_new)                                               # Eq. 18
+        return x_new, U, L
 
-    def _segment(self, k0, k1, d, x, *state):
-        m = len(self.angles)
-        us, lams = list(state[:m]), list(state[m:])
+    def _segment(self, k0, k1, D, x, U, L):
         for k in range(k0, k1):
-            x, us, lams = self._iteration(k, d, x, us, lams)
-        return (x, *us, *lams)
+            x, U, L = self._iteration(k, D, x, U, L)
+        return x, U, L
 
     def forward(self, d):
         """d: list of per-node sinograms (float32 cuda).  Returns x after K iterations."""
         n, dev = self.n, d[0].device
         m = len(self.angles)
+        D = torch.cat([di.reshape(-1, self.n_bins) for di in d], dim=0)
+        if self.owner.device != dev:
+            self.owner, self.rows = self.owner.to(dev), self.rows.to(dev)
         x = torch.zeros((n, n), device=dev)
-        state = [torch.zeros((n, n), device=dev) for _ in range(2 * m)]
+        U = torch.zeros((m, n, n), device=dev)
+        L = torch.zeros((m, n, n), device=dev)
         span = self.ckpt if self.ckpt > 0 else self.iters
         k = 0
         while k < self.iters:
             k1 = min(self.iters, k + span)
             if self.ckpt > 0 and torch.is_grad_enabled():
-                out = checkpoint(self._segment, k, k1, d, x, *state, use_reentrant=False)
+                x, U, L = checkpoint(self._segment, k, k1, D, x, U, L, use_reentrant=False)
             else:
-                out = self._segment(k, k1, d, x, *state)
-            x, state = out[0], list(out[1:])
+                x, U, L = self._segment(k, k1, D, x, U, L)
             k = k1
         return x

@@ -39,6 +39,7 @@ using namespace tomo;
 
 static_assert(sizeof(tomo_node) == 80, "tomo_node must have no padding (plans compare it bytewise)");
 static_assert(sizeof(tomo_msg) == 40, "tomo_msg must have no padding");
+static_assert(sizeof(tomo_proj_item) == 40, "tomo_proj_item must have no padding (plans compare it bytewise)");
 
 namespace {
 
@@ -70,6 +71,44 @@ struct DevBuf {
     if (p) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
+  }
+};
+
+// Pinned host staging for job tables uploaded on every call: a slot is reused
+// only after the copy that read it has completed (an event per slot).
+struct HostRing {
+  static constexpr int kSlots = 4;
+  void* host[kSlots] = {};
+  size_t bytes[kSlots] = {};
+  hipEvent_t ev[kSlots] = {};
+  int next = 0;
+  HostRing() = default;
+  HostRing(const HostRing&) = delete;
+  HostRing& operator=(const HostRing&) = delete;
+  ~HostRing() {
+    for (int i = 0; i < kSlots; ++i) {
+      if (ev[i]) (void)hipEventDestroy(ev[i]);
+      if (host[i]) (void)hipHostFree(host[i]);
+    }
+  }
+  // a slot of at least `want` bytes, or nullptr
+  void* acquire(size_t want, int& slot) {
+    slot = next;
+    next = (next + 1) % kSlots;
+    if (ev[slot] && hipEventSynchronize(ev[slot]) != hipSuccess) return nullptr;
+    if (bytes[slot] < want) {
+      if (host[slot]) (void)hipHostFree(host[slot]);
+      host[slot] = nullptr;
+      bytes[slot] = 0;
+      if (hipHostMalloc(&host[slot], want) != hipSuccess) return nullptr;
+      bytes[slot] = want;
+    }
+    return host[slot];
+  }
+  // after the copy out of `slot` has been enqueued on `stream`
+  bool mark(int slot, hipStream_t stream) {
+    if (!ev[slot] && hipEventCreateWithFlags(&ev[slot], hipEventDisableTiming) != hipSuccess) return false;
+    return hipEventRecord(ev[slot], stream) == hipSuccess;
   }
 };
 
@@ -183,6 +222,9 @@ struct tomo_ctx {
   // still reference their buffers) until the context is destroyed
   std::vector<std::unique_ptr<LocalPlan>> retired_l;
   std::vector<std::unique_ptr<ConsPlan>> retired_c;
+  // tomo_project_many / tomo_backproject_many: job tables staged per call
+  HostRing ring;
+  DevBuf btable, bpartial, bbbase;
   int fail(int code, const std::string& msg) { err = msg; return code; }
 };
 
@@ -360,31 +402,54 @@ LocalPlan* get_local_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, in
 
 // Residual r = P u - d of every node of a plan: the region pass, then (for
 // nodes split into several regions) the reduction pass.
-void launch_projection(const LocalPlan* plan, void* stream) {
-  Many<ProjJob> ps{static_cast<const ProjJob*>(plan->pjobs.p), plan->n_p};
-  if (plan->resident) {
-    Many<ProjJob> rs{static_cast<const ProjJob*>(plan->rjobs.p), plan->n_r};
-    hipLaunchKernelGGL(k_project_res<Many<ProjJob>>, dim3(plan->p_wgs), dim3(QTHREADS), 0, (hipStream_t)stream, ps);
-    hipLaunchKernelGGL(k_project_res_reduce<Many<ProjJob>>, dim3(plan->r_wgs), dim3(QTHREADS), 0,
-                       (hipStream_t)stream, rs);
+// What one batched projection launch needs: the job tables on the device, the
+// workgroup counts and the kernel choice.
+struct ProjLaunch {
+  const ProjJob* pjobs = nullptr;
+  const ProjJob* rjobs = nullptr;
+  int n_p = 0, p_wgs = 0, n_r = 0, r_wgs = 0;
+  int band = 32;
+  bool resident = false, chord = false;
+};
+
+ProjLaunch launch_of(const LocalPlan* plan) {
+  ProjLaunch L;
+  L.pjobs = static_cast<const ProjJob*>(plan->pjobs.p);
+  L.rjobs = static_cast<const ProjJob*>(plan->rjobs.p);
+  L.n_p = plan->n_p;
+  L.p_wgs = plan->p_wgs;
+  L.n_r = plan->n_r;
+  L.r_wgs = plan->r_wgs;
+  L.band = plan->band;
+  L.resident = plan->resident;
+  L.chord = plan->chord;
+  return L;
+}
+
+void launch_projection(const ProjLaunch& L, void* stream) {
+  Many<ProjJob> ps{L.pjobs, L.n_p};
+  if (L.resident) {
+    Many<ProjJob> rs{L.rjobs, L.n_r};
+    hipLaunchKernelGGL(k_project_res<Many<ProjJob>>, dim3(L.p_wgs), dim3(QTHREADS), 0, (hipStream_t)stream, ps);
+    hipLaunchKernelGGL(k_project_res_reduce<Many<ProjJob>>, dim3(L.r_wgs), dim3(QTHREADS), 0, (hipStream_t)stream,
+                       rs);
     return;
   }
-  const dim3 grid(plan->p_wgs), block(PTHREADS);
-  if (plan->chord) {
-    if (plan->band == 32)
+  const dim3 grid(L.p_wgs), block(PTHREADS);
+  if (L.chord) {
+    if (L.band == 32)
       hipLaunchKernelGGL((k_project<32, Many<ProjJob>, true>), grid, block, 0, (hipStream_t)stream, ps);
     else
       hipLaunchKernelGGL((k_project<16, Many<ProjJob>, true>), grid, block, 0, (hipStream_t)stream, ps);
   } else {
-    if (plan->band == 32)
+    if (L.band == 32)
       hipLaunchKernelGGL((k_project<32, Many<ProjJob>, false>), grid, block, 0, (hipStream_t)stream, ps);
     else
       hipLaunchKernelGGL((k_project<16, Many<ProjJob>, false>), grid, block, 0, (hipStream_t)stream, ps);
   }
-  if (plan->n_r > 0) {
-    Many<ProjJob> rs{static_cast<const ProjJob*>(plan->rjobs.p), plan->n_r};
-    hipLaunchKernelGGL(k_project_reduce<Many<ProjJob>>, dim3(plan->r_wgs), dim3(PTHREADS), 0, (hipStream_t)stream,
-                       rs);
+  if (L.n_r > 0) {
+    Many<ProjJob> rs{L.rjobs, L.n_r};
+    hipLaunchKernelGGL(k_project_reduce<Many<ProjJob>>, dim3(L.r_wgs), dim3(PTHREADS), 0, (hipStream_t)stream, rs);
   }
 }
 
@@ -439,6 +504,128 @@ int project_one(tomo_ctx* ctx, tomo_geom g, const double* angles, int n_ang, con
   if (sh.regions() > 1)
     hipLaunchKernelGGL(k_project_reduce<Single<ProjJob>>, dim3(reduce_wgs(sh, g.n_bins)), dim3(PTHREADS), 0,
                        (hipStream_t)stream, Single<ProjJob>{j});
+  return TOMO_OK;
+}
+
+// Job tables of a batch of independent projections (kind 0: sino = P image)
+// or backprojections (kind 1: image = alpha P^T sino + beta image), built on
+// the host for this call, staged through pinned memory and copied to the
+// device on `stream`; the projector's workspace is the context's.  No cache:
+// the item pointers may differ on every call.
+int stage_batch(tomo_ctx* ctx, const tomo_proj_item* items, int n_items, int kind, float alpha, float beta,
+                void* stream, ProjLaunch& plan, int& bp_wgs) {
+  std::vector<ProjJob> pj, rj;
+  std::vector<BPJob> bj;
+  if (kind == 0) {
+    bool resident = ctx->proj_kernel == 1 && ctx->model == 0;
+    for (int i = 0; i < n_items; ++i) resident = resident && items[i].g.n <= QMAXN;
+    std::vector<ProjShape> shapes;
+    size_t part_elems = 0, bb_elems = 0;
+    std::vector<size_t> poff(n_items), boff(n_items);
+    for (int i = 0; i < n_items; ++i) {
+      if (resident) {
+        shapes.push_back(resident_shape(items[i].g.n));
+      } else {
+        shapes.push_back(base_shape(items[i].g.n, items[i].n_ang));
+        split_for_parallelism(shapes.back(), items[i].g.n, ctx->proj_job_wgs);
+      }
+      poff[i] = part_elems;
+      boff[i] = bb_elems;
+      if (resident) {
+        part_elems += (size_t)items[i].n_ang * shapes[i].regions() * QACC;
+      } else if (shapes[i].regions() > 1) {
+        part_elems += (size_t)shapes[i].wgs() * PA * PACC;
+        bb_elems += (size_t)shapes[i].wgs() * PA;
+      }
+    }
+    if (!ctx->bpartial.ensure(std::max<size_t>(part_elems, 1) * 4) ||
+        !ctx->bbbase.ensure(std::max<size_t>(bb_elems, 1) * 4))
+      return ctx->fail(TOMO_ENOMEM, "batch workspace allocation failed");
+    int pw = 0, rw = 0;
+    for (int i = 0; i < n_items; ++i) {
+      const tomo_proj_item& I = items[i];
+      ProjJob j = make_proj_job(I.image, I.angles, nullptr, I.sino, I.g.n, I.g.n_bins, I.n_ang, shapes[i]);
+      j.partial = static_cast<float*>(ctx->bpartial.p) + poff[i];
+      j.bbase = static_cast<int*>(ctx->bbbase.p) + boff[i];
+      j.chord = ctx->model;
+      j.wg_begin = pw;
+      pw += shapes[i].wgs();
+      pj.push_back(j);
+      if (resident || shapes[i].regions() > 1) {
+        ProjJob r = j;
+        r.wg_begin = rw;
+        rw += resident ? resident_reduce_wgs(I.n_ang, I.g.n_bins) : reduce_wgs(shapes[i], I.g.n_bins);
+        rj.push_back(r);
+      }
+    }
+    plan.n_p = (int)pj.size();
+    plan.p_wgs = pw;
+    plan.n_r = (int)rj.size();
+    plan.r_wgs = rw;
+    plan.resident = resident;
+  } else {
+    int bw = 0;
+    for (int i = 0; i < n_items; ++i) {
+      const tomo_proj_item& I = items[i];
+      BPJob b = make_bp_job(I.sino, I.angles, I.image, I.g.n, I.g.n_bins, I.n_ang);
+      b.mode = BP_PLAIN;
+      b.alpha = alpha;
+      b.beta = beta;
+      b.chord = ctx->model;
+      b.wg_begin = bw;
+      bw += b.tiles_x * b.tiles_x;
+      bj.push_back(b);
+    }
+    bp_wgs = bw;
+  }
+  plan.band = ctx->proj_band;
+  plan.chord = ctx->model == 1;
+  // one table: projection jobs, then reduction jobs; or backprojection jobs
+  const size_t pbytes = pj.size() * sizeof(ProjJob), rbytes = rj.size() * sizeof(ProjJob);
+  const size_t total = kind == 0 ? pbytes + rbytes : bj.size() * sizeof(BPJob);
+  int slot = 0;
+  void* host = ctx->ring.acquire(total, slot);
+  if (!host || !ctx->btable.ensure(total)) return ctx->fail(TOMO_ENOMEM, "batch job table allocation failed");
+  if (kind == 0) {
+    std::memcpy(host, pj.data(), pbytes);
+    if (rbytes) std::memcpy(static_cast<char*>(host) + pbytes, rj.data(), rbytes);
+  } else {
+    std::memcpy(host, bj.data(), total);
+  }
+  if (hipMemcpyAsync(ctx->btable.p, host, total, hipMemcpyHostToDevice, (hipStream_t)stream) != hipSuccess ||
+      !ctx->ring.mark(slot, (hipStream_t)stream))
+    return ctx->fail(TOMO_EDEVICE, "job table upload failed");
+  plan.pjobs = static_cast<const ProjJob*>(ctx->btable.p);
+  plan.rjobs = reinterpret_cast<const ProjJob*>(static_cast<const char*>(ctx->btable.p) + pbytes);
+  return TOMO_OK;
+}
+
+// Argument checks of a batch: valid items, and no output overlapping any
+// item's input or another item's output.
+int check_items(tomo_ctx* ctx, const tomo_proj_item* items, int n_items, int kind) {
+  if (!items || n_items < 1) return ctx->fail(TOMO_EINVAL, "empty item list");
+  for (int i = 0; i < n_items; ++i) {
+    const tomo_proj_item& I = items[i];
+    if (int rc = check_geom(ctx, I.g)) return rc;
+    if (I.n_ang < 1) return ctx->fail(TOMO_EINVAL, "item without angles");
+    if (!I.angles || !I.image || !I.sino) return ctx->fail(TOMO_EINVAL, "null item pointer");
+  }
+  auto img_bytes = [](const tomo_proj_item& I) { return (size_t)I.g.n * I.g.n * 4; };
+  auto sino_bytes = [](const tomo_proj_item& I) { return (size_t)I.n_ang * I.g.n_bins * 4; };
+  for (int i = 0; i < n_items; ++i) {
+    const void* out = kind == 0 ? (const void*)items[i].sino : (const void*)items[i].image;
+    const size_t ob = kind == 0 ? sino_bytes(items[i]) : img_bytes(items[i]);
+    for (int j = 0; j < n_items; ++j) {
+      const void* in = kind == 0 ? (const void*)items[j].image : (const void*)items[j].sino;
+      const size_t ib = kind == 0 ? img_bytes(items[j]) : sino_bytes(items[j]);
+      if (overlaps(out, ob, in, ib)) return ctx->fail(TOMO_EINVAL, "an output overlaps an input");
+      if (j != i) {
+        const void* o2 = kind == 0 ? (const void*)items[j].sino : (const void*)items[j].image;
+        const size_t b2 = kind == 0 ? sino_bytes(items[j]) : img_bytes(items[j]);
+        if (overlaps(out, ob, o2, b2)) return ctx->fail(TOMO_EINVAL, "two outputs overlap");
+      }
+    }
+  }
   return TOMO_OK;
 }
 
@@ -633,7 +820,9 @@ int tomo_release(tomo_ctx* ctx) {
   ctx->retired_c.clear();
   ctx->lindex.clear();
   ctx->cindex.clear();
-  for (DevBuf* b : {&ctx->partial, &ctx->pbbase, &ctx->km_work, &ctx->ctr_resid, &ctx->ecode_off}) b->release();
+  for (DevBuf* b : {&ctx->partial, &ctx->pbbase, &ctx->km_work, &ctx->ctr_resid, &ctx->ecode_off, &ctx->btable,
+                    &ctx->bpartial, &ctx->bbbase})
+    b->release();
   return TOMO_OK;
 }
 
@@ -667,6 +856,29 @@ int tomo_backproject(tomo_ctx* ctx, tomo_geom g, const double* angles, int32_t n
   j.chord = ctx->model;
   launch_backproject(Single<BPJob>{j}, j.tiles_x * j.tiles_x, j.chord, stream);
   return launch_status(ctx, "tomo_backproject");
+}
+
+int tomo_project_many(tomo_ctx* ctx, const tomo_proj_item* items, int32_t n_items, void* stream) {
+  if (!ctx) return TOMO_EINVAL;
+  if (int rc = check_items(ctx, items, n_items, 0)) return rc;
+  if (int rc = set_device(ctx)) return rc;
+  ProjLaunch L;
+  int unused = 0;
+  if (int rc = stage_batch(ctx, items, n_items, 0, 0.f, 0.f, stream, L, unused)) return rc;
+  launch_projection(L, stream);
+  return launch_status(ctx, "tomo_project_many");
+}
+
+int tomo_backproject_many(tomo_ctx* ctx, const tomo_proj_item* items, int32_t n_items, float alpha, float beta,
+                          void* stream) {
+  if (!ctx) return TOMO_EINVAL;
+  if (int rc = check_items(ctx, items, n_items, 1)) return rc;
+  if (int rc = set_device(ctx)) return rc;
+  ProjLaunch L;
+  int wgs = 0;
+  if (int rc = stage_batch(ctx, items, n_items, 1, alpha, beta, stream, L, wgs)) return rc;
+  launch_backproject(Many<BPJob>{static_cast<const BPJob*>(ctx->btable.p), n_items}, wgs, ctx->model, stream);
+  return launch_status(ctx, "tomo_backproject_many");
 }
 
 int tomo_ctr_gd(tomo_ctx* ctx, tomo_geom g, const double* angles, int32_t n_ang, const float* d, float* u,
@@ -709,7 +921,7 @@ int admm_local_update(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, in
   if (!plan) return rc;
   Many<BPJob> bs{static_cast<const BPJob*>(plan->bjobs.p), plan->n_b};
   for (int e = 0; e < e1; ++e) {
-    launch_projection(plan, stream);
+    launch_projection(launch_of(plan), stream);
     launch_backproject(bs, plan->b_wgs, plan->chord, stream);
   }
   return launch_status(ctx, "admm_local_update");
@@ -728,7 +940,7 @@ int admm_local_phase(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, int
   }
   if (!plan) return rc;
   if (phase == 0) {
-    launch_projection(plan, stream);
+    launch_projection(launch_of(plan), stream);
   } else {
     Many<BPJob> bs{static_cast<const BPJob*>(plan->bjobs.p), plan->n_b};
     launch_backproject(bs, plan->b_wgs, plan->chord, stream);

@@ -26,7 +26,7 @@ TOMO_QUANT_NONE, TOMO_QUANT_KMEANS, TOMO_QUANT_DCT = 0, 1, 2
 TOMO_OPT_PROJ_JOB_WGS, TOMO_OPT_PROJ_BAND, TOMO_OPT_PROJ_KERNEL, TOMO_OPT_PROJ_MODEL = 1, 3, 4, 5
 EXPORTED = ("tomo_create", "tomo_destroy", "tomo_status_string", "tomo_last_error", "tomo_release", "tomo_set_option",
             "tomo_project",
-            "tomo_backproject", "tomo_ctr_gd", "admm_local_update", "admm_local_phase", "admm_consensus",
+            "tomo_backproject", "tomo_project_many", "tomo_backproject_many", "tomo_ctr_gd", "admm_local_update", "admm_local_phase", "admm_consensus",
             "quantize_kmeans", "quantize_dct", "tomo_pack_labels", "tomo_unpack_labels",
             "tomo_dct_encode_words", "tomo_dct_encode", "tomo_dct_decode", "tomo_sqdiff")
 
@@ -57,7 +57,12 @@ class tomo_msg(ctypes.Structure):
                 ("coeffs", ctypes.c_void_p), ("lohi", ctypes.c_void_p)]
 
 
-assert ctypes.sizeof(tomo_node) == 80 and ctypes.sizeof(tomo_msg) == 40
+class tomo_proj_item(ctypes.Structure):
+    _fields_ = [("g", tomo_geom), ("angles", ctypes.c_void_p), ("n_ang", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("image", ctypes.c_void_p), ("sino", ctypes.c_void_p)]
+
+
+assert ctypes.sizeof(tomo_node) == 80 and ctypes.sizeof(tomo_msg) == 40 and ctypes.sizeof(tomo_proj_item) == 40
 
 _P = ctypes.c_void_p
 _lib.tomo_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int]
@@ -72,6 +77,9 @@ _lib.tomo_project.argtypes = [_P, tomo_geom, _P, ctypes.c_int32, _P, _P, _P]
 _lib.tomo_backproject.argtypes = [_P, tomo_geom, _P, ctypes.c_int32, _P, _P, ctypes.c_float,
                                   ctypes.c_float, _P]
 _lib.tomo_ctr_gd.argtypes = [_P, tomo_geom, _P, ctypes.c_int32, _P, _P, ctypes.c_float, ctypes.c_int32, _P]
+_lib.tomo_project_many.argtypes = [_P, ctypes.POINTER(tomo_proj_item), ctypes.c_int32, _P]
+_lib.tomo_backproject_many.argtypes = [_P, ctypes.POINTER(tomo_proj_item), ctypes.c_int32, ctypes.c_float,
+                                       ctypes.c_float, _P]
 _lib.admm_local_update.argtypes = [_P, ctypes.POINTER(tomo_node), ctypes.c_int32, ctypes.c_int32, _P]
 _lib.admm_local_phase.argtypes = [_P, ctypes.POINTER(tomo_node), ctypes.c_int32, ctypes.c_int32, _P]
 _lib.admm_consensus.argtypes = [_P, ctypes.POINTER(tomo_node), ctypes.c_int32, ctypes.c_int32,
@@ -189,6 +197,31 @@ def tomo_backproject(ctx: Context, angles, sino, n: int, out=None, alpha: float 
                                _stream(stream))
     ctx.check(rc, "tomo_backproject")
     return out
+
+
+def make_items(entries):
+    """ctypes tomo_proj_item array from dicts with keys angles (float64), image
+    (float32 [n][n]) and sino (float32 [n_ang][n_bins]); tensors are checked."""
+    arr = (tomo_proj_item * len(entries))()
+    for i, e in enumerate(entries):
+        n_ang, nb = e["sino"].shape
+        n = e["image"].shape[0]
+        arr[i].g = tomo_geom(n, nb)
+        arr[i].angles = _dev(e["angles"], torch.float64, "angles", (n_ang,))
+        arr[i].n_ang = n_ang
+        arr[i].reserved = 0
+        arr[i].image = _dev(e["image"], torch.float32, "image", (n, n))
+        arr[i].sino = _dev(e["sino"], torch.float32, "sino", (n_ang, nb))
+    return arr
+
+
+def tomo_project_many(ctx: Context, items, stream=None):
+    ctx.check(_lib.tomo_project_many(ctx.handle, items, len(items), _stream(stream)), "tomo_project_many")
+
+
+def tomo_backproject_many(ctx: Context, items, alpha: float = 1.0, beta: float = 0.0, stream=None):
+    ctx.check(_lib.tomo_backproject_many(ctx.handle, items, len(items), float(alpha), float(beta), _stream(stream)),
+              "tomo_backproject_many")
 
 
 def tomo_ctr_gd(ctx: Context, angles, d, u, eta: float, iters: int, stream=None):

@@ -48,6 +48,7 @@ def test_struct_layouts():
     assert ctypes.sizeof(T.tomo_msg) == 40
     assert ctypes.sizeof(T.tomo_quant) == 16
     assert ctypes.sizeof(T.tomo_geom) == 8
+    assert ctypes.sizeof(T.tomo_proj_item) == 40
 
 
 def test_status_strings_and_null_context(lib):
