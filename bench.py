@@ -73,31 +73,51 @@ def _traffic(kernel: str, workload: str, tiles):
     return entry.get("hbm_bytes_per_launch") if entry else None
 
 
-def cpu_baseline(slices_info, sample_nodes, model="joseph"):
-    """The oracle's Alg. 2 local update (E1 steps of P and P^T) on a sample of
-    nodes, timed on the host; returns ray-voxel updates/s and seconds."""
+def _cpu_node(job):
+    """One sampled node: its data, then the oracle's Alg. 2 local update, which
+    alone is timed.  Returns (ray-voxel updates, seconds)."""
     import numpy as np
 
     import synthdata
     from oracle import admm as oadmm
     from oracle import chord, joseph
 
+    w, si, m, model = job
     proj = chord if model == "chord" else joseph
-
-    rng = np.random.default_rng(0)
-    upd = 0
+    th = synthdata.angles(w.n_angles)
+    part = synthdata.partition_angles(w.n_angles, w.n_nodes, w.split)[m]
+    d = proj.project(synthdata.phantom(w, si), th[part], w.n_bins)
+    u = np.random.default_rng(m).random((w.n, w.n))
     t0 = time.perf_counter()
+    oadmm.local_update(u, np.zeros((w.n, w.n)), np.zeros((w.n, w.n)), d, th[part], 1.0, 1e-5, w.inner_iters,
+                       proj=proj)
+    return 2 * w.inner_iters * len(part) * w.n * w.n, time.perf_counter() - t0
+
+
+def cpu_baseline(slices_info, sample_nodes, model="joseph"):
+    """The oracle's Alg. 2 local update (E1 steps of P and P^T) on a sample of
+    nodes, one after another in this process; returns ray-voxel updates/s and
+    the seconds timed."""
+    upd, dt = 0, 0.0
     for w, si, m in sample_nodes:
-        th = synthdata.angles(w.n_angles)
-        part = synthdata.partition_angles(w.n_angles, w.n_nodes, w.split)[m]
-        truth = synthdata.phantom(w, si)
-        d = proj.project(truth, th[part], w.n_bins)
-        u = rng.random((w.n, w.n))
-        oadmm.local_update(u, np.zeros((w.n, w.n)), np.zeros((w.n, w.n)), d, th[part], 1.0, 1e-5, w.inner_iters,
-                           proj=proj)
-        upd += 2 * w.inner_iters * len(part) * w.n * w.n
-    dt = time.perf_counter() - t0
+        u, t = _cpu_node((w, si, m, model))
+        upd += u
+        dt += t
     return upd / dt, dt
+
+
+def cpu_baseline_pool(sample_nodes, model="joseph", processes=8):
+    """The same sample with one worker process per node (forked before this
+    process touches the GPU); the rate is the total updates over the wall time
+    of the pool's work."""
+    import multiprocessing as mp
+
+    jobs = [(w, si, m, model) for w, si, m in sample_nodes]
+    with mp.get_context("fork").Pool(processes) as pool:
+        t0 = time.perf_counter()
+        res = pool.map(_cpu_node, jobs, chunksize=1)
+        wall = time.perf_counter() - t0
+    return sum(u for u, _ in res) / wall, wall
 
 
 def build(which, ctx, A, T, synthdata, log):
@@ -283,6 +303,16 @@ def main():
         if not args.quiet:
             print(msg, file=sys.stderr, flush=True)
 
+    pool = None
+    if args.workload == "single" and not args.no_cpu_baseline and not args.profile_kernels:
+        # before anything initialises the GPU: the workers are forked
+        w1 = synthdata.WORKLOADS["single"]
+        procs = min(8, os.cpu_count() or 1)
+        log(f"cpu baseline: oracle local update of nodes 0-7 of 16, {procs} worker processes ...")
+        v_pool, wall = cpu_baseline_pool([(w1, 0, m) for m in range(8)], args.model, procs)
+        pool = {"value": v_pool, "unit": "updates/s", "cores": procs, "kind": "oracle",
+                "sample": f"Alg. 2 local update (E1=5: P and P^T) of nodes 0-7 of 16 (512^2, 45 angles each), "
+                          f"float64 NumPy, one process per node, {wall:.1f} s wall"}
     torch.cuda.set_device(0)
     ctx = T.Context(0)
     if args.model == "chord":
@@ -455,6 +485,7 @@ def main():
                  "frac": traffic / dur_s / 1e9 / PEAK_HBM_GBS} if traffic else None),
         "setup_s": setup_s,
         "cpu_baseline": cpu,
+        "cpu_baseline_pool": pool,
     }
     print(json.dumps(out), flush=True)
 
