@@ -101,8 +101,23 @@ int tomo_release(tomo_ctx* ctx);
  *                           (half-open pixels).  Model 1 always uses the
  *                           band-streamed projector and computes positions in
  *                           float64 (about twice the cost).
+ *   TOMO_OPT_PROJ_ORDER     dispatch order of the band-streamed projector
+ *                           of admm_local_update / admm_local_phase: with 1
+ *                           (default), a launch of at most 8 workgroups per
+ *                           compute unit starts its workgroups in an order
+ *                           the plan derives from a cost it estimates from
+ *                           the node angles (read back to the host once, when
+ *                           the plan is built): per die, largest first;
+ *                           larger launches, and 0, keep node order.  Results
+ *                           are bit-identical for both values.
  */
-enum { TOMO_OPT_PROJ_JOB_WGS = 1, TOMO_OPT_PROJ_BAND = 3, TOMO_OPT_PROJ_KERNEL = 4, TOMO_OPT_PROJ_MODEL = 5 };
+enum {
+  TOMO_OPT_PROJ_JOB_WGS = 1,
+  TOMO_OPT_PROJ_BAND = 3,
+  TOMO_OPT_PROJ_KERNEL = 4,
+  TOMO_OPT_PROJ_MODEL = 5,
+  TOMO_OPT_PROJ_ORDER = 6
+};
 int tomo_set_option(tomo_ctx* ctx, int32_t option, int64_t value);
 
 typedef struct {

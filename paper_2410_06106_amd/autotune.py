@@ -27,7 +27,7 @@ from . import tomoadmm as T
 
 BANDS = (16, 32)
 MAX_RESIDENT_N = 2048          # the region-resident kernel's largest image side
-JOB_WGS = (8, 16, 32, 64, 128)
+JOB_WGS = (8, 16, 32, 48, 64, 128)
 
 
 def signature(nodes) -> str:

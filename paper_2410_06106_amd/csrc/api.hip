@@ -135,6 +135,137 @@ ProjShape resident_shape(int n) {
 
 int resident_reduce_wgs(int n_ang, int n_bins) { return n_ang * ((n_bins + QTHREADS - 1) / QTHREADS); }
 
+// Estimated run time of every workgroup of one band-projector job, appended to
+// `cost` in the job's workgroup order, in units of one wave's pass of 64 rays
+// through a band: per band of R driving lines, the rays of the band's angle
+// class (the kernel's own ray range, affine in the band start) shared by the
+// four waves, plus one unit for staging the band and one per workgroup.  Only
+// the dispatch order depends on it, never a result.
+void band_costs(const double* ang, int n_ang, int n, int nb, const ProjShape& s, int R, int chord,
+                std::vector<float>& cost) {
+  const double h = 0.5 * (n - 1), hb = 0.5 * (nb - 1);
+  const int PAD = R + 4, per_round = 64 * (PTHREADS / 64);
+  for (int ac = 0; ac < s.n_achunk; ++ac)
+    for (int g = 0; g < s.regions(); ++g) {
+      const int rr = g / s.n_rc, rc = g - rr * s.n_rc;
+      const int gr0 = rr * s.reg_h, gc0 = rc * s.reg_w;
+      const int gh = std::min(s.reg_h, n - gr0), gw = std::min(s.reg_w, n - gc0);
+      const int na = std::min(PA, n_ang - ac * PA);
+      int cls[PA], bb[PA];
+      double lo[PA], hi[PA], sl[PA];
+      for (int a = 0; a < na; ++a) {
+        double cs, sn;
+        angle_trig(ang[ac * PA + a], chord, cs, sn);
+        const double s00 = (gc0 - h) * cs + (gr0 - h) * sn + hb;
+        bb[a] = (int)std::floor(s00 + std::min(0.0, (gw - 1) * cs) + std::min(0.0, (gh - 1) * sn));
+        const bool rows = std::fabs(cs) >= std::fabs(sn);
+        const double ib = rows ? cs : sn, gam = rows ? -sn / cs : -cs / sn;
+        const double xi0 = rows ? (bb[a] - hb - (gr0 - h) * sn) / cs + h - gc0 + PAD
+                                : (bb[a] - hb - (gc0 - h) * cs) / sn + h - gr0 + PAD;
+        const int W = rows ? gw : gh;
+        const double span = (R - 1) * gam;
+        const double t1 = (PAD - 1 - xi0 - std::max(0.0, span)) * ib;
+        const double t2 = (PAD + W - xi0 - std::min(0.0, span)) * ib;
+        cls[a] = rows ? 0 : 1;
+        lo[a] = std::min(t1, t2);
+        hi[a] = std::max(t1, t2);
+        sl[a] = -gam * ib;
+      }
+      float c = 1.f;
+      for (int k = 0; k < 2; ++k) {
+        bool any = false;
+        for (int a = 0; a < na; ++a) any |= cls[a] == k;
+        if (!any) continue;
+        const int D = k == 0 ? gh : gw;
+        for (int db = 0; db < D; db += R) {
+          int tot = 0;
+          for (int a = 0; a < na; ++a) {
+            if (cls[a] != k) continue;
+            const int jl = std::max((int)std::floor(lo[a] + db * sl[a]), std::max(0, -bb[a]));
+            const int jh = std::min((int)std::ceil(hi[a] + db * sl[a]), std::min(PACC - 1, nb - 1 - bb[a]));
+            tot += std::max(0, jh - jl + 1);
+          }
+          c += 1.f + (float)((tot + per_round - 1) / per_round);
+        }
+      }
+      cost.push_back(c);
+    }
+}
+
+constexpr int kOrderMaxWgsPerCu = 8;   // largest launch (workgroups per CU) given a dispatch order
+
+// Dispatch order of a batched band-projector launch.  Workgroups are dealt to
+// the dies round-robin (workgroup b runs on die b % n_xcc, each die with its
+// own L2), and the workgroups resident on one die's compute units share them.
+// So: (1) the workgroups of one (job, region) pair form a group that reads one
+// region of one image; the groups go to the dies heaviest first (estimated
+// cost), each into the least loaded die with room left (a die holds its share
+// of the launch's workgroups; a group that does not fit continues in the next
+// such die), so that each region is read on about one die and the dies finish
+// together; (2) each die's list is sorted by cost, largest first (ties keep
+// table order), so that a compute unit receives a mix of heavy and light
+// workgroups and the longest ones do not trail at the end; (3) the lists are
+// interleaved: blockIdx b takes entry b / n_xcc of the list of die b % n_xcc.
+// Needs the angles on the host; returns false (and the launch keeps table
+// order) when they cannot be read.
+bool band_order(const tomo_node* nodes, int n_nodes, const std::vector<ProjShape>& shapes,
+                const std::vector<ProjJob>& pj, int R, int chord, int n_xcc, std::vector<int2>& order) {
+  std::vector<float> cost;
+  std::vector<int2> ent;
+  std::vector<std::vector<int>> groups;
+  std::vector<double> gcost;
+  std::vector<double> ang;
+  for (int i = 0; i < n_nodes; ++i) {
+    ang.resize(nodes[i].n_ang);
+    if (hipMemcpy(ang.data(), nodes[i].angles, ang.size() * sizeof(double), hipMemcpyDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    const int c0 = (int)cost.size();
+    if (pj[i].wg_begin != c0) return false;
+    band_costs(ang.data(), nodes[i].n_ang, nodes[i].g.n, nodes[i].g.n_bins, shapes[i], R, chord, cost);
+    for (int k = c0; k < (int)cost.size(); ++k) ent.push_back(make_int2(i, k - c0));
+    const int G = shapes[i].regions();
+    for (int g = 0; g < G; ++g) {
+      groups.emplace_back();
+      double sum = 0.0;
+      for (int ac = 0; ac < shapes[i].n_achunk; ++ac) {
+        groups.back().push_back(c0 + ac * G + g);
+        sum += cost[c0 + ac * G + g];
+      }
+      gcost.push_back(sum);
+    }
+  }
+  const int T = (int)cost.size(), nx = std::max(1, std::min(n_xcc, T));
+  std::vector<int> gi(groups.size());
+  for (size_t k = 0; k < gi.size(); ++k) gi[k] = (int)k;
+  std::stable_sort(gi.begin(), gi.end(), [&](int a, int b) { return gcost[a] > gcost[b]; });
+  std::vector<std::vector<int>> die(nx);
+  std::vector<double> load(nx, 0.0);
+  std::vector<int> room(nx);
+  for (int x = 0; x < nx; ++x) room[x] = T / nx + (x < T % nx ? 1 : 0);   // workgroups b with b % nx == x
+  for (int g : gi) {
+    size_t k = 0;
+    while (k < groups[g].size()) {
+      int best = -1;
+      for (int x = 0; x < nx; ++x)
+        if (room[x] > 0 && (best < 0 || load[x] < load[best])) best = x;
+      if (best < 0) return false;
+      for (; k < groups[g].size() && room[best] > 0; ++k) {
+        die[best].push_back(groups[g][k]);
+        load[best] += cost[groups[g][k]];
+        --room[best];
+      }
+    }
+  }
+  order.resize(T);
+  for (int x = 0; x < nx; ++x) {
+    std::stable_sort(die[x].begin(), die[x].end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    for (size_t k = 0; k < die[x].size(); ++k) order[k * nx + x] = ent[die[x][k]];
+  }
+  return true;
+}
+
 ProjShape base_shape(int n, int n_ang) {
   ProjShape s;
   s.n_achunk = (n_ang + PA - 1) / PA;
@@ -172,6 +303,8 @@ bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
 struct LocalPlan {
   std::vector<tomo_node> key;
   DevBuf pjobs, rjobs, bjobs, resid, partial, bbase;
+  DevBuf order;                  // band projector dispatch order (int2 per workgroup), if built
+  bool ordered = false;
   int n_p = 0, p_wgs = 0, n_r = 0, r_wgs = 0, n_b = 0, b_wgs = 0;
   int band = 16;                 // projector band depth (16 or 32)
   bool resident = false;         // region-resident projector (k_project_res)
@@ -204,10 +337,12 @@ bool same_nodes(const std::vector<tomo_node>& k, const tomo_node* nodes, int n) 
 struct tomo_ctx {
   int device = 0;
   int n_cu = 1;
+  int n_xcc = 1;              // accelerator complex dies: workgroup b of a launch runs on die b % n_xcc
   int proj_job_wgs = 16;      // TOMO_OPT_PROJ_JOB_WGS
   int proj_band = 32;         // TOMO_OPT_PROJ_BAND
   int proj_kernel = 0;        // TOMO_OPT_PROJ_KERNEL
   int model = 0;              // TOMO_OPT_PROJ_MODEL (0 Joseph, 1 chord lengths)
+  int proj_order = 1;         // TOMO_OPT_PROJ_ORDER (0 table order, 1 estimated cost, largest first)
   std::string err;
   DevBuf partial;                                // standalone projector workspace
   DevBuf pbbase;                                 // standalone projector: region bin bases
@@ -386,6 +521,20 @@ LocalPlan* get_local_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, in
     rc = ctx->fail(TOMO_EDEVICE, "descriptor upload failed");
     return nullptr;
   }
+  std::vector<int2> ord;
+  // with many workgroups per CU the hardware's dynamic dispatch evens out the
+  // load and table order keeps the angle chunks of one region together in
+  // time (shared reads in L2); the table pays off for launches of a few waves
+  if (!resident && ctx->proj_order == 1 && pw <= kOrderMaxWgsPerCu * ctx->n_cu &&
+      band_order(nodes, n_nodes, shapes, pj, ctx->proj_band, ctx->model, ctx->n_xcc, ord) &&
+      (int)ord.size() == pw) {
+    if (!plan->order.ensure(ord.size() * sizeof(int2)) ||
+        hipMemcpy(plan->order.p, ord.data(), ord.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess) {
+      rc = ctx->fail(TOMO_EDEVICE, "dispatch order upload failed");
+      return nullptr;
+    }
+    plan->ordered = true;
+  }
   plan->n_r = (int)rj.size();
   plan->r_wgs = rw;
   plan->n_p = (int)pj.size();
@@ -407,6 +556,7 @@ LocalPlan* get_local_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, in
 struct ProjLaunch {
   const ProjJob* pjobs = nullptr;
   const ProjJob* rjobs = nullptr;
+  const int2* order = nullptr;   // band kernel dispatch order or null
   int n_p = 0, p_wgs = 0, n_r = 0, r_wgs = 0;
   int band = 32;
   bool resident = false, chord = false;
@@ -416,6 +566,7 @@ ProjLaunch launch_of(const LocalPlan* plan) {
   ProjLaunch L;
   L.pjobs = static_cast<const ProjJob*>(plan->pjobs.p);
   L.rjobs = static_cast<const ProjJob*>(plan->rjobs.p);
+  L.order = plan->ordered ? static_cast<const int2*>(plan->order.p) : nullptr;
   L.n_p = plan->n_p;
   L.p_wgs = plan->p_wgs;
   L.n_r = plan->n_r;
@@ -436,6 +587,7 @@ void launch_projection(const ProjLaunch& L, void* stream) {
     return;
   }
   const dim3 grid(L.p_wgs), block(PTHREADS);
+  ps.order = L.order;
   if (L.chord) {
     if (L.band == 32)
       hipLaunchKernelGGL((k_project<32, Many<ProjJob>, true>), grid, block, 0, (hipStream_t)stream, ps);
@@ -767,6 +919,9 @@ int tomo_create(tomo_ctx** out, int device) {
   c->device = device;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->n_cu = std::max(1, prop.multiProcessorCount);
+  int xcc = 1;
+  if (hipDeviceGetAttribute(&xcc, hipDeviceAttributeNumberOfXccs, device) == hipSuccess) c->n_xcc = std::max(1, xcc);
+  (void)hipGetLastError();
   *out = c;
   return TOMO_OK;
 }
@@ -797,6 +952,10 @@ int tomo_set_option(tomo_ctx* ctx, int32_t option, int64_t value) {
     case TOMO_OPT_PROJ_MODEL:
       if (value != 0 && value != 1) return ctx->fail(TOMO_EINVAL, "projector model must be 0 or 1");
       ctx->model = (int)value;
+      break;
+    case TOMO_OPT_PROJ_ORDER:
+      if (value != 0 && value != 1) return ctx->fail(TOMO_EINVAL, "projector order must be 0 or 1");
+      ctx->proj_order = (int)value;
       break;
     default:
       return ctx->fail(TOMO_EINVAL, "unknown option");

@@ -24,7 +24,15 @@ template <class Job>
 struct Many {
   const Job* jobs;
   int n_jobs;
+  // optional dispatch order: workgroup b of the launch runs entry order[b] =
+  // {job, workgroup within the job}; null runs the jobs in table order
+  const int2* order = nullptr;
   __device__ __forceinline__ Job get(int bid, int& lid) const {
+    if (order) {
+      const int2 e = order[bid];
+      lid = e.y;
+      return jobs[e.x];
+    }
     int lo = 0, hi = n_jobs - 1;
     while (lo < hi) {  // last job with wg_begin <= bid (uniform across the WG)
       int mid = (lo + hi + 1) >> 1;
@@ -104,7 +112,7 @@ struct BPJob {
 // or sine within 1e-12 of zero as exactly zero (the angle is axis-aligned and
 // lines on pixel edges follow the half-open pixel convention); the Joseph
 // model uses the values as computed.
-__device__ __forceinline__ void angle_trig(double th, int chord, double& cs, double& sn) {
+__host__ __device__ __forceinline__ void angle_trig(double th, int chord, double& cs, double& sn) {
   double c = cos(th), s = sin(th);
   if (chord) {
     const bool zc = fabs(c) < 1e-12, zs = fabs(s) < 1e-12;

@@ -24,6 +24,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 TOMO_XUPDATE_SEGMENT, TOMO_XUPDATE_AVERAGE = 0, 1
 TOMO_QUANT_NONE, TOMO_QUANT_KMEANS, TOMO_QUANT_DCT = 0, 1, 2
 TOMO_OPT_PROJ_JOB_WGS, TOMO_OPT_PROJ_BAND, TOMO_OPT_PROJ_KERNEL, TOMO_OPT_PROJ_MODEL = 1, 3, 4, 5
+TOMO_OPT_PROJ_ORDER = 6
 EXPORTED = ("tomo_create", "tomo_destroy", "tomo_status_string", "tomo_last_error", "tomo_release", "tomo_set_option",
             "tomo_project",
             "tomo_backproject", "tomo_project_many", "tomo_backproject_many", "tomo_ctr_gd", "admm_local_update", "admm_local_phase", "admm_consensus",
