@@ -122,16 +122,48 @@ class DADMM:
                 T.admm_local_update(self.ctx, self.single[i], self.e1, stream)
             T.admm_consensus(self.ctx, self.per_slice[si], self.mode, self.e2, self.quant, None, stream)
 
-    def capture(self, iters_per_graph=1):
+    def prime(self, stream=None):
+        """First projection of the next pipelined iteration (see step_pipelined);
+        call it once after the state was set, before the first step_pipelined."""
+        T.admm_local_phase(self.ctx, self.nodes, 0, stream)
+
+    def step_pipelined(self, side):
+        """One iteration whose first projection (residual P_m u_m - d_m) was
+        launched by prime() or by the previous call.  At its end the next
+        iteration's first projection runs on stream ``side`` concurrently with
+        this iteration's consensus: it reads only u_m and d_m, which the
+        consensus (x-update, quantizer, dual update) does not write, and writes
+        only the residual, which the consensus does not read.  Every kernel sees
+        the same inputs as in step(), so the iterates are bit-identical."""
+        if self.e1 < 1:
+            raise ValueError("the pipelined iteration needs E1 >= 1")
+        main = torch.cuda.current_stream()
+        T.admm_local_phase(self.ctx, self.nodes, 1)
+        for _ in range(self.e1 - 1):
+            T.admm_local_phase(self.ctx, self.nodes, 0)
+            T.admm_local_phase(self.ctx, self.nodes, 1)
+        side.wait_stream(main)
+        with torch.cuda.stream(side):
+            T.admm_local_phase(self.ctx, self.nodes, 0)
+        T.admm_consensus(self.ctx, self.nodes, self.mode, self.e2, self.quant, self.msgs)
+        main.wait_stream(side)
+
+    def capture(self, iters_per_graph=1, pipelined=False):
         """Capture ``iters_per_graph`` batched iterations into a HIP graph (after one
-        uncaptured call has built the plans)."""
+        uncaptured call has built the plans).  ``pipelined``: the iterations are
+        step_pipelined ones (fork/join inside the graph); call prime() before the
+        first replay and again whenever the state was reset."""
         g = torch.cuda.CUDAGraph()
         s = torch.cuda.Stream()
+        side = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s):
             with torch.cuda.graph(g, stream=s):
                 for _ in range(iters_per_graph):
-                    self.step()
+                    if pipelined:
+                        self.step_pipelined(side)
+                    else:
+                        self.step()
         torch.cuda.current_stream().wait_stream(s)
         self.graph = g
         return g

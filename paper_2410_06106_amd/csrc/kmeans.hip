@@ -55,7 +55,6 @@ struct KMShared {
   int cb3[3][65];                 // the same for k <= 64, three generations
   long long sb3[3][65];
   long long wsum[KWAVES];
-  long long cell[KWAVES];         // per-wave partial code sums of a bucket scan
   int wcnt[KWAVES];
   float red[2 * KWAVES];
   int redb[KWAVES];
@@ -144,33 +143,54 @@ __device__ void bucket_scan(KMShared& sh, int B) {
   __syncthreads();
 }
 
-// Count and code sum of the values a <= x, by one wave (every lane gets the
-// result): the buckets left of x's bucket plus the qualifying values of that
-// bucket.  The count comes from ballots, the sum from LDS atomics on *cell.
+// Sum of a 64-bit integer over the 64 lanes of a wave (every lane active),
+// returned to every lane: butterflies within each row of 16 lanes (DPP quad
+// permutations and the half-row and row mirrors), then the four row sums.
+// Integer adds, so exact in any order.
+template <int CTRL>
+__device__ __forceinline__ long long dpp_add_i64(long long v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, 0xF, 0xF, false);
+  return v + (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ long long wave_sum_i64(long long v) {
+  v = dpp_add_i64<0xB1>(v);    // quad_perm [1, 0, 3, 2]: pairs
+  v = dpp_add_i64<0x4E>(v);    // quad_perm [2, 3, 0, 1]: quads
+  v = dpp_add_i64<0x141>(v);   // row_half_mirror: lanes i and 7 - i of each half-row
+  v = dpp_add_i64<0x140>(v);   // row_mirror: lanes i and 15 - i of each row
+  auto lane = [&](int i) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)v, i);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(v >> 32), i);
+    return (long long)(((unsigned long long)hi << 32) | lo);
+  };
+  return lane(0) + lane(16) + lane(32) + lane(48);
+}
+
+// Count and code sum of the values a <= x, by one wave (every lane active and
+// every lane gets the result): the buckets left of x's bucket plus the
+// qualifying values of that bucket, counted with ballots and summed across
+// the wave in registers.
 template <class VP>
 __device__ __forceinline__ void at_or_below(const KMShared& sh, VP V, float x, const Buckets& bk, float lo,
-                                            float hi, int n, long long tot, int S, long long* cell, int& cnt,
-                                            long long& sum) {
+                                            float hi, int n, long long tot, int S, int& cnt, long long& sum) {
   if (x < lo) { cnt = 0; sum = 0; return; }
   if (x >= hi) { cnt = n; sum = tot; return; }
   const int b = bk.of(x);
   const int p0 = sh.start[b], p1 = sh.start[b + 1];
+  const long long below = sh.psum[b];        // code sum of the buckets left of b
   const int l = threadIdx.x & 63;
-  if (l == 0) *cell = 0;
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
   int c = 0;
   long long s = 0;
   for (int pw = p0; pw < p1; pw += 64) {     // uniform trip count: every lane sees every ballot
     const int p = pw + l;
-    const float a = p < p1 ? V[p] : 0.f;
+    const float a = V[min(p, p1 - 1)];       // in the bucket (p1 > p0 here); lanes past it are masked below
     const bool in = p < p1 && a <= x;
     c += __popcll(__ballot(in));
     if (in) s += km_fixed(a, S);
   }
-  if (s != 0) atomicAdd((unsigned long long*)cell, (unsigned long long)s);
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
   cnt = p0 + c;
-  sum = sh.psum[b] + *cell;
+  sum = below + wave_sum_i64(s);
 }
 
 }  // namespace
@@ -333,8 +353,8 @@ __global__ __launch_bounds__(KT) void k_kmeans(const KMJob* jobs, KMJob single, 
   __syncthreads();
 
   auto scan_bucket = [&](float x, int& c, long long& s) {
-    if constexpr (REG) at_or_below(sh, vlds, x, bk, lo, hi, n, tot, S, &sh.cell[w], c, s);
-    else at_or_below(sh, gptr((const float*)wv), x, bk, lo, hi, n, tot, S, &sh.cell[w], c, s);
+    if constexpr (REG) at_or_below(sh, vlds, x, bk, lo, hi, n, tot, S, c, s);
+    else at_or_below(sh, gptr((const float*)wv), x, bk, lo, hi, n, tot, S, c, s);
   };
 
   int it = 0;
@@ -344,13 +364,14 @@ __global__ __launch_bounds__(KT) void k_kmeans(const KMJob* jobs, KMJob single, 
     // boundary counts; wave w scans the buckets of thresholds w, w + 16, ...
     // The counts rotate through three generations, so the one written in an
     // iteration was last read two barriers earlier.
+    // Lane l holds centre l and the threshold between centres l and l + 1
+    // (its right neighbour's centre comes in with one shuffle).
     float cj = l < k ? sh.cent[l] : 0.f;
+    float xt = threshold((double)cj + (double)__shfl_down(cj, 1, 64));
     int gen = 0;
     for (int t = 0;; ++t) {
       for (int j = w; j < k - 1; j += KWAVES) {
-        const float cl = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cj), j));
-        const float cr = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cj), j + 1));
-        const float x = threshold((double)cl + (double)cr);
+        const float x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(xt), j));
         int c;
         long long sm;
         scan_bucket(x, c, sm);
@@ -367,27 +388,40 @@ __global__ __launch_bounds__(KT) void k_kmeans(const KMJob* jobs, KMJob single, 
         sh.sb3[gen][k] = tot;
       }
       __syncthreads();
+      // every count this iteration needs, read at once (the previous
+      // generation is read but unused at t = 0)
+      const int prev = gen == 0 ? 2 : gen - 1;
+      const int b0 = sh.cb3[gen][l], b1 = sh.cb3[gen][l + 1], bp = sh.cb3[prev][l + 1];
+      const long long s0 = sh.sb3[gen][l], s1 = sh.sb3[gen][l + 1];
       if (t > 0) {
         it = t;
-        const int prev = gen == 0 ? 2 : gen - 1;
-        const bool moved = __ballot(l + 1 < k && sh.cb3[gen][l + 1] != sh.cb3[prev][l + 1]) != 0;
+        const bool moved = __ballot(l + 1 < k && b1 != bp) != 0;
         if (!moved) break;
       }
       if (t == max_iter) break;
-      // centres of the current labels, then their stable ranks (broadcast one
-      // lane at a time); every lane picks the centre ranked l
-      const int c = l < k ? sh.cb3[gen][l + 1] - sh.cb3[gen][l] : 0;
+      // centres of the current labels, then their stable sort: when they are
+      // already non-decreasing the sort is the identity; otherwise every lane
+      // finds its stable rank (broadcast one lane at a time) and picks the
+      // centre ranked l
+      const int c = l < k ? b1 - b0 : 0;
       float u = cj;
-      if (c > 0) u = (float)(ldexp((double)(sh.sb3[gen][l + 1] - sh.sb3[gen][l]), -S) / (double)c);
-      int r = 0;
-      for (int i = 0; i < k; ++i) {
-        const float ui = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(u), i));
-        r += (ui < u) || (ui == u && i < l);
+      if (c > 0) u = (float)(ldexp((double)(s1 - s0), -S) / (double)c);
+      float un = __shfl_down(u, 1, 64);
+      if (__ballot(l + 1 < k && un < u) == 0) {
+        cj = u;
+      } else {
+        int r = 0;
+        for (int i = 0; i < k; ++i) {
+          const float ui = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(u), i));
+          r += (ui < u) || (ui == u && i < l);
+        }
+        for (int i = 0; i < k; ++i) {
+          const float ui = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(u), i));
+          cj = __builtin_amdgcn_readlane(r, i) == l ? ui : cj;
+        }
+        un = __shfl_down(cj, 1, 64);
       }
-      for (int i = 0; i < k; ++i) {
-        const float ui = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(u), i));
-        cj = __builtin_amdgcn_readlane(r, i) == l ? ui : cj;
-      }
+      xt = threshold((double)cj + (double)un);
       gen = gen == 2 ? 0 : gen + 1;
     }
     if (tid < k) sh.cent[tid] = cj;

@@ -179,6 +179,42 @@ def test_graph_replay_matches_eager(mods, ctx):
             assert torch.equal(s.x.cpu(), e), f"replay {k} differs from eager"
 
 
+def test_pipelined_iteration_matches_step(mods, ctx):
+    """The pipelined iteration (the next iteration's first projection on a side
+    stream, concurrent with the consensus) gives the iterates of step() bit for
+    bit, launched eagerly and replayed from a captured fork/join graph, with
+    unrelated eager work and synchronizations between the replays."""
+    T, A = mods
+    slices = _slices(T, A, ctx)
+    q = T.tomo_quant(T.TOMO_QUANT_KMEANS, 16, 30, 50)
+    run = A.DADMM(ctx, slices, quant=q)
+    s0 = _snapshot(slices)
+    eager = []
+    for _ in range(4):
+        run.step()
+        torch.cuda.synchronize()
+        eager.append([t.cpu().clone() for s in slices for t in s.u + s.lam + [s.x]])
+    _restore(slices, s0)
+    side = torch.cuda.Stream()
+    run.prime()
+    for k in range(4):
+        run.step_pipelined(side)
+        torch.cuda.synchronize()
+        got = [t.cpu() for s in slices for t in s.u + s.lam + [s.x]]
+        assert all(torch.equal(a, b) for a, b in zip(got, eager[k])), f"eager pipelined iteration {k} differs"
+    g = run.capture(1, pipelined=True)
+    _restore(slices, s0)
+    torch.cuda.synchronize()
+    run.prime()
+    for k in range(4):
+        g.replay()
+        torch.cuda.synchronize()
+        _ = torch.ones(8, device="cuda").sum().item()     # unrelated eager work between replays
+        got = [t.cpu() for s in slices for t in s.u + s.lam + [s.x]]
+        assert all(torch.equal(a, b) for a, b in zip(got, eager[k])), f"pipelined replay {k} differs"
+        log(f"  replay {k}: identical to step()")
+
+
 def test_dispatch_order_does_not_change_results(mods):
     """The batched projector started in estimated-cost order
     (TOMO_OPT_PROJ_ORDER = 1, the default) and in node order (0) gives the same
