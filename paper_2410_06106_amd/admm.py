@@ -142,10 +142,14 @@ class DADMM:
         for _ in range(self.e1 - 1):
             T.admm_local_phase(self.ctx, self.nodes, 0)
             T.admm_local_phase(self.ctx, self.nodes, 1)
-        side.wait_stream(main)
+        ready = torch.cuda.Event()
+        ready.record(main)
+        # the consensus is issued first so that its few large workgroups reach
+        # the CUs before the projector's fill them
+        T.admm_consensus(self.ctx, self.nodes, self.mode, self.e2, self.quant, self.msgs)
+        side.wait_event(ready)
         with torch.cuda.stream(side):
             T.admm_local_phase(self.ctx, self.nodes, 0)
-        T.admm_consensus(self.ctx, self.nodes, self.mode, self.e2, self.quant, self.msgs)
         main.wait_stream(side)
 
     def capture(self, iters_per_graph=1, pipelined=False):
