@@ -268,6 +268,58 @@ int admm_consensus(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, int32
                    int32_t e2, const tomo_quant* q, const tomo_msg* msg, void* stream);
 
 /*
+ * Regularization as one more ADMM block (the separate sub-problem that the
+ * paper's discussion, Section 4, proposes without a formulation).  A slice may
+ * carry one block: a copy z of its image with its own dual nu, adding
+ *   mu R(z) + nu^T (z - x) + rho_z/2 ||z - x||^2
+ * to the augmented Lagrangian (Eq. 7).  Per outer iteration:
+ *   admm_reg_update      z = prox_{theta R}(x - nu/rho_z), theta = mu/rho_z, and
+ *                        t_z = z + nu/rho_z (reads x and nu, i.e. x^k, nu^k);
+ *   admm_consensus_reg   the x-update with the block's term (SEG: every Alg. 3
+ *                        step of a segment becomes
+ *                        x <- x - eta2 (rho (x - u - lambda/rho) + rho_z (x - t_z));
+ *                        AVG: x = (sum_m rho_m (u_m + lambda_m/rho_m) + rho_z t_z)
+ *                        / (sum_m rho_m + rho_z)), the quantizer, Eq. 24 for every
+ *                        node and nu <- nu + rho_z (z - x) for every block.
+ * R: TOMO_REG_TIKHONOV, R(z) = 1/2 ||z||^2, prox v / (1 + theta); TOMO_REG_TV,
+ * isotropic total variation sum_ij |(grad z)_ij| with forward differences that
+ * vanish across the last row and column, its prox by tv_iters iterations of
+ * Chambolle's dual projection algorithm (J. Math. Imaging Vis. 20, 2004):
+ *   w = div p - v/theta,  p <- (p + tau grad w) / (1 + tau |grad w|),
+ *   z = v - theta div p,
+ * from the field p the block holds (warm start; zero it before the first
+ * iteration), 0 < tau <= 0.25 (the convergence proof asks tau <= 1/8).
+ * All pointers are device pointers the caller owns; z, nu, tz are float32
+ * [n][n] and p float32 [2][n][n] (p1 then p2; TV only, else may be NULL), n
+ * the slice's image side; they must not overlap each other or x.  The library
+ * keeps one scratch field of 2 n^2 floats per TV block in a plan cached by the
+ * block array (like the node plans; freed by tomo_release / tomo_destroy).
+ * Errors: TOMO_EINVAL for a slice id no listed node has, two blocks of one
+ * slice, an unknown kind, rho_z <= 0, mu < 0, tau outside (0, 0.25],
+ * tv_iters outside [0, 10000] or a NULL pointer the kind needs.
+ */
+enum { TOMO_REG_TIKHONOV = 1, TOMO_REG_TV = 2 };
+
+typedef struct {
+  int32_t slice;     /* slice id (tomo_node.slice) the block belongs to        */
+  int32_t kind;      /* TOMO_REG_TIKHONOV or TOMO_REG_TV                       */
+  int32_t tv_iters;  /* Chambolle iterations per z-update (TV)                 */
+  float mu;          /* weight of R (>= 0)                                     */
+  float rho;         /* penalty rho_z of the constraint z = x (> 0)            */
+  float tau;         /* Chambolle step (TV), 0 < tau <= 0.25                   */
+  float* z;          /* float32 [n][n] the block's copy (written)              */
+  float* nu;         /* float32 [n][n] its dual (updated by the consensus)     */
+  float* tz;         /* float32 [n][n] z + nu/rho_z (written by the z-update)  */
+  float* p;          /* float32 [2][n][n] TV dual field (read and written)     */
+} tomo_reg;
+
+int admm_reg_update(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, const tomo_reg* regs,
+                    int32_t n_regs, void* stream);
+int admm_consensus_reg(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, int32_t mode, int32_t e2,
+                       const tomo_quant* q, const tomo_msg* msg, const tomo_reg* regs, int32_t n_regs,
+                       void* stream);
+
+/*
  * Scalar K-means quantizer (Alg. 5) of a float32 vector a[n], bit-exact:
  *  lo,hi = min,max (NaN/Inf -> TOMO_EINVAL is NOT detectable on the host: the
  *  kernel then writes iters = -1 and leaves the outputs unspecified);

@@ -13,6 +13,8 @@ Follows Section 2.3-2.6 of the paper:
 * Eq. 23  x^{k+1} = conc(Q(x[1]), ..., Q(x[M])).
 * Eq. 24  lambda_m <- lambda_m + rho (u_m^{k+1} - x^{k+1}).
 * Alg. 4  zero initialisation and K outer iterations.
+* With ``reg`` (oracle/reg.py): the regularization block of the discussion
+  (Section 4), its z-update before the x-update and its dual after it.
 
 Readings where the paper is silent: u_m is zero only at k = 0 and warm-starts
 afterwards; Alg. 3 starts from the current global x^k[m]; every node, the owner
@@ -26,6 +28,7 @@ from typing import Callable, Sequence
 import numpy as np
 
 from . import joseph
+from . import reg as regmod
 from .kmeans import kmeans_quantize
 from .dct import dct_quantize
 from .metrics import rmse
@@ -114,15 +117,19 @@ class Problem:
 class Trace:
     rmse: list = field(default_factory=list)
     rel_change: list = field(default_factory=list)
+    reg_state: tuple | None = None        # (z, nu, p) of the regularization block
 
 
 def run(prob: Problem, iters: int, rho: float, eta1: float, e1: int, eta2: float, e2: int,
         mode: str = "seg", quant: Quantizer | None = None, exact_u: bool = False,
-        state=None, cast32: bool = False):
+        state=None, cast32: bool = False, reg: "regmod.Reg | None" = None, reg_state=None):
     """Alg. 4.  ``mode`` is 'seg' (Eq. 16 per node) or 'avg' (Eq. 9).
 
     ``cast32`` rounds the exchanged x to float32 each iteration (the GPU keeps x
-    in float32); everything else stays float64.  Returns (x, us, lams, trace).
+    in float32); everything else stays float64.  ``reg`` adds the
+    regularization block (z, nu and, for TV, the dual field p; ``reg_state``
+    continues from a given (z, nu, p)).  Returns (x, us, lams, trace); the
+    block's final state is trace.reg_state.
     """
     quant = quant or Quantizer()
     n, m_nodes = prob.n, len(prob.d)
@@ -135,7 +142,16 @@ def run(prob: Problem, iters: int, rho: float, eta1: float, e1: int, eta2: float
         us = [np.array(t, dtype=np.float64) for t in state[1]]
         lams = [np.array(t, dtype=np.float64) for t in state[2]]
     tr = Trace()
+    if reg is not None:
+        if reg_state is None:
+            z, nu, pz = np.zeros((n, n)), np.zeros((n, n)), None
+        else:
+            z, nu = (np.array(t, dtype=np.float64) for t in reg_state[:2])
+            pz = reg_state[2]
     for _ in range(iters):
+        if reg is not None:
+            z, pz = regmod.z_update(reg, x, nu, pz)
+            tz = z + nu / reg.rho
         for m in range(m_nodes):
             if exact_u:
                 us[m] = local_update_exact(x, lams[m], prob.d[m], prob.thetas[m], rho, n)
@@ -145,9 +161,15 @@ def run(prob: Problem, iters: int, rho: float, eta1: float, e1: int, eta2: float
             xt = x.copy()
             for m, (r0, nr) in enumerate(prob.segments):
                 sl = slice(r0, r0 + nr)
-                xt[sl] = x_update_segment(x[sl], us[m][sl], lams[m][sl], rho, eta2, e2)
+                if reg is None:
+                    xt[sl] = x_update_segment(x[sl], us[m][sl], lams[m][sl], rho, eta2, e2)
+                else:
+                    xt[sl] = regmod.x_update_segment(x[sl], us[m][sl], lams[m][sl], rho, tz[sl], reg.rho, eta2, e2)
         elif mode == "avg":
-            xt = x_update_average(us, lams, rho)
+            if reg is None:
+                xt = x_update_average(us, lams, rho)
+            else:
+                xt = regmod.x_update_average(us, lams, [rho] * m_nodes, tz, reg.rho)
         else:
             raise ValueError(mode)
         x_new = np.empty_like(xt)
@@ -158,9 +180,13 @@ def run(prob: Problem, iters: int, rho: float, eta1: float, e1: int, eta2: float
             x_new = x_new.astype(np.float32).astype(np.float64)
         for m in range(m_nodes):
             lams[m] = dual_update(lams[m], us[m], x_new, rho)
+        if reg is not None:
+            nu = regmod.dual_update(nu, z, x_new, reg.rho)
         denom = np.linalg.norm(x)
         tr.rel_change.append(float(np.linalg.norm(x_new - x) / denom) if denom > 0 else float("inf"))
         x = x_new
         if prob.truth is not None:
             tr.rmse.append(rmse(x, prob.truth))
+    if reg is not None:
+        tr.reg_state = (z, nu, pz)
     return x, us, lams, tr

@@ -37,14 +37,21 @@ class SliceState:
     x: torch.Tensor | None = None
     truth: torch.Tensor | None = None
     eta1: float = 0.0
+    reg: dict | None = None      # regularization block: z, nu, tz [n][n], p [2][n][n]
 
     def allocate(self, device):
         self.u = [torch.zeros((self.n, self.n), dtype=torch.float32, device=device) for _ in self.d]
         self.lam = [torch.zeros((self.n, self.n), dtype=torch.float32, device=device) for _ in self.d]
         self.x = torch.zeros((self.n, self.n), dtype=torch.float32, device=device)
 
+    def allocate_reg(self):
+        """Buffers of a regularization block for this slice (zero)."""
+        dev = self.x.device
+        self.reg = {k: torch.zeros((self.n, self.n), dtype=torch.float32, device=dev) for k in ("z", "nu", "tz")}
+        self.reg["p"] = torch.zeros((2, self.n, self.n), dtype=torch.float32, device=dev)
+
     def zero(self):
-        for t in self.u + self.lam + [self.x]:
+        for t in self.u + self.lam + [self.x] + (list(self.reg.values()) if self.reg else []):
             t.zero_()
 
 
@@ -92,7 +99,9 @@ class DADMM:
     """Alg. 4 over one or many slices, all nodes on one GPU."""
 
     def __init__(self, ctx, slices, rho=1.0, eta2=0.2, e1=5, e2=10, mode=T.TOMO_XUPDATE_SEGMENT,
-                 quant: T.tomo_quant | None = None, msgs=None):
+                 quant: T.tomo_quant | None = None, msgs=None, reg: dict | None = None):
+        """``reg``: a regularization block for every slice, dict(kind=T.TOMO_REG_TV
+        or T.TOMO_REG_TIKHONOV, mu, and for TV tv_iters, tau); its penalty is rho."""
         self.ctx, self.slices = ctx, slices
         self.rho, self.eta2, self.e1, self.e2, self.mode, self.quant = rho, eta2, e1, e2, mode, quant
         entries, self.slice_ranges = [], []
@@ -111,16 +120,37 @@ class DADMM:
         self.single = [T.make_nodes([e]) for e in entries]
         self.per_slice = [T.make_nodes(entries[a:b]) for a, b in self.slice_ranges]
         self.graph = None
+        self.regs, self.regs_per_slice = None, None
+        if reg is not None:
+            ents = []
+            for si, s in enumerate(slices):
+                if s.reg is None:
+                    s.allocate_reg()
+                ents.append(dict(slice=si, kind=reg["kind"], mu=reg["mu"], rho=rho, tv_iters=reg.get("tv_iters", 10),
+                                 tau=reg.get("tau", 0.125), **s.reg))
+            self.regs = T.make_regs(ents)
+            self.regs_per_slice = [T.make_regs([e]) for e in ents]
+
+    def _consensus(self, nodes, msgs, regs, stream=None):
+        if regs is None:
+            T.admm_consensus(self.ctx, nodes, self.mode, self.e2, self.quant, msgs, stream)
+        else:
+            T.admm_consensus_reg(self.ctx, nodes, self.mode, self.e2, self.quant, msgs, regs, stream)
 
     def step(self, stream=None):
+        if self.regs is not None:
+            T.admm_reg_update(self.ctx, self.nodes, self.regs, stream)
         T.admm_local_update(self.ctx, self.nodes, self.e1, stream)
-        T.admm_consensus(self.ctx, self.nodes, self.mode, self.e2, self.quant, self.msgs, stream)
+        self._consensus(self.nodes, self.msgs, self.regs, stream)
 
     def step_plain(self, stream=None):
         for si, (a, b) in enumerate(self.slice_ranges):
+            if self.regs is not None:
+                T.admm_reg_update(self.ctx, self.per_slice[si], self.regs_per_slice[si], stream)
             for i in range(a, b):
                 T.admm_local_update(self.ctx, self.single[i], self.e1, stream)
-            T.admm_consensus(self.ctx, self.per_slice[si], self.mode, self.e2, self.quant, None, stream)
+            self._consensus(self.per_slice[si], None, None if self.regs is None else self.regs_per_slice[si],
+                            stream)
 
     def prime(self, stream=None):
         """First projection of the next pipelined iteration (see step_pipelined);
@@ -138,6 +168,8 @@ class DADMM:
         if self.e1 < 1:
             raise ValueError("the pipelined iteration needs E1 >= 1")
         main = torch.cuda.current_stream()
+        if self.regs is not None:
+            T.admm_reg_update(self.ctx, self.nodes, self.regs)
         T.admm_local_phase(self.ctx, self.nodes, 1)
         for _ in range(self.e1 - 1):
             T.admm_local_phase(self.ctx, self.nodes, 0)
@@ -146,7 +178,7 @@ class DADMM:
         ready.record(main)
         # the consensus is issued first so that its few large workgroups reach
         # the CUs before the projector's fill them
-        T.admm_consensus(self.ctx, self.nodes, self.mode, self.e2, self.quant, self.msgs)
+        self._consensus(self.nodes, self.msgs, self.regs)
         side.wait_event(ready)
         with torch.cuda.stream(side):
             T.admm_local_phase(self.ctx, self.nodes, 0)

@@ -24,6 +24,9 @@ __global__ void k_seg_dct(const SegJob*, int, int, int);
 __global__ void k_dct(const float*, int, int, int, int, int16_t*, float*, float*);
 __global__ void k_avg(Many<AvgJob>, const NodeRef*);
 __global__ void k_dual(Many<NodeRef>);
+__global__ void k_reg_init(Many<RegJob>);
+__global__ void k_tv_iter(Many<RegJob>, int);
+__global__ void k_tv_final(Many<RegJob>);
 __global__ void k_sqdiff(const float*, const float*, long long, double*);
 __global__ void k_pack_labels(const uint8_t*, int, int, unsigned*, long long);
 __global__ void k_ecode_bits(const int16_t*, int, int, int, unsigned*);
@@ -314,12 +317,24 @@ struct LocalPlan {
 struct ConsPlan {
   std::vector<tomo_node> key;
   std::vector<tomo_msg> msg_key;
+  std::vector<tomo_reg> reg_key;
   DevBuf seg, avg, noderefs, labels, kmjobs, kmwork;
   int n_seg = 0, n_avg = 0, avg_wgs = 0, dual_wgs = 0;
+  int n_refs = 0;                 // dual-update entries: the nodes, then the regularization blocks
   int km_small = 0, km_big = 0;   // K-means jobs regrouping in LDS, then those using the workspace
 };
 
 constexpr int kKmThreads = 1024;
+
+// z-update of a list of regularization blocks: job table and the TV blocks'
+// scratch fields, built once per block array (and the slices' images)
+struct RegPlan {
+  std::vector<tomo_reg> key;
+  std::vector<const float*> xs;
+  DevBuf jobs, scratch;
+  int n_jobs = 0, wgs = 0, max_iters = 0;
+  bool any_tv = false;
+};
 
 // FNV-1a hash of a descriptor array: the plan caches are indexed by it.
 uint64_t hash_bytes(const void* p, size_t n, uint64_t h = 1469598103934665603ull) {
@@ -357,6 +372,7 @@ struct tomo_ctx {
   // still reference their buffers) until the context is destroyed
   std::vector<std::unique_ptr<LocalPlan>> retired_l;
   std::vector<std::unique_ptr<ConsPlan>> retired_c;
+  std::vector<std::unique_ptr<RegPlan>> rplans;   // z-update plans (independent of the options)
   // tomo_project_many / tomo_backproject_many: job tables staged per call
   HostRing ring;
   DevBuf btable, bpartial, bbbase;
@@ -786,24 +802,126 @@ bool same_msg(const std::vector<tomo_msg>& k, const tomo_msg* msg, int n) {
   return (int)k.size() == n && std::memcmp(k.data(), msg, sizeof(tomo_msg) * n) == 0;
 }
 
-ConsPlan* get_cons_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, const tomo_msg* msg, int& rc) {
+bool same_regs(const std::vector<tomo_reg>& k, const tomo_reg* regs, int n) {
+  return (int)k.size() == n && (n == 0 || std::memcmp(k.data(), regs, sizeof(tomo_reg) * n) == 0);
+}
+
+// the block of a slice, or null
+const tomo_reg* reg_of(const tomo_reg* regs, int n_regs, int slice) {
+  for (int r = 0; r < n_regs; ++r)
+    if (regs[r].slice == slice) return &regs[r];
+  return nullptr;
+}
+
+// Validates a block array against the node list; fills the image and side of
+// each block's slice.
+int check_regs(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, const tomo_reg* regs, int n_regs,
+               std::vector<const float*>& xs, std::vector<int>& ns) {
+  if (n_regs < 0 || (n_regs > 0 && !regs)) return ctx->fail(TOMO_EINVAL, "bad regularization block array");
+  xs.assign(n_regs, nullptr);
+  ns.assign(n_regs, 0);
+  for (int r = 0; r < n_regs; ++r) {
+    const tomo_reg& R = regs[r];
+    for (int q = 0; q < r; ++q)
+      if (regs[q].slice == R.slice) return ctx->fail(TOMO_EINVAL, "two regularization blocks for one slice");
+    for (int i = 0; i < n_nodes; ++i)
+      if (nodes[i].slice == R.slice) { xs[r] = nodes[i].x; ns[r] = nodes[i].g.n; break; }
+    if (!xs[r]) return ctx->fail(TOMO_EINVAL, "regularization block of a slice no listed node has");
+    if (R.kind != TOMO_REG_TIKHONOV && R.kind != TOMO_REG_TV) return ctx->fail(TOMO_EINVAL, "unknown regularizer");
+    if (!(R.rho > 0.f) || !(R.mu >= 0.f)) return ctx->fail(TOMO_EINVAL, "regularization needs rho > 0 and mu >= 0");
+    if (R.kind == TOMO_REG_TV && (!(R.tau > 0.f) || R.tau > 0.25f || R.tv_iters < 0 || R.tv_iters > 10000))
+      return ctx->fail(TOMO_EINVAL, "TV needs 0 < tau <= 0.25 and 0 <= tv_iters <= 10000");
+    if (!R.z || !R.nu || !R.tz || (R.kind == TOMO_REG_TV && !R.p))
+      return ctx->fail(TOMO_EINVAL, "null regularization pointer");
+    const size_t img = (size_t)ns[r] * ns[r] * sizeof(float);
+    const void* ptr[5] = {R.z, R.nu, R.tz, xs[r], R.p};
+    const size_t len[5] = {img, img, img, img, 2 * img};
+    const int np = R.kind == TOMO_REG_TV ? 5 : 4;
+    for (int a = 0; a < np; ++a)
+      for (int b = a + 1; b < np; ++b)
+        if (overlaps(ptr[a], len[a], ptr[b], len[b]))
+          return ctx->fail(TOMO_EINVAL, "regularization arrays must not overlap each other or x");
+  }
+  return TOMO_OK;
+}
+
+RegPlan* get_reg_plan(tomo_ctx* ctx, const tomo_reg* regs, int n_regs, const std::vector<const float*>& xs,
+                      const std::vector<int>& ns, int& rc) {
   rc = TOMO_OK;
-  const uint64_t h = cons_hash(nodes, n_nodes, msg);
+  for (auto& p : ctx->rplans)
+    if (same_regs(p->key, regs, n_regs) && p->xs == xs) return p.get();
+  auto plan = std::make_unique<RegPlan>();
+  plan->key.assign(regs, regs + n_regs);
+  plan->xs = xs;
+  size_t scratch = 0;
+  for (int r = 0; r < n_regs; ++r)
+    if (regs[r].kind == TOMO_REG_TV) scratch += 2 * (size_t)ns[r] * ns[r];
+  if (!plan->scratch.ensure(std::max<size_t>(scratch, 1) * sizeof(float)) ||
+      !plan->jobs.ensure((size_t)std::max(n_regs, 1) * sizeof(RegJob))) {
+    rc = ctx->fail(TOMO_ENOMEM, "regularization plan allocation failed");
+    return nullptr;
+  }
+  std::vector<RegJob> jobs;
+  float* sp = static_cast<float*>(plan->scratch.p);
+  int w = 0;
+  for (int r = 0; r < n_regs; ++r) {
+    const tomo_reg& R = regs[r];
+    RegJob j{};
+    j.x = xs[r]; j.nu = R.nu; j.z = R.z; j.tz = R.tz;
+    j.n = ns[r];
+    j.kind = R.kind == TOMO_REG_TV ? REG_TV : REG_TIKHONOV;
+    j.theta = R.mu / R.rho;
+    j.irho_z = 1.f / R.rho;
+    j.tau = R.tau;
+    // with theta = 0 the prox is the identity: no iterations
+    j.iters = (j.kind == REG_TV && j.theta > 0.f) ? R.tv_iters : 0;
+    if (j.kind == REG_TV) {
+      j.p[0] = R.p;
+      j.p[1] = sp;
+      sp += 2 * (size_t)ns[r] * ns[r];
+      plan->any_tv = true;
+      plan->max_iters = std::max(plan->max_iters, j.iters);
+    }
+    j.wg_begin = w;
+    w += (int)(((long long)ns[r] * ns[r] + 255) / 256);
+    jobs.push_back(j);
+  }
+  if (n_regs > 0 &&
+      hipMemcpy(plan->jobs.p, jobs.data(), jobs.size() * sizeof(RegJob), hipMemcpyHostToDevice) != hipSuccess) {
+    rc = ctx->fail(TOMO_EDEVICE, "regularization plan upload failed");
+    return nullptr;
+  }
+  plan->n_jobs = n_regs;
+  plan->wgs = w;
+  ctx->rplans.push_back(std::move(plan));
+  return ctx->rplans.back().get();
+}
+
+ConsPlan* get_cons_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, const tomo_msg* msg,
+                        const tomo_reg* regs, int n_regs, int& rc) {
+  rc = TOMO_OK;
+  uint64_t h = cons_hash(nodes, n_nodes, msg);
+  if (n_regs > 0) h = hash_bytes(regs, sizeof(tomo_reg) * n_regs, h);
   auto range = ctx->cindex.equal_range(h);
   for (auto it = range.first; it != range.second; ++it)
-    if (same_nodes(it->second->key, nodes, n_nodes) && same_msg(it->second->msg_key, msg, n_nodes))
+    if (same_nodes(it->second->key, nodes, n_nodes) && same_msg(it->second->msg_key, msg, n_nodes) &&
+        same_regs(it->second->reg_key, regs, n_regs))
       return it->second;
   auto plan = std::make_unique<ConsPlan>();
   plan->key.assign(nodes, nodes + n_nodes);
   if (msg) plan->msg_key.assign(msg, msg + n_nodes);
+  if (n_regs > 0) plan->reg_key.assign(regs, regs + n_regs);
   std::vector<SegJob> seg;
   std::vector<AvgJob> avg;
   std::vector<NodeRef> refs;
   int aw = 0, dw = 0;
   for (int i = 0; i < n_nodes; ++i) {
     const tomo_node& N = nodes[i];
+    const tomo_reg* B = reg_of(regs, n_regs, N.slice);
     SegJob s{};
     s.x = N.x; s.u = N.u; s.lam = N.lam;
+    s.tz = B ? B->tz : nullptr;
+    s.rho_z = B ? B->rho : 0.f;
     s.n = N.g.n; s.row0 = N.seg_row0; s.rows = N.seg_rows;
     s.rho = N.rho; s.eta2 = N.eta2;
     if (msg) {
@@ -819,10 +937,23 @@ ConsPlan* get_cons_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, cons
     if (i == 0 || nodes[i - 1].slice != N.slice) {
       AvgJob a{};
       a.x = N.x; a.node0 = i; a.n_nodes = 0; a.n = N.g.n; a.wg_begin = aw;
+      a.tz = B ? B->tz : nullptr;
+      a.rho_z = B ? B->rho : 0.f;
       aw += (int)(((long long)N.g.n * N.g.n + 255) / 256);
       avg.push_back(a);
     }
     avg.back().n_nodes++;
+  }
+  // dual update of every block: nu += rho_z (z - x), as one more (u, lambda) entry
+  for (int r = 0; r < n_regs; ++r) {
+    const tomo_reg& R = regs[r];
+    NodeRef ref{};
+    for (int i = 0; i < n_nodes; ++i)
+      if (nodes[i].slice == R.slice) { ref.x = nodes[i].x; ref.n = nodes[i].g.n; break; }
+    ref.u = R.z; ref.lam = R.nu; ref.rho = R.rho;
+    ref.wg_begin = dw;
+    dw += (int)(((long long)ref.n * ref.n + 1023) / 1024);
+    refs.push_back(ref);
   }
   // K-means jobs: segments that fit the registers first, then the longer ones,
   // each with its own slice of the label scratch and of the workspace
@@ -855,6 +986,10 @@ ConsPlan* get_cons_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, cons
     j.a_hat = N.x + off;
     j.u = N.u + off;
     j.lam = N.lam + off;
+    if (const tomo_reg* B = reg_of(regs, n_regs, N.slice)) {
+      j.tz = B->tz + off;
+      j.rho_z = B->rho;
+    }
     j.n = (long long)N.seg_rows * N.g.n;
     j.rho = N.rho;
     j.eta2 = N.eta2;
@@ -883,6 +1018,7 @@ ConsPlan* get_cons_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, cons
     return nullptr;
   }
   plan->n_seg = (int)seg.size();
+  plan->n_refs = (int)refs.size();
   plan->n_avg = (int)avg.size();
   plan->avg_wgs = aw;
   plan->dual_wgs = dw;
@@ -977,6 +1113,7 @@ int tomo_release(tomo_ctx* ctx) {
   ctx->cplans.clear();
   ctx->retired_l.clear();
   ctx->retired_c.clear();
+  ctx->rplans.clear();
   ctx->lindex.clear();
   ctx->cindex.clear();
   for (DevBuf* b : {&ctx->partial, &ctx->pbbase, &ctx->km_work, &ctx->ctr_resid, &ctx->ecode_off, &ctx->btable,
@@ -1109,6 +1246,12 @@ int admm_local_phase(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, int
 
 int admm_consensus(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, int32_t mode, int32_t e2,
                    const tomo_quant* q, const tomo_msg* msg, void* stream) {
+  return admm_consensus_reg(ctx, nodes, n_nodes, mode, e2, q, msg, nullptr, 0, stream);
+}
+
+int admm_consensus_reg(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, int32_t mode, int32_t e2,
+                       const tomo_quant* q, const tomo_msg* msg, const tomo_reg* regs, int32_t n_regs,
+                       void* stream) {
   if (!ctx) return TOMO_EINVAL;
   if (mode != TOMO_XUPDATE_SEGMENT && mode != TOMO_XUPDATE_AVERAGE) return ctx->fail(TOMO_EINVAL, "bad mode");
   if (e2 < 0) return ctx->fail(TOMO_EINVAL, "E2 < 0");
@@ -1122,9 +1265,12 @@ int admm_consensus(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, int32
     if (kind == TOMO_QUANT_DCT && (q->quality < 1 || q->quality > 100 || nodes[i].seg_rows % 8 || nodes[i].g.n % 8))
       return ctx->fail(TOMO_EINVAL, "bad DCT parameters (quality 1..100, segment sides multiples of 8)");
   }
+  std::vector<const float*> rxs;
+  std::vector<int> rns;
+  if (int rc = check_regs(ctx, nodes, n_nodes, regs, n_regs, rxs, rns)) return rc;
   if (int rc = set_device(ctx)) return rc;
   int rc = TOMO_OK;
-  ConsPlan* plan = get_cons_plan(ctx, nodes, n_nodes, msg, rc);
+  ConsPlan* plan = get_cons_plan(ctx, nodes, n_nodes, msg, regs, n_regs, rc);
   if (!plan) return rc;
   hipStream_t s = (hipStream_t)stream;
   const SegJob* seg = static_cast<const SegJob*>(plan->seg.p);
@@ -1149,9 +1295,31 @@ int admm_consensus(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, int32
   } else if (do_x) {
     hipLaunchKernelGGL(k_seg_none, dim3(plan->n_seg), dim3(256), 0, s, seg, do_x, e2);
   }
-  Many<NodeRef> ds{refs, n_nodes};
+  Many<NodeRef> ds{refs, plan->n_refs};
   hipLaunchKernelGGL(k_dual, dim3(plan->dual_wgs), dim3(256), 0, s, ds);
   return launch_status(ctx, "admm_consensus");
+}
+
+int admm_reg_update(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, const tomo_reg* regs, int32_t n_regs,
+                    void* stream) {
+  if (!ctx) return TOMO_EINVAL;
+  if (!nodes || n_nodes < 1) return ctx->fail(TOMO_EINVAL, "empty node list");
+  if (n_regs == 0) return TOMO_OK;
+  std::vector<const float*> xs;
+  std::vector<int> ns;
+  if (int rc = check_regs(ctx, nodes, n_nodes, regs, n_regs, xs, ns)) return rc;
+  if (int rc = set_device(ctx)) return rc;
+  int rc = TOMO_OK;
+  RegPlan* plan = get_reg_plan(ctx, regs, n_regs, xs, ns, rc);
+  if (!plan) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  Many<RegJob> js{static_cast<const RegJob*>(plan->jobs.p), plan->n_jobs};
+  hipLaunchKernelGGL(k_reg_init, dim3(plan->wgs), dim3(256), 0, s, js);
+  if (plan->any_tv) {
+    for (int t = 0; t < plan->max_iters; ++t) hipLaunchKernelGGL(k_tv_iter, dim3(plan->wgs), dim3(256), 0, s, js, t);
+    hipLaunchKernelGGL(k_tv_final, dim3(plan->wgs), dim3(256), 0, s, js);
+  }
+  return launch_status(ctx, "admm_reg_update");
 }
 
 int quantize_kmeans(tomo_ctx* ctx, const float* a, int64_t n, int32_t k, int32_t max_iter, uint8_t* labels,

@@ -132,6 +132,8 @@ struct SegJob {
   float* x;             // slice consensus image [n][n]
   const float* u;       // this node's u (SEG mode)
   const float* lam;     // this node's lambda (SEG mode)
+  const float* tz;      // regularization block's target z + nu / rho_z [n][n], or null
+  float rho_z;          // its penalty
   int n, row0, rows;
   float rho, eta2;
   // AVG mode: the slice's nodes are nodes[node0 .. node0 + n_nodes)
@@ -155,6 +157,8 @@ struct NodeRef {        // u, lambda of one node (AVG gather, dual update)
 
 struct AvgJob {         // x = mean over nodes[node0 .. node0+n_nodes) of u + lambda/rho
   float* x;
+  const float* tz;      // regularization block's target, or null (then the plain mean)
+  float rho_z;
   int node0, n_nodes, n;
   int wg_begin;
 };
@@ -168,6 +172,8 @@ struct KMJob {
   float* a_hat;         // quantized values (nullable, may equal src)
   const float* u;       // Alg. 3 inputs, or null for no x-update
   const float* lam;
+  const float* tz;      // regularization block's target of the segment, or null
+  float rho_z;
   uint8_t* labels;      // [n] (nullable)
   float* cent;          // [k] (nullable)
   int32_t* iters;       // [1] (nullable)
@@ -179,6 +185,35 @@ struct KMJob {
 // Segments up to this many values are regrouped in LDS; longer ones in the
 // job's global workspace of n floats.
 constexpr int KM_LDS_VALUES = 16384;
+
+// ---------------------------------------------------------------------------
+// Regularization block (one per slice): z = prox_{theta R}(x - nu / rho_z),
+// theta = mu / rho_z; R Tikhonov (1/2 ||z||^2) or isotropic TV by Chambolle's
+// dual projection iterations on the field (p1, p2), ping-ponged between the
+// caller's buffer (slot 0) and a library scratch buffer (slot 1).
+// ---------------------------------------------------------------------------
+enum { REG_TIKHONOV = 1, REG_TV = 2 };
+
+// One Alg. 3 step with a block's term, x - eta2 (rho (x - u - lambda/rho) +
+// rho_z (x - t_z)), with every fused multiply-add explicit so that each kernel
+// running it rounds the same way.
+__device__ __forceinline__ float xstep_reg(float xv, float uv, float lv, float tv, float rho, float irho,
+                                           float rho_z, float eta2) {
+  const float a = fmaf(-lv, irho, xv - uv);
+  const float delta = fmaf(rho, a, rho_z * (xv - tv));
+  return fmaf(-eta2, delta, xv);
+}
+
+struct RegJob {
+  const float* x;       // slice consensus image [n][n]
+  const float* nu;      // block dual
+  float* z;             // block copy (output)
+  float* tz;            // v = x - nu / rho_z during the iterations, then z + nu / rho_z
+  float* p[2];          // TV dual field slots, each [2][n][n] (p1 then p2)
+  int n, kind, iters;
+  float theta, irho_z, tau;
+  int wg_begin;
+};
 
 __device__ __forceinline__ float wave_sum(float v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

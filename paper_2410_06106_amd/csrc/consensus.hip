@@ -33,7 +33,8 @@ __device__ __forceinline__ void wg_minmax(float& lo, float& hi, int& bad, float*
 }
 
 // ---------------------------------------------------------------------------
-// Alg. 3 on one segment (in place on x): E2 steps from the current x^k[m]
+// Alg. 3 on one segment (in place on x): E2 steps from the current x^k[m];
+// with a regularization block its copy adds rho_z (x - t_z) to every step
 // ---------------------------------------------------------------------------
 template <int NT>
 __device__ void segment_xupdate(const SegJob& S, int e2) {
@@ -43,9 +44,14 @@ __device__ void segment_xupdate(const SegJob& S, int e2) {
   for (size_t i = threadIdx.x; i < cnt; i += NT) {
     float xv = S.x[base + i];
     const float uv = S.u[base + i], lv = S.lam[base + i];
-    for (int e = 0; e < e2; ++e) {
-      float delta = S.rho * (xv - uv - lv * irho);
-      xv = xv - S.eta2 * delta;
+    if (S.tz) {
+      const float tv = S.tz[base + i];
+      for (int e = 0; e < e2; ++e) xv = xstep_reg(xv, uv, lv, tv, S.rho, irho, S.rho_z, S.eta2);
+    } else {
+      for (int e = 0; e < e2; ++e) {
+        float delta = S.rho * (xv - uv - lv * irho);
+        xv = xv - S.eta2 * delta;
+      }
     }
     S.x[base + i] = xv;
   }
@@ -187,7 +193,9 @@ __global__ __launch_bounds__(DCT_THREADS) void k_dct(const float* a, int rows, i
   dct_wg(a, rows, cols, ld, quality, coeffs, a_hat, lohi, sh);
 }
 
-// Eq. 9: x = mean over the slice's nodes of (u_m + lambda_m / rho); one job per slice
+// Eq. 9: x = mean over the slice's nodes of (u_m + lambda_m / rho); one job per
+// slice.  With a regularization block, the closed-form argmin with its term:
+// (sum_m rho_m (u_m + lambda_m / rho_m) + rho_z t_z) / (sum_m rho_m + rho_z).
 __global__ __launch_bounds__(256) void k_avg(Many<AvgJob> src, const NodeRef* nodes) {
   int lid;
   const AvgJob A = src.get(blockIdx.x, lid);
@@ -195,6 +203,17 @@ __global__ __launch_bounds__(256) void k_avg(Many<AvgJob> src, const NodeRef* no
   const size_t cnt = (size_t)A.n * A.n;
   if (i >= cnt) return;
   float s = 0.f;
+  if (A.tz) {
+    float w = A.rho_z;
+    s = A.rho_z * A.tz[i];
+    for (int m = 0; m < A.n_nodes; ++m) {
+      const NodeRef R = nodes[A.node0 + m];
+      s += R.rho * (R.u[i] + R.lam[i] / R.rho);
+      w += R.rho;
+    }
+    A.x[i] = s / w;
+    return;
+  }
   for (int m = 0; m < A.n_nodes; ++m) {
     const NodeRef R = nodes[A.node0 + m];
     s += R.u[i] + R.lam[i] / R.rho;

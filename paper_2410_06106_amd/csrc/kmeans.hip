@@ -73,6 +73,13 @@ __device__ __forceinline__ float km_xupdate(float xv, float uv, float lv, float 
   return xv;
 }
 
+// the same with a regularization block's target t_z and penalty rho_z
+__device__ __forceinline__ float km_xupdate_reg(float xv, float uv, float lv, float tv, float rho, float irho,
+                                                float rho_z, float eta2, int e2) {
+  for (int e = 0; e < e2; ++e) xv = xstep_reg(xv, uv, lv, tv, rho, irho, rho_z, eta2);
+  return xv;
+}
+
 // Largest float32 below a finite x.
 __device__ __forceinline__ float prev_float(float x) {
   if (x == 0.f) return __uint_as_float(0x80000001u);
@@ -214,6 +221,7 @@ __global__ __launch_bounds__(KT) void k_kmeans(const KMJob* jobs, KMJob single, 
   const auto ahat = gptr(J.a_hat);
   const auto uu = gptr(J.u);
   const auto ll = gptr(J.lam);
+  const auto tzz = gptr(J.tz);
   const auto labels = gptr(J.labels);
   const auto vals = do_x ? gptr((const float*)J.x) : src;   // the segment after the x-update
   if (n <= 0) {
@@ -269,11 +277,26 @@ __global__ __launch_bounds__(KT) void k_kmeans(const KMJob* jobs, KMJob single, 
         uv[e] = uu[i < n ? i : n - 1];
         lv[e] = ll[i < n ? i : n - 1];
       }
+      if (J.tz) {
+        float tv[KVPT];
 #pragma unroll
-      for (int e = 0; e < KVPT; ++e) {
-        const long long i = base + tid + (long long)e * KT;
-        a[e] = km_xupdate(a[e], uv[e], lv[e], J.rho, irho, J.eta2, e2);
-        if (i < n) xo[i] = a[e];
+        for (int e = 0; e < KVPT; ++e) {
+          const long long i = base + tid + (long long)e * KT;
+          tv[e] = tzz[i < n ? i : n - 1];
+        }
+#pragma unroll
+        for (int e = 0; e < KVPT; ++e) {
+          const long long i = base + tid + (long long)e * KT;
+          a[e] = km_xupdate_reg(a[e], uv[e], lv[e], tv[e], J.rho, irho, J.rho_z, J.eta2, e2);
+          if (i < n) xo[i] = a[e];
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < KVPT; ++e) {
+          const long long i = base + tid + (long long)e * KT;
+          a[e] = km_xupdate(a[e], uv[e], lv[e], J.rho, irho, J.eta2, e2);
+          if (i < n) xo[i] = a[e];
+        }
       }
     }
 #pragma unroll

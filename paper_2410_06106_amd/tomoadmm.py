@@ -25,9 +25,11 @@ TOMO_XUPDATE_SEGMENT, TOMO_XUPDATE_AVERAGE = 0, 1
 TOMO_QUANT_NONE, TOMO_QUANT_KMEANS, TOMO_QUANT_DCT = 0, 1, 2
 TOMO_OPT_PROJ_JOB_WGS, TOMO_OPT_PROJ_BAND, TOMO_OPT_PROJ_KERNEL, TOMO_OPT_PROJ_MODEL = 1, 3, 4, 5
 TOMO_OPT_PROJ_ORDER = 6
+TOMO_REG_TIKHONOV, TOMO_REG_TV = 1, 2
 EXPORTED = ("tomo_create", "tomo_destroy", "tomo_status_string", "tomo_last_error", "tomo_release", "tomo_set_option",
             "tomo_project",
             "tomo_backproject", "tomo_project_many", "tomo_backproject_many", "tomo_ctr_gd", "admm_local_update", "admm_local_phase", "admm_consensus",
+            "admm_reg_update", "admm_consensus_reg",
             "quantize_kmeans", "quantize_dct", "tomo_pack_labels", "tomo_unpack_labels",
             "tomo_dct_encode_words", "tomo_dct_encode", "tomo_dct_decode", "tomo_sqdiff")
 
@@ -63,7 +65,14 @@ class tomo_proj_item(ctypes.Structure):
                 ("reserved", ctypes.c_int32), ("image", ctypes.c_void_p), ("sino", ctypes.c_void_p)]
 
 
+class tomo_reg(ctypes.Structure):
+    _fields_ = [("slice", ctypes.c_int32), ("kind", ctypes.c_int32), ("tv_iters", ctypes.c_int32),
+                ("mu", ctypes.c_float), ("rho", ctypes.c_float), ("tau", ctypes.c_float),
+                ("z", ctypes.c_void_p), ("nu", ctypes.c_void_p), ("tz", ctypes.c_void_p), ("p", ctypes.c_void_p)]
+
+
 assert ctypes.sizeof(tomo_node) == 80 and ctypes.sizeof(tomo_msg) == 40 and ctypes.sizeof(tomo_proj_item) == 40
+assert ctypes.sizeof(tomo_reg) == 56
 
 _P = ctypes.c_void_p
 _lib.tomo_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int]
@@ -85,6 +94,11 @@ _lib.admm_local_update.argtypes = [_P, ctypes.POINTER(tomo_node), ctypes.c_int32
 _lib.admm_local_phase.argtypes = [_P, ctypes.POINTER(tomo_node), ctypes.c_int32, ctypes.c_int32, _P]
 _lib.admm_consensus.argtypes = [_P, ctypes.POINTER(tomo_node), ctypes.c_int32, ctypes.c_int32,
                                 ctypes.c_int32, ctypes.POINTER(tomo_quant), ctypes.POINTER(tomo_msg), _P]
+_lib.admm_reg_update.argtypes = [_P, ctypes.POINTER(tomo_node), ctypes.c_int32, ctypes.POINTER(tomo_reg),
+                                 ctypes.c_int32, _P]
+_lib.admm_consensus_reg.argtypes = [_P, ctypes.POINTER(tomo_node), ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.c_int32, ctypes.POINTER(tomo_quant), ctypes.POINTER(tomo_msg),
+                                    ctypes.POINTER(tomo_reg), ctypes.c_int32, _P]
 _lib.quantize_kmeans.argtypes = [_P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P]
 _lib.quantize_dct.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                               _P, _P, _P, _P]
@@ -255,6 +269,21 @@ def admm_consensus(ctx: Context, nodes, mode: int, e2: int, quant: tomo_quant | 
     ctx.check(rc, "admm_consensus")
 
 
+def admm_reg_update(ctx: Context, nodes, regs, stream=None):
+    """z-update of every regularization block (tomo_reg array, see make_regs)."""
+    rc = _lib.admm_reg_update(ctx.handle, nodes, len(nodes), regs, len(regs), _stream(stream))
+    ctx.check(rc, "admm_reg_update")
+
+
+def admm_consensus_reg(ctx: Context, nodes, mode: int, e2: int, quant: tomo_quant | None = None, msgs=None,
+                       regs=None, stream=None):
+    q = ctypes.byref(quant) if quant is not None else None
+    n_regs = 0 if regs is None else len(regs)
+    rc = _lib.admm_consensus_reg(ctx.handle, nodes, len(nodes), int(mode), int(e2), q, msgs, regs, n_regs,
+                                 _stream(stream))
+    ctx.check(rc, "admm_consensus_reg")
+
+
 def quantize_kmeans(ctx: Context, a, k: int, max_iter: int = 30, labels=None, centroids=None, a_hat=None,
                     iters=None, stream=None):
     a = a.reshape(-1)
@@ -377,6 +406,21 @@ def make_nodes(entries):
         arr[i].eta1 = float(e["eta1"])
         arr[i].eta2 = float(e["eta2"])
         arr[i].reserved = 0
+    return arr
+
+
+def make_regs(entries):
+    """ctypes tomo_reg array from dicts: slice, kind, mu, rho, and z, nu, tz (float32
+    [n][n] cuda tensors), for TV also p (float32 [2][n][n]), tv_iters, tau."""
+    arr = (tomo_reg * len(entries))()
+    for i, e in enumerate(entries):
+        r = arr[i]
+        r.slice, r.kind = int(e["slice"]), int(e["kind"])
+        r.tv_iters = int(e.get("tv_iters", 0))
+        r.mu, r.rho, r.tau = float(e["mu"]), float(e["rho"]), float(e.get("tau", 0.125))
+        for key in ("z", "nu", "tz"):
+            setattr(r, key, _dev(e[key], torch.float32, key).value)
+        r.p = None if e.get("p") is None else _dev(e["p"], torch.float32, "p").value
     return arr
 
 
