@@ -284,6 +284,10 @@ def main():
                     help="projector choice instead of autotuning: BAND/JOB_WGS (band kernel) or 'resident'")
     ap.add_argument("--model", default="joseph", choices=("joseph", "chord"),
                     help="system matrix: Joseph interpolation (default) or the chord lengths of Eq. 2")
+    ap.add_argument("--reg", default=None, choices=("tv", "tikhonov"),
+                    help="add a regularization block (the extra ADMM sub-problem) to every slice")
+    ap.add_argument("--reg-mu", type=float, default=0.02)
+    ap.add_argument("--reg-iters", type=int, default=10, help="Chambolle iterations per z-update (TV)")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only launch the projector and backprojector of the workload a few times, and a "
@@ -333,7 +337,12 @@ def main():
         n_nodes = sum(len(s.d) for s in slices)
         km_iters = torch.zeros((n_nodes, 1), dtype=torch.int32, device="cuda")
         msgs = T.make_msgs([dict(iters=km_iters[i]) for i in range(n_nodes)])
-    run = A.DADMM(ctx, slices, rho=1.0, eta2=0.2, e1=5, e2=10, mode=T.TOMO_XUPDATE_SEGMENT, quant=q, msgs=msgs)
+    reg = None
+    if args.reg:
+        reg = dict(kind=T.TOMO_REG_TV if args.reg == "tv" else T.TOMO_REG_TIKHONOV, mu=args.reg_mu,
+                   tv_iters=args.reg_iters, tau=0.125)
+    run = A.DADMM(ctx, slices, rho=1.0, eta2=0.2, e1=5, e2=10, mode=T.TOMO_XUPDATE_SEGMENT, quant=q, msgs=msgs,
+                  reg=reg)
     updates_per_step = sum(2 * w.inner_iters * w.n_angles * w.n * w.n for w in ws)
     upd_per_launch = sum(w.n_angles * w.n * w.n for w in ws)
     tiles = None
@@ -478,14 +487,35 @@ def main():
     if km_iters is not None:
         it = km_iters.cpu().numpy().reshape(-1)
         lloyd = {"mean": float(it.mean()), "max": int(it.max()), "min": int(it.min())}
+    # --- z-update of the regularization blocks: algorithmic HBM bytes per pixel
+    # are 12 to start (x, nu read, v written), 20 per Chambolle iteration (the
+    # field read and written, v read), 24 to finish (field, v, nu read, z and
+    # t_z written); Tikhonov 16 (x, nu read, z and t_z written)
+    zinfo = None
+    if run.regs is not None:
+        T.admm_reg_update(ctx, run.nodes, run.regs)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.kernel_reps):
+            T.admm_reg_update(ctx, run.nodes, run.regs)
+        e1.record()
+        torch.cuda.synchronize()
+        z_us = e0.elapsed_time(e1) / args.kernel_reps * 1e3
+        px = sum(s.n * s.n for s in slices)
+        per_px = (12 + 20 * args.reg_iters + 24 + (16 if args.reg_iters % 2 else 0)) if args.reg == "tv" else 16
+        zinfo = {"kind": args.reg, "mu": args.reg_mu, "tv_iters": args.reg_iters if args.reg == "tv" else None,
+                 "us": z_us, "algorithmic_bytes": per_px * px,
+                 "achieved_GBps": per_px * px / (z_us * 1e-6) / 1e9, "peak_GBps": PEAK_HBM_GBS}
+        log(f"z-update ({args.reg}): {z_us:.1f} us, {zinfo['achieved_GBps']:.0f} GB/s algorithmic")
     # --- consensus (quantized x-update + dual update), same stream; it moves the
     # iterates on, so it runs after everything reported above has been read
-    T.admm_consensus(ctx, run.nodes, run.mode, run.e2, run.quant, run.msgs)
+    run.consensus(run.nodes, run.msgs, run.regs)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(args.kernel_reps):
-        T.admm_consensus(ctx, run.nodes, run.mode, run.e2, run.quant, run.msgs)
+        run.consensus(run.nodes, run.msgs, run.regs)
     e1.record()
     torch.cuda.synchronize()
     consensus_us = e0.elapsed_time(e1) / args.kernel_reps * 1e3
@@ -512,7 +542,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": dict({"workload": desc}, **cfg, system_matrix=args.model),
+        "config": dict({"workload": desc}, **cfg, system_matrix=args.model,
+                       **({"regularization": f"{args.reg} mu={args.reg_mu}"} if args.reg else {})),
         "admm_iters_per_s": {"batched_graph": n_slices * 1e3 / ms_per_step, "plain_loop": n_slices / plain_s,
                              "unit": "slice-iterations/s"},
         "equal_rmse": {"iterations": n_eq, "bit_identical": identical, "max_rel_rmse_diff": max(rel),
@@ -521,6 +552,7 @@ def main():
         "kmeans_lloyd_iters_last_step": lloyd,
         "projector_tiles": tiles,
         "iteration_graph": {"form": form, "trial_us": trial_us},
+        "regularization": zinfo,
         "phases_us": dict({k: v * 1e3 for k, v in kern.items()}, consensus=consensus_us),
         "roofline": {"bound": "alu", "kernel": PHASE_KERNELS[dom], "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,

@@ -131,7 +131,8 @@ class DADMM:
             self.regs = T.make_regs(ents)
             self.regs_per_slice = [T.make_regs([e]) for e in ents]
 
-    def _consensus(self, nodes, msgs, regs, stream=None):
+    def consensus(self, nodes, msgs, regs, stream=None):
+        """The consensus call of the listed nodes, with the regularization blocks if any."""
         if regs is None:
             T.admm_consensus(self.ctx, nodes, self.mode, self.e2, self.quant, msgs, stream)
         else:
@@ -141,7 +142,7 @@ class DADMM:
         if self.regs is not None:
             T.admm_reg_update(self.ctx, self.nodes, self.regs, stream)
         T.admm_local_update(self.ctx, self.nodes, self.e1, stream)
-        self._consensus(self.nodes, self.msgs, self.regs, stream)
+        self.consensus(self.nodes, self.msgs, self.regs, stream)
 
     def step_plain(self, stream=None):
         for si, (a, b) in enumerate(self.slice_ranges):
@@ -149,7 +150,7 @@ class DADMM:
                 T.admm_reg_update(self.ctx, self.per_slice[si], self.regs_per_slice[si], stream)
             for i in range(a, b):
                 T.admm_local_update(self.ctx, self.single[i], self.e1, stream)
-            self._consensus(self.per_slice[si], None, None if self.regs is None else self.regs_per_slice[si],
+            self.consensus(self.per_slice[si], None, None if self.regs is None else self.regs_per_slice[si],
                             stream)
 
     def prime(self, stream=None):
@@ -178,7 +179,7 @@ class DADMM:
         ready.record(main)
         # the consensus is issued first so that its few large workgroups reach
         # the CUs before the projector's fill them
-        self._consensus(self.nodes, self.msgs, self.regs)
+        self.consensus(self.nodes, self.msgs, self.regs)
         side.wait_event(ready)
         with torch.cuda.stream(side):
             T.admm_local_phase(self.ctx, self.nodes, 0)

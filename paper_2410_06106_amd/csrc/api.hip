@@ -883,7 +883,7 @@ RegPlan* get_reg_plan(tomo_ctx* ctx, const tomo_reg* regs, int n_regs, const std
       plan->max_iters = std::max(plan->max_iters, j.iters);
     }
     j.wg_begin = w;
-    w += (int)(((long long)ns[r] * ns[r] + 255) / 256);
+    w += ((ns[r] + TV_TILE_H - 1) / TV_TILE_H) * ((ns[r] + TV_TILE_W - 1) / TV_TILE_W);   // one workgroup per tile
     jobs.push_back(j);
   }
   if (n_regs > 0 &&
@@ -1316,7 +1316,8 @@ int admm_reg_update(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, cons
   Many<RegJob> js{static_cast<const RegJob*>(plan->jobs.p), plan->n_jobs};
   hipLaunchKernelGGL(k_reg_init, dim3(plan->wgs), dim3(256), 0, s, js);
   if (plan->any_tv) {
-    for (int t = 0; t < plan->max_iters; ++t) hipLaunchKernelGGL(k_tv_iter, dim3(plan->wgs), dim3(256), 0, s, js, t);
+    for (int t = 0; t < plan->max_iters; t += TV_BLOCK)
+      hipLaunchKernelGGL(k_tv_iter, dim3(plan->wgs), dim3(256), 0, s, js, t);
     hipLaunchKernelGGL(k_tv_final, dim3(plan->wgs), dim3(256), 0, s, js);
   }
   return launch_status(ctx, "admm_reg_update");

@@ -189,10 +189,14 @@ constexpr int KM_LDS_VALUES = 16384;
 // ---------------------------------------------------------------------------
 // Regularization block (one per slice): z = prox_{theta R}(x - nu / rho_z),
 // theta = mu / rho_z; R Tikhonov (1/2 ||z||^2) or isotropic TV by Chambolle's
-// dual projection iterations on the field (p1, p2), ping-ponged between the
-// caller's buffer (slot 0) and a library scratch buffer (slot 1).
+// dual projection iterations on the field (p1, p2), ping-ponged per launch
+// between the caller's buffer (slot 0) and a library scratch buffer (slot 1).
 // ---------------------------------------------------------------------------
 enum { REG_TIKHONOV = 1, REG_TV = 2 };
+constexpr int TV_BLOCK = 4;     // Chambolle iterations per k_tv_iter launch (and its halo width)
+// k_reg_init / k_tv_iter / k_tv_final: one workgroup per tile of 8 rows x
+// (64 - 2 TV_BLOCK) columns
+constexpr int TV_TILE_H = 8, TV_TILE_W = 64 - 2 * TV_BLOCK;
 
 // One Alg. 3 step with a block's term, x - eta2 (rho (x - u - lambda/rho) +
 // rho_z (x - t_z)), with every fused multiply-add explicit so that each kernel

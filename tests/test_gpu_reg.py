@@ -40,7 +40,7 @@ def _slice_nodes(T, n, n_nodes, x, us, lams, rho=1.0, eta2=0.2, slice_id=0):
     return ents
 
 
-@pytest.mark.parametrize("iters", [0, 1, 7, 10])
+@pytest.mark.parametrize("iters", [0, 1, 7, 10, 16, 17])
 def test_z_update_matches_oracle(mods, ctx, iters):
     """Two blocks in one call: TV on a 130 x 130 slice (several workgroups, a
     ragged tail) from a non-zero field, Tikhonov on a 37 x 37 slice."""
