@@ -6,6 +6,8 @@
             levels (the elbow method of Section 3.3) and the DCT codec at
             several quality factors;
 * Fig. 6-7  robustness to Gaussian measurement noise given as NSD (Eq. 27);
+* Section 4 the regularization block the discussion proposes (TV or Tikhonov
+            as one more ADMM sub-problem) on the noisiest data of Fig. 6-7;
 * Eq. 20    per-node traffic of each run from its real messages (K-means
             labels packed by ``tomo_pack_labels`` plus the codebook; DCT codes
             entropy-coded by ``tomo_dct_encode``; float32 segments without
@@ -121,11 +123,12 @@ def run_ctr(ctx, w, truth, th, d, iters: int, c: float = 1.0, tol: float = 1e-6,
 
 def run_dadmm(ctx, w, truth, d, quant: str = "none", level: int = 0, iters: int = 1000, c: float = 0.1,
               tol: float = 1e-6, mode: int = T.TOMO_XUPDATE_SEGMENT, nsd: float = 0.0,
-              eta1: float | None = None) -> Run:
+              eta1: float | None = None, reg: dict | None = None) -> Run:
     """Alg. 4 on ``w.n_nodes`` nodes with Q = K-means (``level`` = K), the DCT codec
     (``level`` = quality) or none, until the relative change of x drops below
     ``tol`` or after ``iters`` iterations.  eta1 = c / (L + rho) with L the largest
-    ||P_m^T P_m|| unless ``eta1`` is given."""
+    ||P_m^T P_m|| unless ``eta1`` is given.  ``reg``: a regularization block
+    (see ``admm.DADMM``)."""
     s = A.make_slice(ctx, w, d_host=d, truth_host=truth)
     s.eta1 = A.step_size(ctx, s, w.rho, c) if eta1 is None else eta1
     msgs, coeffs = None, []
@@ -144,7 +147,7 @@ def run_dadmm(ctx, w, truth, d, quant: str = "none", level: int = 0, iters: int 
     else:
         q, bits = None, 32.0
     run = A.DADMM(ctx, [s], rho=w.rho, eta2=w.eta2, e1=w.inner_iters, e2=w.x_iters, mode=mode, quant=q,
-                  msgs=msgs)
+                  msgs=msgs, reg=reg)
     stop, trace = _Stopper(ctx, s.x), []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -177,6 +180,8 @@ def run_dadmm(ctx, w, truth, d, quant: str = "none", level: int = 0, iters: int 
     best = int(np.argmin(trace))
     peak = float(truth.max())
     label = {"none": "dADMM", "kmeans": f"dADMM-K K={level}", "dct": f"dADMM-J q={level}"}[quant]
+    if reg is not None:
+        label += f" +{'TV' if reg['kind'] == T.TOMO_REG_TV else 'Tikhonov'} mu={reg['mu']:g}"
     return Run(f"{label} M={w.n_nodes}", "dadmm", w.n_nodes, quant, level, nsd, len(trace), trace[-1],
                _psnr(trace[-1], peak), trace[best], best + 1, bits, traffic, eq20, sec, trace)
 
@@ -208,7 +213,21 @@ def study_noise(ctx, w, iters, k=3, quality=30, nsds=(0.0,) + NSD_LEVELS):
     return out
 
 
-STUDIES = {"ctr": study_ctr, "elbow": study_elbow, "noise": study_noise}
+def study_reg(ctx, w, iters, nsd=NSD_LEVELS[-1], k=3, mus=(0.01, 0.05, 0.2)):
+    """Section 4: the regularization block on the noisiest data of Fig. 6-7,
+    dADMM-K (K = 3) alone, with a TV block (10 Chambolle iterations per
+    z-update) at several weights, and with a Tikhonov block."""
+    truth, _, d = make_problem(ctx, w, nsd)
+    out = [run_dadmm(ctx, w, truth, d, "kmeans", k, iters, nsd=nsd)]
+    for mu in mus:
+        out.append(run_dadmm(ctx, w, truth, d, "kmeans", k, iters, nsd=nsd,
+                             reg=dict(kind=T.TOMO_REG_TV, mu=mu, tv_iters=10)))
+    out.append(run_dadmm(ctx, w, truth, d, "kmeans", k, iters, nsd=nsd,
+                         reg=dict(kind=T.TOMO_REG_TIKHONOV, mu=mus[1])))
+    return out
+
+
+STUDIES = {"ctr": study_ctr, "elbow": study_elbow, "noise": study_noise, "reg": study_reg}
 
 
 def table(runs) -> str:
@@ -248,7 +267,7 @@ def main(argv=None):
     for name in (sorted(STUDIES) if args.study == "all" else [args.study]):
         print(f"== {name}: {w.n}x{w.n}, {w.n_angles} angles, {w.n_bins} bins, up to {iters} iterations, "
               f"{args.model} system matrix", flush=True)
-        kw = {} if name == "noise" else {"nsd": args.nsd}
+        kw = {} if name in ("noise", "reg") else {"nsd": args.nsd}
         res = STUDIES[name](ctx, w, iters, **kw)
         print(table(res), flush=True)
         runs += res

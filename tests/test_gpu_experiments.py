@@ -13,6 +13,7 @@ from gpu_common import log, require_gpu
 from oracle import admm as oadmm
 from oracle import joseph, stepsize
 from oracle.metrics import comm_per_node, rmse
+from oracle import reg as oreg
 from oracle import wire
 
 pytestmark = pytest.mark.gpu
@@ -49,12 +50,12 @@ def _eta1(w, th, c=0.1):
     return float(np.float32(c / (L + w.rho)))
 
 
-def _oracle_trace(w, truth, th, d, quant, iters, eta1):
+def _oracle_trace(w, truth, th, d, quant, iters, eta1, reg=None):
     parts = synthdata.partition_angles(w.n_angles, w.n_nodes, w.split)
     prob = oadmm.Problem(w.n, w.n_bins, [th[p] for p in parts], [d[p].astype(np.float64) for p in parts],
                          synthdata.segment_rows(w.n, w.n_nodes), truth.astype(np.float64))
     _, _, _, tr = oadmm.run(prob, iters, w.rho, eta1, w.inner_iters, w.eta2, w.x_iters, mode="seg",
-                            quant=quant, cast32=True)
+                            quant=quant, cast32=True, reg=reg)
     return np.array(tr.rmse)
 
 
@@ -85,6 +86,19 @@ def test_dadmm_without_quantizer_matches_oracle(E, ctx):
     want = _oracle_trace(W, truth, th, d, oadmm.Quantizer("none"), 6, eta1)
     np.testing.assert_allclose(run.trace, want, rtol=1e-4)
     assert run.bits_per_value == 32.0
+
+
+def test_dadmm_with_tv_block_matches_oracle(E, ctx):
+    """The regularization study's runs: unquantized dADMM with a TV block."""
+    truth, th, d = _inputs(W, nsd=2.43)
+    eta1 = _eta1(W, th)
+    run = E.run_dadmm(ctx, W, truth, d, "none", 0, iters=6, tol=0.0, eta1=eta1,
+                      reg=dict(kind=E.T.TOMO_REG_TV, mu=0.05, tv_iters=10))
+    want = _oracle_trace(W, truth, th, d, oadmm.Quantizer("none"), 6, eta1,
+                         reg=oreg.Reg(kind=oreg.TV, mu=0.05, rho=W.rho, tv_iters=10))
+    log(f"  gpu {np.array(run.trace)} oracle {want}")
+    np.testing.assert_allclose(run.trace, want, rtol=1e-4)
+    assert "+TV mu=0.05" in run.label
 
 
 def test_dadmm_dct_runs_match_oracle(E, ctx):
