@@ -8,7 +8,7 @@
 #include <unordered_map>
 #include <vector>
 
-#include "common.h"
+#include "consensus.h"
 #include "codec.h"
 #include "../../include/tomoadmm.h"
 
@@ -19,7 +19,7 @@ template <class Src> __global__ void k_project_res(Src);
 template <class Src> __global__ void k_project_res_reduce(Src);
 template <class Src, bool CHORD> __global__ void k_backproject(Src);
 __global__ void k_seg_none(const SegJob*, int, int);
-template <bool REG> __global__ void k_kmeans(const KMJob*, KMJob, int, int, int);
+template <bool REG, bool TZ> __global__ void k_kmeans(const KMJob*, KMJob, int, int, int, const KMBlock*);
 __global__ void k_seg_dct(const SegJob*, int, int, int);
 __global__ void k_dct(const float*, int, int, int, int, int16_t*, float*, float*);
 __global__ void k_avg(Many<AvgJob>, const NodeRef*);
@@ -318,7 +318,7 @@ struct ConsPlan {
   std::vector<tomo_node> key;
   std::vector<tomo_msg> msg_key;
   std::vector<tomo_reg> reg_key;
-  DevBuf seg, avg, noderefs, labels, kmjobs, kmwork;
+  DevBuf seg, avg, noderefs, labels, kmjobs, kmwork, kmblocks;
   int n_seg = 0, n_avg = 0, avg_wgs = 0, dual_wgs = 0;
   int n_refs = 0;                 // dual-update entries: the nodes, then the regularization blocks
   int km_small = 0, km_big = 0;   // K-means jobs regrouping in LDS, then those using the workspace
@@ -958,6 +958,7 @@ ConsPlan* get_cons_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, cons
   // K-means jobs: segments that fit the registers first, then the longer ones,
   // each with its own slice of the label scratch and of the workspace
   std::vector<KMJob> km_small, km_big;
+  std::vector<KMBlock> kb_small, kb_big;
   std::vector<size_t> label_off(n_nodes), work_off(n_nodes, 0);
   size_t label_elems = 0, work_elems = 0;
   for (int i = 0; i < n_nodes; ++i) {
@@ -986,9 +987,10 @@ ConsPlan* get_cons_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, cons
     j.a_hat = N.x + off;
     j.u = N.u + off;
     j.lam = N.lam + off;
+    KMBlock kb{nullptr, 0.f};
     if (const tomo_reg* B = reg_of(regs, n_regs, N.slice)) {
-      j.tz = B->tz + off;
-      j.rho_z = B->rho;
+      kb.tz = B->tz + off;
+      kb.rho_z = B->rho;
     }
     j.n = (long long)N.seg_rows * N.g.n;
     j.rho = N.rho;
@@ -999,13 +1001,23 @@ ConsPlan* get_cons_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, cons
     if (j.n > KM_LDS_VALUES) {
       j.work = static_cast<float*>(plan->kmwork.p) + work_off[i];
       km_big.push_back(j);
+      kb_big.push_back(kb);
     } else {
       km_small.push_back(j);
+      kb_small.push_back(kb);
     }
   }
   plan->km_small = (int)km_small.size();
   plan->km_big = (int)km_big.size();
   km_small.insert(km_small.end(), km_big.begin(), km_big.end());
+  kb_small.insert(kb_small.end(), kb_big.begin(), kb_big.end());
+  if (n_regs > 0 &&
+      (!plan->kmblocks.ensure(kb_small.size() * sizeof(KMBlock)) ||
+       hipMemcpy(plan->kmblocks.p, kb_small.data(), kb_small.size() * sizeof(KMBlock), hipMemcpyHostToDevice) !=
+           hipSuccess)) {
+    rc = ctx->fail(TOMO_EDEVICE, "K-means block table upload failed");
+    return nullptr;
+  }
   if (hipMemcpy(plan->kmjobs.p, km_small.data(), km_small.size() * sizeof(KMJob), hipMemcpyHostToDevice) !=
       hipSuccess) {
     rc = ctx->fail(TOMO_EDEVICE, "K-means plan upload failed");
@@ -1283,13 +1295,15 @@ int admm_consensus_reg(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, i
   if (kind == TOMO_QUANT_KMEANS) {
     // the x-update (SEG) runs inside the K-means kernel; AVG already wrote x
     const KMJob* kj = static_cast<const KMJob*>(plan->kmjobs.p);
+    const KMBlock* kb = plan->reg_key.empty() ? nullptr : static_cast<const KMBlock*>(plan->kmblocks.p);
     const int ex = do_x ? e2 : 0;
     if (plan->km_small > 0)
-      hipLaunchKernelGGL(k_kmeans<true>, dim3(plan->km_small), dim3(kKmThreads), 0, s, kj, KMJob{}, q->levels,
-                         q->max_iter, ex);
+      hipLaunchKernelGGL((plan->reg_key.empty() ? k_kmeans<true, false> : k_kmeans<true, true>), dim3(plan->km_small),
+                         dim3(kKmThreads), 0, s, kj, KMJob{}, q->levels, q->max_iter, ex, kb);
     if (plan->km_big > 0)
-      hipLaunchKernelGGL(k_kmeans<false>, dim3(plan->km_big), dim3(kKmThreads), 0, s, kj + plan->km_small,
-                         KMJob{}, q->levels, q->max_iter, ex);
+      hipLaunchKernelGGL((plan->reg_key.empty() ? k_kmeans<false, false> : k_kmeans<false, true>), dim3(plan->km_big),
+                         dim3(kKmThreads), 0, s, kj + plan->km_small, KMJob{}, q->levels, q->max_iter, ex,
+                         kb ? kb + plan->km_small : nullptr);
   } else if (kind == TOMO_QUANT_DCT) {
     hipLaunchKernelGGL(k_seg_dct, dim3(plan->n_seg), dim3(256), 0, s, seg, do_x, e2, q->quality);
   } else if (do_x) {
@@ -1344,11 +1358,11 @@ int quantize_kmeans(tomo_ctx* ctx, const float* a, int64_t n, int32_t k, int32_t
   j.rho = 1.f;
   if (big) {
     j.work = static_cast<float*>(ctx->km_work.p);
-    hipLaunchKernelGGL(k_kmeans<false>, dim3(1), dim3(kKmThreads), 0, (hipStream_t)stream, nullptr, j, k, max_iter,
-                       0);
+    hipLaunchKernelGGL((k_kmeans<false, false>), dim3(1), dim3(kKmThreads), 0, (hipStream_t)stream, nullptr, j, k, max_iter,
+                       0, (const KMBlock*)nullptr);
   } else {
-    hipLaunchKernelGGL(k_kmeans<true>, dim3(1), dim3(kKmThreads), 0, (hipStream_t)stream, nullptr, j, k, max_iter,
-                       0);
+    hipLaunchKernelGGL((k_kmeans<true, false>), dim3(1), dim3(kKmThreads), 0, (hipStream_t)stream, nullptr, j, k, max_iter,
+                       0, (const KMBlock*)nullptr);
   }
   return launch_status(ctx, "quantize_kmeans");
 }

@@ -1,4 +1,6 @@
-// Shared device-side definitions of the tomoadmm HIP library (gfx950).
+// Shared device-side definitions of the tomoadmm HIP library (gfx950): job
+// sources and the projector / backprojector descriptors (the consensus,
+// quantizer and regularization descriptors are in consensus.h).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -123,105 +125,6 @@ __host__ __device__ __forceinline__ void angle_trig(double th, int chord, double
   }
   cs = c;
   sn = s;
-}
-
-// ---------------------------------------------------------------------------
-// Consensus / quantization: one job = one segment of one node.
-// ---------------------------------------------------------------------------
-struct SegJob {
-  float* x;             // slice consensus image [n][n]
-  const float* u;       // this node's u (SEG mode)
-  const float* lam;     // this node's lambda (SEG mode)
-  const float* tz;      // regularization block's target z + nu / rho_z [n][n], or null
-  float rho_z;          // its penalty
-  int n, row0, rows;
-  float rho, eta2;
-  // AVG mode: the slice's nodes are nodes[node0 .. node0 + n_nodes)
-  int node0, n_nodes;
-  // message outputs (nullable)
-  uint8_t* labels;
-  float* centroids;
-  int32_t* iters;
-  int16_t* coeffs;
-  float* lohi;
-};
-
-struct NodeRef {        // u, lambda of one node (AVG gather, dual update)
-  float* u;
-  float* lam;
-  const float* x;
-  int n;
-  float rho;
-  int wg_begin;
-};
-
-struct AvgJob {         // x = mean over nodes[node0 .. node0+n_nodes) of u + lambda/rho
-  float* x;
-  const float* tz;      // regularization block's target, or null (then the plain mean)
-  float rho_z;
-  int node0, n_nodes, n;
-  int wg_begin;
-};
-
-// K-means over segments: one job per segment (see kmeans.hip)
-constexpr int KM_MAX_K = 256;
-
-struct KMJob {
-  const float* src;     // values (the segment of x in the consensus step)
-  float* x;             // where the x-updated values are stored (consensus)
-  float* a_hat;         // quantized values (nullable, may equal src)
-  const float* u;       // Alg. 3 inputs, or null for no x-update
-  const float* lam;
-  const float* tz;      // regularization block's target of the segment, or null
-  float rho_z;
-  uint8_t* labels;      // [n] (nullable)
-  float* cent;          // [k] (nullable)
-  int32_t* iters;       // [1] (nullable)
-  float* work;          // [n] regrouping workspace, required when n > KM_LDS_VALUES
-  long long n;          // < 2^31
-  float rho, eta2;
-};
-
-// Segments up to this many values are regrouped in LDS; longer ones in the
-// job's global workspace of n floats.
-constexpr int KM_LDS_VALUES = 16384;
-
-// ---------------------------------------------------------------------------
-// Regularization block (one per slice): z = prox_{theta R}(x - nu / rho_z),
-// theta = mu / rho_z; R Tikhonov (1/2 ||z||^2) or isotropic TV by Chambolle's
-// dual projection iterations on the field (p1, p2), ping-ponged per launch
-// between the caller's buffer (slot 0) and a library scratch buffer (slot 1).
-// ---------------------------------------------------------------------------
-enum { REG_TIKHONOV = 1, REG_TV = 2 };
-constexpr int TV_BLOCK = 4;     // Chambolle iterations per k_tv_iter launch (and its halo width)
-// k_reg_init / k_tv_iter / k_tv_final: one workgroup per tile of 8 rows x
-// (64 - 2 TV_BLOCK) columns
-constexpr int TV_TILE_H = 8, TV_TILE_W = 64 - 2 * TV_BLOCK;
-
-// One Alg. 3 step with a block's term, x - eta2 (rho (x - u - lambda/rho) +
-// rho_z (x - t_z)), with every fused multiply-add explicit so that each kernel
-// running it rounds the same way.
-__device__ __forceinline__ float xstep_reg(float xv, float uv, float lv, float tv, float rho, float irho,
-                                           float rho_z, float eta2) {
-  const float a = fmaf(-lv, irho, xv - uv);
-  const float delta = fmaf(rho, a, rho_z * (xv - tv));
-  return fmaf(-eta2, delta, xv);
-}
-
-struct RegJob {
-  const float* x;       // slice consensus image [n][n]
-  const float* nu;      // block dual
-  float* z;             // block copy (output)
-  float* tz;            // v = x - nu / rho_z during the iterations, then z + nu / rho_z
-  float* p[2];          // TV dual field slots, each [2][n][n] (p1 then p2)
-  int n, kind, iters;
-  float theta, irho_z, tau;
-  int wg_begin;
-};
-
-__device__ __forceinline__ float wave_sum(float v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
 }
 
 }  // namespace tomo

@@ -6,7 +6,7 @@
 // One workgroup owns one segment for the x-update and the DCT quantizer, so a
 // segment's level-map range never leaves the workgroup.  (The K-means quantizer
 // lives in kmeans.hip.)
-#include "common.h"
+#include "consensus.h"
 
 namespace tomo {
 
@@ -45,8 +45,8 @@ __device__ void segment_xupdate(const SegJob& S, int e2) {
     float xv = S.x[base + i];
     const float uv = S.u[base + i], lv = S.lam[base + i];
     if (S.tz) {
-      const float tv = S.tz[base + i];
-      for (int e = 0; e < e2; ++e) xv = xstep_reg(xv, uv, lv, tv, S.rho, irho, S.rho_z, S.eta2);
+      const float tm = reg_target(uv, lv, irho), tv = S.tz[base + i];
+      for (int e = 0; e < e2; ++e) xv = xstep_reg(xv, tm, tv, S.rho, S.rho_z, S.eta2);
     } else {
       for (int e = 0; e < e2; ++e) {
         float delta = S.rho * (xv - uv - lv * irho);

@@ -30,7 +30,7 @@
 // updates them from the shared counts.  Segments of up to 16384 values stay in
 // registers from the first pass to the last, where labels and quantized values
 // are written.  The optional Alg. 3 x-update of the segment is applied on load.
-#include "common.h"
+#include "consensus.h"
 
 namespace tomo {
 
@@ -74,9 +74,9 @@ __device__ __forceinline__ float km_xupdate(float xv, float uv, float lv, float 
 }
 
 // the same with a regularization block's target t_z and penalty rho_z
-__device__ __forceinline__ float km_xupdate_reg(float xv, float uv, float lv, float tv, float rho, float irho,
-                                                float rho_z, float eta2, int e2) {
-  for (int e = 0; e < e2; ++e) xv = xstep_reg(xv, uv, lv, tv, rho, irho, rho_z, eta2);
+__device__ __forceinline__ float km_xupdate_reg(float xv, float tm, float tv, float rho, float rho_z, float eta2,
+                                                int e2) {
+  for (int e = 0; e < e2; ++e) xv = xstep_reg(xv, tm, tv, rho, rho_z, eta2);
   return xv;
 }
 
@@ -204,9 +204,12 @@ __device__ __forceinline__ void at_or_below(const KMShared& sh, VP V, float x, c
 
 // One workgroup per segment.  REG: the segment fits the registers (n <=
 // KM_LDS_VALUES) and its bucket-ordered copy fits LDS; otherwise the values
-// are streamed in every pass and the copy goes to the job's workspace.
-template <bool REG>
-__global__ __launch_bounds__(KT) void k_kmeans(const KMJob* jobs, KMJob single, int k, int max_iter, int e2) {
+// are streamed in every pass and the copy goes to the job's workspace.  TZ:
+// jobs may carry a regularization block's target (a separate instantiation,
+// so that the kernel without blocks keeps its register allocation).
+template <bool REG, bool TZ>
+__global__ __launch_bounds__(KT) void k_kmeans(const KMJob* jobs, KMJob single, int k, int max_iter, int e2,
+                                               const KMBlock* blocks) {
 #pragma clang fp contract(off)
   __shared__ KMShared sh;
   __shared__ float vlds[REG ? KM_LDS_VALUES : 1];
@@ -221,7 +224,6 @@ __global__ __launch_bounds__(KT) void k_kmeans(const KMJob* jobs, KMJob single, 
   const auto ahat = gptr(J.a_hat);
   const auto uu = gptr(J.u);
   const auto ll = gptr(J.lam);
-  const auto tzz = gptr(J.tz);
   const auto labels = gptr(J.labels);
   const auto vals = do_x ? gptr((const float*)J.x) : src;   // the segment after the x-update
   if (n <= 0) {
@@ -277,17 +279,21 @@ __global__ __launch_bounds__(KT) void k_kmeans(const KMJob* jobs, KMJob single, 
         uv[e] = uu[i < n ? i : n - 1];
         lv[e] = ll[i < n ? i : n - 1];
       }
-      if (J.tz) {
-        float tv[KVPT];
+      const KMBlock RB = (TZ && blocks) ? blocks[seg] : KMBlock{nullptr, 0.f};
+      if (TZ && RB.tz) {
+        const auto tzz = gptr(RB.tz);
+        // t_m = u + lambda/rho into the u registers, then t_z into the lambda
+        // registers (no more values in flight than without the block)
 #pragma unroll
         for (int e = 0; e < KVPT; ++e) {
           const long long i = base + tid + (long long)e * KT;
-          tv[e] = tzz[i < n ? i : n - 1];
+          uv[e] = reg_target(uv[e], lv[e], irho);
+          lv[e] = tzz[i < n ? i : n - 1];
         }
 #pragma unroll
         for (int e = 0; e < KVPT; ++e) {
           const long long i = base + tid + (long long)e * KT;
-          a[e] = km_xupdate_reg(a[e], uv[e], lv[e], tv[e], J.rho, irho, J.rho_z, J.eta2, e2);
+          a[e] = km_xupdate_reg(a[e], uv[e], lv[e], J.rho, RB.rho_z, J.eta2, e2);
           if (i < n) xo[i] = a[e];
         }
       } else {
@@ -518,7 +524,9 @@ __global__ __launch_bounds__(KT) void k_kmeans(const KMJob* jobs, KMJob single, 
   if (J.iters && tid == 0) *J.iters = it;
 }
 
-template __global__ void k_kmeans<true>(const KMJob*, KMJob, int, int, int);
-template __global__ void k_kmeans<false>(const KMJob*, KMJob, int, int, int);
+template __global__ void k_kmeans<true, false>(const KMJob*, KMJob, int, int, int, const KMBlock*);
+template __global__ void k_kmeans<false, false>(const KMJob*, KMJob, int, int, int, const KMBlock*);
+template __global__ void k_kmeans<true, true>(const KMJob*, KMJob, int, int, int, const KMBlock*);
+template __global__ void k_kmeans<false, true>(const KMJob*, KMJob, int, int, int, const KMBlock*);
 
 }  // namespace tomo

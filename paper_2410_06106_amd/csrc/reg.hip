@@ -18,7 +18,7 @@
 // the tile's field out, instead of 20 bytes per pixel for every iteration.
 // The update divides by 1 + tau |grad w| with the hardware reciprocal and
 // square root (each within about one unit in the last place).
-#include "common.h"
+#include "consensus.h"
 
 namespace tomo {
 
