@@ -160,7 +160,8 @@ class DADMM:
 
     def step_pipelined(self, side):
         """One iteration whose first projection (residual P_m u_m - d_m) was
-        launched by prime() or by the previous call.  At its end the next
+        launched by prime() or by the previous call.  With regularization
+        blocks, their z-update runs on stream ``side`` beside the local update.  At its end the next
         iteration's first projection runs on stream ``side`` concurrently with
         this iteration's consensus: it reads only u_m and d_m, which the
         consensus (x-update, quantizer, dual update) does not write, and writes
@@ -169,12 +170,21 @@ class DADMM:
         if self.e1 < 1:
             raise ValueError("the pipelined iteration needs E1 >= 1")
         main = torch.cuda.current_stream()
+        zdone = None
         if self.regs is not None:
-            T.admm_reg_update(self.ctx, self.nodes, self.regs)
+            # the z-update reads x^k and nu^k, which the local update does not
+            # touch: it runs on the side stream beside the local update
+            side.wait_stream(main)
+            with torch.cuda.stream(side):
+                T.admm_reg_update(self.ctx, self.nodes, self.regs)
+            zdone = torch.cuda.Event()
+            zdone.record(side)
         T.admm_local_phase(self.ctx, self.nodes, 1)
         for _ in range(self.e1 - 1):
             T.admm_local_phase(self.ctx, self.nodes, 0)
             T.admm_local_phase(self.ctx, self.nodes, 1)
+        if zdone is not None:
+            main.wait_event(zdone)
         ready = torch.cuda.Event()
         ready.record(main)
         # the consensus is issued first so that its few large workgroups reach
