@@ -330,7 +330,8 @@ constexpr int kKmThreads = 1024;
 // scratch fields, built once per block array (and the slices' images)
 struct RegPlan {
   std::vector<tomo_reg> key;
-  std::vector<const float*> xs;
+  std::vector<const float*> xs;   // each block's slice image and side: part of the key
+  std::vector<int> ns;
   DevBuf jobs, scratch;
   int n_jobs = 0, wgs = 0, max_iters = 0;
   bool any_tv = false;
@@ -849,10 +850,11 @@ RegPlan* get_reg_plan(tomo_ctx* ctx, const tomo_reg* regs, int n_regs, const std
                       const std::vector<int>& ns, int& rc) {
   rc = TOMO_OK;
   for (auto& p : ctx->rplans)
-    if (same_regs(p->key, regs, n_regs) && p->xs == xs) return p.get();
+    if (same_regs(p->key, regs, n_regs) && p->xs == xs && p->ns == ns) return p.get();
   auto plan = std::make_unique<RegPlan>();
   plan->key.assign(regs, regs + n_regs);
   plan->xs = xs;
+  plan->ns = ns;
   size_t scratch = 0;
   for (int r = 0; r < n_regs; ++r)
     if (regs[r].kind == TOMO_REG_TV) scratch += 2 * (size_t)ns[r] * ns[r];

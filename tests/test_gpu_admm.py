@@ -215,6 +215,23 @@ def test_pipelined_iteration_matches_step(mods, ctx):
         log(f"  replay {k}: identical to step()")
 
 
+def test_dispatch_order_on_a_one_workgroup_plan(mods):
+    """A plan of fewer projector workgroups than dies (one 8 x 8 node, 3
+    angles: one workgroup) in both dispatch orders: the same local update."""
+    T, A = mods
+    out = []
+    for order in (0, 1):
+        c = T.Context(0)
+        T.tomo_set_option(c, T.TOMO_OPT_PROJ_ORDER, order)
+        w = synthdata.Workload("one", 4, 8, 3, 12, 1, "interleaved", 3, "gaussian", 0.01, 2)
+        s = A.make_slice(c, w)
+        s.eta1 = 1e-3
+        T.admm_local_update(c, A.DADMM(c, [s]).nodes, 3)
+        torch.cuda.synchronize()
+        out.append(s.u[0].cpu().clone())
+    assert torch.equal(out[0], out[1]) and out[0].abs().max() > 0
+
+
 def test_dispatch_order_does_not_change_results(mods):
     """The batched projector started in estimated-cost order
     (TOMO_OPT_PROJ_ORDER = 1, the default) and in node order (0) gives the same

@@ -76,6 +76,28 @@ def test_z_update_matches_oracle(mods, ctx, iters):
             assert rel_l2(gp[0], pz[0]) <= 1e-5 and rel_l2(gp[1], pz[1]) <= 1e-5
 
 
+@pytest.mark.parametrize("n", [1, 2, 9])
+def test_z_update_tiny_images(mods, ctx, n):
+    """TV z-updates on images smaller than one tile (1 x 1: no differences at
+    all; 2 x 2; 9 x 9), 6 iterations from a non-zero field."""
+    T, _ = mods
+    rng = np.random.default_rng(30 + n)
+    x = rng.standard_normal((n, n)).astype(np.float32)
+    nu = (0.3 * rng.standard_normal((n, n))).astype(np.float32)
+    p = (0.5 * rng.uniform(-1, 1, (2, n, n))).astype(np.float32)
+    t = dict(x=to_dev(x), z=torch.zeros((n, n), device="cuda"), nu=to_dev(nu), tz=torch.zeros((n, n), device="cuda"),
+             p=to_dev(p))
+    nodes = T.make_nodes(_slice_nodes(T, n, 1, t["x"], [torch.zeros((n, n), device="cuda")],
+                                      [torch.zeros((n, n), device="cuda")]))
+    regs = T.make_regs([dict(slice=0, kind=T.TOMO_REG_TV, mu=0.3, rho=1.0, tv_iters=6, tau=0.125, z=t["z"],
+                             nu=t["nu"], tz=t["tz"], p=t["p"])])
+    T.admm_reg_update(ctx, nodes, regs)
+    torch.cuda.synchronize()
+    z, pz = oreg.z_update(oreg.Reg(kind=oreg.TV, mu=0.3, rho=1.0, tv_iters=6), x, nu, (p[0], p[1]))
+    np.testing.assert_allclose(t["z"].cpu().numpy(), z, rtol=1e-5, atol=1e-6)
+    np.testing.assert_allclose(t["p"].cpu().numpy()[0], pz[0], rtol=1e-5, atol=1e-6)
+
+
 def _consensus_case(T, rng, n, n_nodes):
     x = rng.standard_normal((n, n)).astype(np.float32)
     us = [rng.standard_normal((n, n)).astype(np.float32) for _ in range(n_nodes)]
