@@ -139,3 +139,33 @@ def test_large_workload_local_update_sampled_node(mods):
     err = rel_l2(keep[2].cpu().numpy() - keep[0], ref - keep[0])
     log(f"  large node {m}: rel-L2 of the step {err:.3g}")
     assert err <= 1e-5
+
+
+def test_single_workload_tv_block_z_update(mods):
+    """The regularization block at bench.py --reg tv's settings on the 512^2,
+    16-node slice (TV, mu = 0.02, 10 Chambolle iterations: three launches, the
+    last with 2 iterations): z, t_z and the field after two z-updates (the
+    second warm-started from the first's field) against the oracle on the
+    whole image."""
+    from oracle import reg as oreg
+    T, A = mods
+    ctx = T.Context(0)
+    w = synthdata.WORKLOADS["single"]
+    s = _slice(T, A, ctx, w)
+    run = A.DADMM(ctx, [s], reg=dict(kind=T.TOMO_REG_TV, mu=0.02, tv_iters=10))
+    rng = np.random.default_rng(7)
+    nu = (0.05 * rng.standard_normal((w.n, w.n))).astype(np.float32)
+    s.reg["nu"].copy_(to_dev(nu))
+    x = s.x.cpu().numpy().astype(np.float64)
+    r = oreg.Reg(kind=oreg.TV, mu=0.02, rho=1.0, tv_iters=10)
+    p = None
+    for k in range(2):
+        T.admm_reg_update(ctx, run.nodes, run.regs)
+        torch.cuda.synchronize()
+        z, p = oreg.z_update(r, x, nu.astype(np.float64), p)
+        ez = rel_l2(s.reg["z"].cpu().numpy(), z)
+        et = rel_l2(s.reg["tz"].cpu().numpy(), z + nu / 1.0)
+        gp = s.reg["p"].cpu().numpy()
+        ep = max(rel_l2(gp[0], p[0]), rel_l2(gp[1], p[1]))
+        log(f"  z-update {k}: z rel {ez:.2e}, t_z rel {et:.2e}, field rel {ep:.2e}")
+        assert ez <= 1e-5 and et <= 1e-5 and ep <= 1e-5
