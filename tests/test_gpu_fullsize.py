@@ -169,3 +169,31 @@ def test_single_workload_tv_block_z_update(mods):
         ep = max(rel_l2(gp[0], p[0]), rel_l2(gp[1], p[1]))
         log(f"  z-update {k}: z rel {ez:.2e}, t_z rel {et:.2e}, field rel {ep:.2e}")
         assert ez <= 1e-5 and et <= 1e-5 and ep <= 1e-5
+
+
+def test_single_workload_chord_local_update_sampled_nodes(mods):
+    """bench.py --model chord's configuration: the 512^2, 16-node slice with the
+    chord-length system matrix (band 32, 48 workgroups per node, the batched
+    call with its dispatch table), one E1 = 1 step, two sampled nodes against
+    the oracle's Alg. 2 with the chord projector."""
+    from oracle import chord
+    T, A = mods
+    ctx = T.Context(0)
+    T.tomo_set_option(ctx, T.TOMO_OPT_PROJ_MODEL, 1)
+    T.tomo_set_option(ctx, T.TOMO_OPT_PROJ_BAND, 32)
+    T.tomo_set_option(ctx, T.TOMO_OPT_PROJ_JOB_WGS, 48)
+    w = synthdata.WORKLOADS["single"]
+    s = _slice(T, A, ctx, w)
+    s.eta1 = 2e-5
+    before = [(u.cpu().numpy(), lam.cpu().numpy()) for u, lam in zip(s.u, s.lam)]
+    x = s.x.cpu().numpy()
+    run = A.DADMM(ctx, [s], rho=w.rho, e1=1)
+    T.admm_local_update(ctx, run.nodes, 1)
+    th = synthdata.angles(w.n_angles)
+    parts = synthdata.partition_angles(w.n_angles, w.n_nodes, w.split)
+    for m in (0, 9):
+        d = s.d[m].cpu().numpy()
+        ref = oadmm.local_update(before[m][0], x, before[m][1], d, th[parts[m]], w.rho, s.eta1, 1, proj=chord)
+        err = rel_l2(s.u[m].cpu().numpy() - before[m][0], ref - before[m][0])
+        log(f"  chord node {m}: rel-L2 of the step {err:.3g}")
+        assert err <= 1e-5
