@@ -49,6 +49,38 @@ def test_struct_layouts():
     assert ctypes.sizeof(T.tomo_quant) == 16
     assert ctypes.sizeof(T.tomo_geom) == 8
     assert ctypes.sizeof(T.tomo_proj_item) == 40
+    assert ctypes.sizeof(T.tomo_reg) == 56
+
+
+def test_binding_structs_match_the_c_header(tmp_path):
+    """Every field offset and struct size of the ctypes binding equals what a C
+    compiler makes of include/tomoadmm.h (compiled as C with gcc)."""
+    import shutil
+    import subprocess
+    from paper_2410_06106_amd import tomoadmm as T
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    structs = [T.tomo_geom, T.tomo_node, T.tomo_quant, T.tomo_msg, T.tomo_proj_item, T.tomo_reg]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', 'int main(void) {']
+    for st in structs:
+        name = st.__name__
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for field, _ in st._fields_:
+            lines.append(f'  printf("{name} {field} %zu\\n", offsetof({name}, {field}));')
+    lines += ['  return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-o", str(exe), str(src)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        name, field, value = line.split()
+        got[(name, field)] = int(value)
+    for st in structs:
+        name = st.__name__
+        assert got[(name, "size")] == ctypes.sizeof(st), name
+        for field, _ in st._fields_:
+            assert got[(name, field)] == getattr(st, field).offset, (name, field)
 
 
 def test_status_strings_and_null_context(lib):

@@ -137,14 +137,15 @@ def test_consensus_with_block_matches_oracle(mods, ctx, mode):
     assert ex <= 1e-5 and enu <= 1e-5 and el <= 1e-5
 
 
-@pytest.mark.parametrize("quant", ["kmeans", "dct"])
-def test_quantized_consensus_with_block_equals_unquantized_then_quantizer(mods, ctx, quant):
+@pytest.mark.parametrize("quant,n,M", [("kmeans", 64, 4), ("dct", 64, 4), ("kmeans", 256, 2)])
+def test_quantized_consensus_with_block_equals_unquantized_then_quantizer(mods, ctx, quant, n, M):
     """The K-means kernel runs the x-update with the block's term on load, the
     DCT path before its transform: both equal the unquantized consensus followed
-    by the standalone quantizer on each segment, bit for bit."""
+    by the standalone quantizer on each segment, bit for bit.  256 x 256 on two
+    nodes gives segments of 32768 values, past the register-resident limit
+    (the K-means variant with the global workspace)."""
     T, _ = mods
     rng = np.random.default_rng(21)
-    n, M = 64, 4
     x, us, lams, z, nu, tz = _consensus_case(T, rng, n, M)
     outs = []
     for q in (None, quant):
