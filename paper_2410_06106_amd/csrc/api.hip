@@ -24,9 +24,7 @@ __global__ void k_seg_dct(const SegJob*, int, int, int);
 __global__ void k_dct(const float*, int, int, int, int, int16_t*, float*, float*);
 __global__ void k_avg(Many<AvgJob>, const NodeRef*);
 __global__ void k_dual(Many<NodeRef>);
-__global__ void k_reg_init(Many<RegJob>);
-__global__ void k_tv_iter(Many<RegJob>, int);
-__global__ void k_tv_final(Many<RegJob>);
+__global__ void k_reg_step(Many<RegJob>, int);
 __global__ void k_sqdiff(const float*, const float*, long long, double*);
 __global__ void k_pack_labels(const uint8_t*, int, int, unsigned*, long long);
 __global__ void k_ecode_bits(const int16_t*, int, int, int, unsigned*);
@@ -333,8 +331,8 @@ struct RegPlan {
   std::vector<const float*> xs;   // each block's slice image and side: part of the key
   std::vector<int> ns;
   DevBuf jobs, scratch;
-  int n_jobs = 0, wgs = 0, max_iters = 0;
-  bool any_tv = false;
+  int n_jobs = 0, wgs = 0;
+  int launches = 1;               // k_reg_step launches of one z-update (the most any block needs)
 };
 
 // FNV-1a hash of a descriptor array: the plan caches are indexed by it.
@@ -881,8 +879,7 @@ RegPlan* get_reg_plan(tomo_ctx* ctx, const tomo_reg* regs, int n_regs, const std
       j.p[0] = R.p;
       j.p[1] = sp;
       sp += 2 * (size_t)ns[r] * ns[r];
-      plan->any_tv = true;
-      plan->max_iters = std::max(plan->max_iters, j.iters);
+      plan->launches = std::max(plan->launches, tv_launches(j.iters));
     }
     j.wg_begin = w;
     w += ((ns[r] + TV_TILE_H - 1) / TV_TILE_H) * ((ns[r] + TV_TILE_W - 1) / TV_TILE_W);   // one workgroup per tile
@@ -1330,12 +1327,7 @@ int admm_reg_update(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, cons
   if (!plan) return rc;
   hipStream_t s = (hipStream_t)stream;
   Many<RegJob> js{static_cast<const RegJob*>(plan->jobs.p), plan->n_jobs};
-  hipLaunchKernelGGL(k_reg_init, dim3(plan->wgs), dim3(256), 0, s, js);
-  if (plan->any_tv) {
-    for (int t = 0; t < plan->max_iters; t += TV_BLOCK)
-      hipLaunchKernelGGL(k_tv_iter, dim3(plan->wgs), dim3(256), 0, s, js, t);
-    hipLaunchKernelGGL(k_tv_final, dim3(plan->wgs), dim3(256), 0, s, js);
-  }
+  for (int l = 0; l < plan->launches; ++l) hipLaunchKernelGGL(k_reg_step, dim3(plan->wgs), dim3(256), 0, s, js, l);
   return launch_status(ctx, "admm_reg_update");
 }
 

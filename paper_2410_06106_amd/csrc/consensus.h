@@ -80,10 +80,21 @@ constexpr int KM_LDS_VALUES = 16384;
 // between the caller's buffer (slot 0) and a library scratch buffer (slot 1).
 // ---------------------------------------------------------------------------
 enum { REG_TIKHONOV = 1, REG_TV = 2 };
-constexpr int TV_BLOCK = 4;     // Chambolle iterations per k_tv_iter launch (and its halo width)
-// k_reg_init / k_tv_iter / k_tv_final: one workgroup per tile of 8 rows x
-// (64 - 2 TV_BLOCK) columns
+constexpr int TV_BLOCK = 4;     // most Chambolle iterations per k_reg_step launch (and its halo width)
+// k_reg_step: one workgroup per tile of 8 rows x (64 - 2 TV_BLOCK) columns
 constexpr int TV_TILE_H = 8, TV_TILE_W = 64 - 2 * TV_BLOCK;
+
+// Launches of one TV z-update of T Chambolle iterations: the fewest that run at
+// most TV_BLOCK iterations each and at most TV_BLOCK - 1 in the last, rounded up
+// to an even count (so that the field ends in the slot it started from); one
+// launch when T = 0 (z from the field as it is).
+__host__ __device__ inline int tv_launches(int T) {
+  return T == 0 ? 1 : ((T / TV_BLOCK + 2) & ~1);
+}
+// iterations of launch l of L: T spread evenly, the remainder on the first ones
+__host__ __device__ inline int tv_launch_iters(int T, int L, int l) {
+  return T / L + (l < T % L ? 1 : 0);
+}
 
 // One Alg. 3 step with a block's term, x - eta2 (rho (x - t_m) + rho_z (x - t_z)),
 // t_m = u + lambda/rho formed once per value (reg_target), with every fused

@@ -8,16 +8,19 @@
 // Chambolle's dual projection iterations
 //   w = div p - v / theta,  p <- (p + tau grad w) / (1 + tau |grad w|),
 //   z = v - theta div p.
-// A workgroup owns an 8 x 56 tile.  A launch stages the tile's field and v
-// with a halo of 4 pixels (a 16 x 64 region, one column per lane) in LDS and
-// runs up to 4 iterations there (temporal blocking).  A launch reads the field of one slot and writes the other, since
-// neighbouring tiles read the old field; a block alternates between the
-// caller's field (slot 0) and a scratch one (slot 1), and an odd launch count
-// starts from a copy in slot 1, so that the last launch lands in slot 0.  Per
-// launch HBM moves the region's field and v (about 2.3 times the tile) in and
-// the tile's field out, instead of 20 bytes per pixel for every iteration.
-// The update divides by 1 + tau |grad w| with the hardware reciprocal and
-// square root (each within about one unit in the last place).
+// A workgroup owns an 8 x 56 tile.  One z-update of a TV block is an even
+// number of launches of k_reg_step; each stages the tile's field with a halo
+// of 4 pixels (a 16 x 64 region, one column per lane) in LDS, forms v there
+// from x and nu, and runs up to 4 iterations on it (temporal blocking).  A
+// launch reads the field of one slot and writes the other, since neighbouring
+// tiles read the old field; the launches alternate between the caller's field
+// (slot 0) and a scratch one (slot 1), starting from slot 0 and, their count
+// being even, ending in it.  The last launch runs at most 3 iterations, so that
+// the field one pixel above and left of its tile is exact as well, and forms z
+// and t_z from the divergence in LDS.  Nothing but z and t_z is written outside
+// the field, so the launches need no other pass over the image.  The update
+// divides by 1 + tau |grad w| with the hardware reciprocal and square root
+// (each within about one unit in the last place).
 #include "consensus.h"
 
 namespace tomo {
@@ -26,11 +29,6 @@ namespace {
 
 constexpr int TH = TV_TILE_H, TW = TV_TILE_W;    // tile; with its halo a 16 x 64 region
 constexpr int TT = 256;
-
-// field slot read by launch l of a block: the launches alternate slots and the
-// last one writes slot 0 (an odd launch count starts from a copy in slot 1)
-__device__ __forceinline__ int launches(const RegJob& J) { return (J.iters + TV_BLOCK - 1) / TV_BLOCK; }
-__device__ __forceinline__ int slot_in(const RegJob& J, int l) { return (l + (launches(J) & 1)) & 1; }
 
 struct Tile {
   int r0, c0;
@@ -42,74 +40,50 @@ __device__ __forceinline__ Tile tile_of(const RegJob& J, int lid) {
   return Tile{ty * TH, (lid - ty * tx) * TW};
 }
 
-// (div p)(r, c) from the global field: p1(r, c) [r < n-1] - p1(r-1, c) [r > 0]
-// + p2(r, c) [c < n-1] - p2(r, c-1) [c > 0]
-__device__ __forceinline__ float div_global(const float* p1, const float* p2, int n, int r, int c) {
-  const size_t i = (size_t)r * n + c;
-  float d = 0.f;
-  if (r < n - 1) d += p1[i];
-  if (r > 0) d -= p1[i - n];
-  if (c < n - 1) d += p2[i];
-  if (c > 0) d -= p2[i - 1];
-  return d;
-}
+__device__ __forceinline__ float v_of(const RegJob& J, size_t i) { return J.x[i] - J.nu[i] * J.irho_z; }
 
 }  // namespace
 
-// v, and for Tikhonov the whole z-update; for TV with an odd iteration count
-// the copy of the field into slot 1
-__global__ __launch_bounds__(TT) void k_reg_init(Many<RegJob> src) {
-  int lid;
-  const RegJob J = src.get(blockIdx.x, lid);
-  const Tile T = tile_of(J, lid);
-  const int n = J.n;
-  const size_t cnt = (size_t)n * n;
-  for (int k = threadIdx.x; k < TH * TW; k += TT) {
-    const int r = T.r0 + k / TW, c = T.c0 + k % TW;
-    if (r >= n || c >= n) continue;
-    const size_t i = (size_t)r * n + c;
-    const float nv = J.nu[i];
-    const float v = J.x[i] - nv * J.irho_z;
-    if (J.kind == REG_TIKHONOV) {
-      const float z = v / (1.f + J.theta);
-      J.z[i] = z;
-      J.tz[i] = z + nv * J.irho_z;
-      continue;
-    }
-    J.tz[i] = v;
-    if (launches(J) & 1) {
-      J.p[1][i] = J.p[0][i];
-      J.p[1][cnt + i] = J.p[0][cnt + i];
-    }
-  }
-}
-
-// Chambolle iterations [t0, t0 + k) of every TV block that has more than t0
-// iterations, k = min(TV_BLOCK, remaining): the tile and a halo of TV_BLOCK
-// pixels are staged in LDS and iterated there.  Each iteration is exact on the
-// region shrunk by one pixel per side (a value depends on its neighbours at
-// distance one), so after k <= TV_BLOCK iterations the tile is exact; in-image
-// values never depend on values outside the image (the zero-flux conditions),
-// so the halo is simply cut at the image border.
-__global__ __launch_bounds__(TT) void k_tv_iter(Many<RegJob> src, int t0) {
+// Launch l of the z-update of every block.  Tikhonov blocks finish in launch 0.
+// A TV block with T iterations takes L = tv_launches(T) launches; launch l runs
+// tv_launch_iters(T, L, l) of them from the field in slot (L - l) & 1 (slot 0
+// when T = 0) into the other slot.  Each iteration is exact on the region
+// shrunk by one pixel per side (a value depends on its neighbours at distance
+// one), so after k <= 4 iterations the tile is exact, and after k <= 3 so is
+// the ring around it; in-image values never depend on values outside the image
+// (the zero-flux conditions), so the halo is simply cut at the image border.
+__global__ __launch_bounds__(TT) void k_reg_step(Many<RegJob> src, int l) {
   constexpr int H = TV_BLOCK, RH = TH + 2 * H, RW = TW + 2 * H, RN = RH * RW;
   constexpr int RPT = RN / TT;                     // region rows per thread
   static_assert(RW == 64 && RN % TT == 0, "a thread owns one region column");
   __shared__ float s1[RN], s2[RN], sv[RN], sw[RN];
   int lid;
   const RegJob J = src.get(blockIdx.x, lid);
-  if (J.kind != REG_TV || t0 >= J.iters) return;
-  const int kk = min(H, J.iters - t0);
   const Tile T = tile_of(J, lid);
-  const int n = J.n, R0 = T.r0 - H, C0 = T.c0 - H;
+  const int n = J.n;
+  if (J.kind == REG_TIKHONOV) {
+    if (l != 0) return;
+    for (int k = threadIdx.x; k < TH * TW; k += TT) {
+      const int r = T.r0 + k / TW, c = T.c0 + k % TW;
+      if (r >= n || c >= n) continue;
+      const size_t i = (size_t)r * n + c;
+      const float z = v_of(J, i) / (1.f + J.theta);
+      J.z[i] = z;
+      J.tz[i] = z + J.nu[i] * J.irho_z;
+    }
+    return;
+  }
+  const int L = tv_launches(J.iters);
+  if (l >= L) return;
+  const int kk = tv_launch_iters(J.iters, L, l);
+  const int R0 = T.r0 - H, C0 = T.c0 - H;
   const size_t cnt = (size_t)n * n;
-  const int launch = t0 / H;
   // slot pointers by select, not by a runtime index into J.p (which would put
   // the job in scratch memory)
-  const bool s_in = slot_in(J, launch) != 0;
+  const bool s_in = J.iters > 0 && ((L - l) & 1) != 0;
   const float* p1 = s_in ? J.p[1] : J.p[0];
   float* o1 = s_in ? J.p[0] : J.p[1];
-  const float ith = 1.f / J.theta, tau = J.tau;
+  const float ith = J.iters > 0 ? 1.f / J.theta : 0.f, tau = J.tau;
   // thread: region column cl, rows rb, rb + TT/64, ...
   const int cl = threadIdx.x & 63, rb = threadIdx.x >> 6, c = C0 + cl;
 #pragma unroll
@@ -119,7 +93,7 @@ __global__ __launch_bounds__(TT) void k_tv_iter(Many<RegJob> src, int t0) {
     const size_t i = in ? (size_t)r * n + c : 0;
     s1[k] = in ? p1[i] : 0.f;
     s2[k] = in ? p1[cnt + i] : 0.f;
-    sv[k] = in ? J.tz[i] * ith : 0.f;          // v / theta
+    sv[k] = in ? v_of(J, i) * ith : 0.f;      // v / theta
   }
   __syncthreads();
   for (int it = 0; it < kk; ++it) {
@@ -149,32 +123,28 @@ __global__ __launch_bounds__(TT) void k_tv_iter(Many<RegJob> src, int t0) {
     }
     __syncthreads();
   }
+  const bool last = l == L - 1;
 #pragma unroll
   for (int j = 0; j < RPT; ++j) {
-    const int rl = rb + j * (TT / 64), r = R0 + rl;
+    const int rl = rb + j * (TT / 64), r = R0 + rl, k = rl * RW + cl;
     if (rl < H || rl >= H + TH || cl < H || cl >= H + TW || r >= n || c >= n) continue;
     const size_t i = (size_t)r * n + c;
-    o1[i] = s1[rl * RW + cl];
-    o1[cnt + i] = s2[rl * RW + cl];
-  }
-}
-
-// z = v - theta div p, t_z = z + nu / rho_z (TV blocks)
-__global__ __launch_bounds__(TT) void k_tv_final(Many<RegJob> src) {
-  int lid;
-  const RegJob J = src.get(blockIdx.x, lid);
-  if (J.kind != REG_TV) return;
-  const Tile T = tile_of(J, lid);
-  const int n = J.n;
-  const size_t cnt = (size_t)n * n;
-  const float* p1 = J.p[0];
-  for (int k = threadIdx.x; k < TH * TW; k += TT) {
-    const int r = T.r0 + k / TW, c = T.c0 + k % TW;
-    if (r >= n || c >= n) continue;
-    const size_t i = (size_t)r * n + c;
-    const float z = J.tz[i] - J.theta * div_global(p1, p1 + cnt, n, r, c);
-    J.z[i] = z;
-    J.tz[i] = z + J.nu[i] * J.irho_z;
+    if (J.iters > 0) {
+      o1[i] = s1[k];
+      o1[cnt + i] = s2[k];
+    }
+    if (last) {
+      // z = v - theta div p; the neighbours above and to the left are exact (kk <= 3)
+      float d = 0.f;
+      if (r < n - 1) d += s1[k];
+      if (r > 0) d -= s1[k - RW];
+      if (c < n - 1) d += s2[k];
+      if (c > 0) d -= s2[k - 1];
+      const float nv = J.nu[i];
+      const float z = (J.x[i] - nv * J.irho_z) - J.theta * d;
+      J.z[i] = z;
+      J.tz[i] = z + nv * J.irho_z;
+    }
   }
 }
 
