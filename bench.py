@@ -503,7 +503,10 @@ def main():
         torch.cuda.synchronize()
         z_us = e0.elapsed_time(e1) / args.kernel_reps * 1e3
         px = sum(s.n * s.n for s in slices)
-        per_px = (12 + 20 * args.reg_iters + 24 + (16 if args.reg_iters % 2 else 0)) if args.reg == "tv" else 16
+        # algorithmic bytes per pixel: v formed (x, nu read, v written), each Chambolle
+        # iteration (field read and written, v read), z and t_z formed (field, v, nu
+        # read, z and t_z written); Tikhonov: x, nu read, z, t_z written
+        per_px = (12 + 20 * args.reg_iters + 24) if args.reg == "tv" else 16
         zinfo = {"kind": args.reg, "mu": args.reg_mu, "tv_iters": args.reg_iters if args.reg == "tv" else None,
                  "us": z_us, "algorithmic_bytes": per_px * px,
                  "achieved_GBps": per_px * px / (z_us * 1e-6) / 1e9, "peak_GBps": PEAK_HBM_GBS}
