@@ -1327,7 +1327,7 @@ int admm_reg_update(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, cons
   if (!plan) return rc;
   hipStream_t s = (hipStream_t)stream;
   Many<RegJob> js{static_cast<const RegJob*>(plan->jobs.p), plan->n_jobs};
-  for (int l = 0; l < plan->launches; ++l) hipLaunchKernelGGL(k_reg_step, dim3(plan->wgs), dim3(256), 0, s, js, l);
+  for (int l = 0; l < plan->launches; ++l) hipLaunchKernelGGL(k_reg_step, dim3(plan->wgs), dim3(TV_THREADS), 0, s, js, l);
   return launch_status(ctx, "admm_reg_update");
 }
 
