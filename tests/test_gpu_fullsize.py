@@ -143,8 +143,9 @@ def test_large_workload_local_update_sampled_node(mods):
 
 def test_single_workload_tv_block_z_update(mods):
     """The regularization block at bench.py --reg tv's settings on the 512^2,
-    16-node slice (TV, mu = 0.02, 10 Chambolle iterations: three launches, the
-    last with 2 iterations): z, t_z and the field after two z-updates (the
+    16-node slice (TV, mu = 0.02, 10 Chambolle iterations: two launches of 5
+    iterations, the second also forming z and t_z): z, t_z and the field after
+    two z-updates (the
     second warm-started from the first's field) against the oracle on the
     whole image."""
     from oracle import reg as oreg
