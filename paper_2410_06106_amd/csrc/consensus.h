@@ -80,9 +80,9 @@ constexpr int KM_LDS_VALUES = 16384;
 // between the caller's buffer (slot 0) and a library scratch buffer (slot 1).
 // ---------------------------------------------------------------------------
 enum { REG_TIKHONOV = 1, REG_TV = 2 };
-constexpr int TV_BLOCK = 8;     // most Chambolle iterations per k_reg_step launch (and its halo width)
-// k_reg_step: one workgroup per tile of 16 rows x (64 - 2 TV_BLOCK) columns
-constexpr int TV_TILE_H = 16, TV_TILE_W = 64 - 2 * TV_BLOCK;
+constexpr int TV_BLOCK = 6;     // most Chambolle iterations per k_reg_step launch (and its halo width)
+// k_reg_step: one workgroup per tile of 20 rows x (64 - 2 TV_BLOCK) columns
+constexpr int TV_TILE_H = 20, TV_TILE_W = 64 - 2 * TV_BLOCK;
 constexpr int TV_THREADS = 1024; // threads per k_reg_step workgroup: two region rows per thread
 
 // Launches of one TV z-update of T Chambolle iterations: the fewest that run at

@@ -8,15 +8,15 @@
 // Chambolle's dual projection iterations
 //   w = div p - v / theta,  p <- (p + tau grad w) / (1 + tau |grad w|),
 //   z = v - theta div p.
-// A workgroup of 1024 threads owns a 16 x 48 tile.  One z-update of a TV block
+// A workgroup of 1024 threads owns a 20 x 52 tile.  One z-update of a TV block
 // is an even number of launches of k_reg_step; each stages the tile's field
-// with a halo of 8 pixels (a 32 x 64 region, one column per lane, two rows per
-// thread) in LDS, forms v there from x and nu, and runs up to 8 iterations on
+// with a halo of 6 pixels (a 32 x 64 region, one column per lane, two rows per
+// thread) in LDS, forms v there from x and nu, and runs up to 6 iterations on
 // it (temporal blocking).  A
 // launch reads the field of one slot and writes the other, since neighbouring
 // tiles read the old field; the launches alternate between the caller's field
 // (slot 0) and a scratch one (slot 1), starting from slot 0 and, their count
-// being even, ending in it.  The last launch runs at most 7 iterations, so that
+// being even, ending in it.  The last launch runs at most 5 iterations, so that
 // the field one pixel above and left of its tile is exact as well, and forms z
 // and t_z from the divergence in LDS.  Nothing but z and t_z is written outside
 // the field, so the launches need no other pass over the image.  The update
@@ -50,7 +50,7 @@ __device__ __forceinline__ float v_of(const RegJob& J, size_t i) { return J.x[i]
 // tv_launch_iters(T, L, l) of them from the field in slot (L - l) & 1 (slot 0
 // when T = 0) into the other slot.  Each iteration is exact on the region
 // shrunk by one pixel per side (a value depends on its neighbours at distance
-// one), so after k <= 8 iterations the tile is exact, and after k <= 7 so is
+// one), so after k <= 6 iterations the tile is exact, and after k <= 5 so is
 // the ring around it; in-image values never depend on values outside the image
 // (the zero-flux conditions), so the halo is simply cut at the image border.
 __global__ __launch_bounds__(TT) void k_reg_step(Many<RegJob> src, int l) {
