@@ -192,7 +192,10 @@ int tomo_ctr_gd(tomo_ctx* ctx, tomo_geom g, const double* angles, int32_t n_ang,
  * One node of the decentralized problem (Eq. 6-7): its angles and data d_m,
  * its local image u_m and dual variable lambda_m, the slice-wide consensus image
  * x, and the segment x[m] it owns (rows seg_row0 .. seg_row0+seg_rows-1 of x,
- * Eq. 13/17).  Nodes of one slice share `x` and must be adjacent in a node list.
+ * Eq. 13/17).  Nodes of one slice share `x` and must be adjacent in a node list;
+ * the segments of one slice must not overlap, and the x arrays of different
+ * slices must not overlap (TOMO_EINVAL otherwise: the consensus writes every
+ * segment of every slice at the same time).
  */
 typedef struct {
   tomo_geom g;
@@ -320,7 +323,7 @@ int admm_consensus_reg(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, i
                        void* stream);
 
 /*
- * Scalar K-means quantizer (Alg. 5) of a float32 vector a[n], bit-exact:
+ * Scalar K-means quantizer (Alg. 5, Section 2.7) of a float32 vector a[n], bit-exact:
  *  lo,hi = min,max (NaN/Inf -> TOMO_EINVAL is NOT detectable on the host: the
  *  kernel then writes iters = -1 and leaves the outputs unspecified);
  *  centres start at lo + (hi-lo)(2j+1)/(2k) (float64, no FMA, rounded to float32);
@@ -339,7 +342,7 @@ int quantize_kmeans(tomo_ctx* ctx, const float* a, int64_t n, int32_t k, int32_t
                     uint8_t* labels, float* centroids, float* a_hat, int32_t* iters, void* stream);
 
 /*
- * Wire format of a K-means message (Section 2.5, Eq. 20; Section 3.3 counts a
+ * Wire format of a K-means message (Section 2.6, Eq. 20; Section 3.3 counts a
  * K-level code as ceil(log2 K) bits).  tomo_pack_labels writes the n labels as
  * `bits`-bit codes: value i occupies bits [i*bits, (i+1)*bits) of a stream of
  * 32-bit words, least significant bit first, stream bit j being bit j mod 32 of
@@ -359,7 +362,7 @@ int tomo_unpack_labels(tomo_ctx* ctx, const uint32_t* packed, int64_t n, int32_t
                        const float* centroids, int32_t k, uint8_t* labels, float* a_hat, void* stream);
 
 /*
- * Entropy code of DCT codes (the DCT message on the wire, Section 2.6 / Eq. 20):
+ * Entropy code of DCT codes (the DCT message on the wire, Sections 2.6 and 2.7 / Eq. 20):
  * 8x8 blocks in row-major order; in a block the 64 int16 codes in zigzag order
  * (the scan order of baseline JPEG); the DC code sent as the difference from
  * the previous block's DC, differenced from 0 at the first block of every
@@ -395,7 +398,8 @@ int tomo_dct_decode(tomo_ctx* ctx, const uint32_t* words, int64_t n_words, const
 
 /*
  * JPEG-style quantizer of a float32 matrix a[rows][cols] with leading dimension
- * ld (elements): per-matrix level map v = (a-lo)*255/(hi-lo) - 128, orthonormal
+ * ld (elements), the "standard JPEG" that Section 2.7 applies to an exchanged
+ * segment as the Q of Eq. 23 (dADMM-J): per-matrix level map v = (a-lo)*255/(hi-lo) - 128, orthonormal
  * 8x8 DCT-II per block, codes = round-half-even(F / Qs) with Qs the ITU-T T.81
  * Table K.1 luminance table scaled to `quality` (scale 5000/q below 50, else
  * 200-2q; step = clamp(floor((T*scale+50)/100), 1, 255)), dequantize, inverse

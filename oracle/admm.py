@@ -1,6 +1,6 @@
 """Decentralized ADMM with quantized exchange (float64 oracle).
 
-Follows Section 2.3-2.6 of the paper:
+Follows Sections 2.2-2.5 and 2.7 of the paper:
 
 * Alg. 1  centralized gradient descent on 0.5 ||P u - d||^2 (Eq. 5).
 * Alg. 2  node m's u-update: E1 gradient steps on

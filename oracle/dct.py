@@ -1,4 +1,4 @@
-"""JPEG-style quantizer of an exchanged segment (the paper's dADMM-J, Section 2.6).
+"""JPEG-style quantizer of an exchanged segment (the paper's dADMM-J, Section 2.7).
 
 The paper applies "standard JPEG compression" to each exchanged vector without
 further detail.  This module keeps the lossy core of baseline JPEG and drops the

@@ -1,6 +1,6 @@
 """Lossless entropy code of a segment's DCT codes (integers only; oracle).
 
-Section 2.6 applies "standard JPEG" to the exchanged segments.  Baseline JPEG
+Section 2.7 applies "standard JPEG" to the exchanged segments.  Baseline JPEG
 follows its quantizer with a lossless entropy code; the paper gives no tables.
 This module defines the code the library puts on the wire, so the bytes of a
 DCT message can be counted for Eq. 20.  It follows baseline JPEG's sequential

@@ -2,7 +2,7 @@
 
 The paper runs K-means on the entries of a vector, replaces every entry by its
 nearest cluster centre, and notes that K-means yields a locally optimal scalar
-quantizer for squared error (Section 2.6).  It leaves initialisation, stopping,
+quantizer for squared error (Section 2.7).  It leaves initialisation, stopping,
 tie-breaking and arithmetic open; this module fixes them so that any
 implementation that follows the same steps reaches identical labels:
 

@@ -5,7 +5,7 @@
 * Eq. 27  NSD = sigma / x_peak * 100 %.
 * Eq. 19  per-node memory  D/M + 3X.
 * Eq. 20  per-node traffic per iteration 2 (M - 1) / M * X, scaled by the
-          quantizer's bits per value over 32 (Section 2.5 and 3.3).
+          quantizer's bits per value over 32 (Sections 2.6 and 3.3).
 """
 from __future__ import annotations
 

@@ -1,6 +1,6 @@
 """Wire format of a K-means message (float64-free; integers only).
 
-Section 2.5 prices the exchange of Eq. 23 in bits per value (Eq. 20 scales the
+Section 2.6 prices the exchange of Eq. 23 in bits per value (Eq. 20 scales the
 image bytes by the quantizer's bits over 32), and Section 3.3 counts a K-level
 K-means code as ceil(log2 K) bits.  The message of one segment here is its
 labels packed at ``bits`` bits each plus the float32 codebook:

@@ -442,6 +442,29 @@ int check_nodes(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes) {
   std::sort(starts.begin(), starts.end());
   if (std::adjacent_find(starts.begin(), starts.end()) != starts.end())
     return ctx->fail(TOMO_EINVAL, "nodes of one slice must be adjacent");
+  // The consensus kernels of different nodes write their segments of x at the
+  // same time: the segments of a slice must be disjoint and the x arrays of
+  // different slices must not overlap.
+  std::vector<std::pair<int32_t, int32_t>> segs;   // (row0, rows) of one slice
+  std::vector<std::pair<uintptr_t, size_t>> xs;    // (address, bytes) per slice
+  for (int a = 0; a < n_nodes;) {
+    int b = a;
+    segs.clear();
+    while (b < n_nodes && nodes[b].slice == nodes[a].slice) {
+      segs.emplace_back(nodes[b].seg_row0, nodes[b].seg_rows);
+      ++b;
+    }
+    std::sort(segs.begin(), segs.end());
+    for (size_t j = 1; j < segs.size(); ++j)
+      if (segs[j - 1].first + segs[j - 1].second > segs[j].first)
+        return ctx->fail(TOMO_EINVAL, "segments of one slice overlap");
+    xs.emplace_back(reinterpret_cast<uintptr_t>(nodes[a].x), (size_t)nodes[a].g.n * nodes[a].g.n * sizeof(float));
+    a = b;
+  }
+  std::sort(xs.begin(), xs.end());
+  for (size_t j = 1; j < xs.size(); ++j)
+    if (xs[j - 1].first + xs[j - 1].second > xs[j].first)
+      return ctx->fail(TOMO_EINVAL, "x of different slices overlap");
   return TOMO_OK;
 }
 

@@ -1,4 +1,4 @@
-// Wire format of a K-means message (Section 2.5 and 3.3): a segment's labels
+// Wire format of a K-means message (Sections 2.6 and 3.3): a segment's labels
 // packed at `bits` bits per value into a little-endian stream of 32-bit words,
 // value i in stream bits [i*bits, (i+1)*bits), least significant bit first.
 // Packing and unpacking are HBM-bound streaming passes.

@@ -370,3 +370,35 @@ def test_argument_errors_are_reported(T, ctx):
     with pytest.raises(T.TomoError):   # image and sino overlap
         T._lib and T.tomo_project(ctx, to_dev(np.zeros(1), torch.float64), sino[:64].view(8, 8), 8,
                                   out=sino[8:16].view(1, 8))
+
+
+def test_node_list_errors_are_reported(T, ctx):
+    """Segments of one slice that overlap, and distinct slice ids that share x,
+    are rejected before anything is launched (the consensus writes all
+    segments of all slices at the same time)."""
+    n, nb = 16, 23
+    ang = to_dev(np.linspace(0.0, 3.0, 4), torch.float64)
+    d = torch.zeros((4, nb), dtype=torch.float32, device="cuda")
+    X = torch.zeros((n, n), dtype=torch.float32, device="cuda")
+    X2 = torch.zeros((n, n), dtype=torch.float32, device="cuda")
+
+    def ent(sl, x, r0, nr):
+        return dict(n=n, n_bins=nb, angles=ang, slice=sl, d=d, u=torch.zeros_like(X), lam=torch.zeros_like(X),
+                    x=x, seg_row0=r0, seg_rows=nr, rho=1.0, eta1=0.0, eta2=0.2)
+
+    q = T.tomo_quant(T.TOMO_QUANT_KMEANS, 4, 30, 50)
+    ok = T.make_nodes([ent(0, X, 0, 8), ent(0, X, 8, 8), ent(1, X2, 0, 16)])
+    T.admm_consensus(ctx, ok, T.TOMO_XUPDATE_SEGMENT, 1, q)
+    bad_cases = {
+        "overlapping segments": [ent(0, X, 0, 9), ent(0, X, 8, 8)],
+        "one segment inside another": [ent(0, X, 8, 8), ent(0, X, 0, 16)],
+        "two slice ids share x": [ent(0, X, 0, 16), ent(1, X, 0, 16)],
+    }
+    for name, ents in bad_cases.items():
+        log(f"  rejected: {name}")
+        nodes = T.make_nodes(ents)
+        with pytest.raises(T.TomoError):
+            T.admm_consensus(ctx, nodes, T.TOMO_XUPDATE_SEGMENT, 1, q)
+        with pytest.raises(T.TomoError):
+            T.admm_local_update(ctx, nodes, 1)
+    torch.cuda.synchronize()

@@ -125,3 +125,82 @@ def test_power_iteration_matches_eigvalsh():
     v0 = np.random.default_rng(0).standard_normal((prob.n, prob.n))
     got = stepsize.normal_operator_norm(prob.thetas[1], prob.n, prob.n_bins, v0, iters=200)
     assert abs(got - ref) <= 1e-6 * ref
+
+
+def _dense_quantized_iterations(prob, iters, rho, eta1, e1, eta2, e2, mode, q):
+    """Alg. 4 with the exchange of Eq. 23-24 written with dense matrices: the
+    local update by its closed form u* + (I - eta1 H)^E1 (u - u*), the segment
+    x-update by t + (1 - eta2 rho)^E2 (x[m] - t) (or the Eq. 9 average), then Q
+    on every segment of the concatenation, the owner's segment included
+    (reading R11), and the dual with the quantized x."""
+    n, M = prob.n, len(prob.d)
+    I = np.eye(n * n)
+    ops = []
+    for m in range(M):
+        A = joseph.dense_matrix(n, prob.n_bins, prob.thetas[m])
+        H = A.T @ A + rho * I
+        ops.append((A, H, np.linalg.matrix_power(I - eta1 * H, e1)))
+    x = np.zeros(n * n)
+    us = [np.zeros(n * n) for _ in range(M)]
+    lams = [np.zeros(n * n) for _ in range(M)]
+    for _ in range(iters):
+        for m, (A, H, G) in enumerate(ops):
+            ustar = np.linalg.solve(H, A.T @ prob.d[m].reshape(-1) + rho * x - lams[m])
+            us[m] = ustar + G @ (us[m] - ustar)
+        if mode == "seg":
+            xt = x.copy()
+            for m, (r0, nr) in enumerate(prob.segments):
+                sl = slice(r0 * n, (r0 + nr) * n)
+                t = us[m][sl] + lams[m][sl] / rho
+                xt[sl] = t + (1 - eta2 * rho) ** e2 * (x[sl] - t)
+        else:
+            xt = sum(u + l / rho for u, l in zip(us, lams)) / M
+        xq = np.empty_like(xt)
+        for r0, nr in prob.segments:
+            sl = slice(r0 * n, (r0 + nr) * n)
+            xq[sl] = q(xt[sl].reshape(nr, n)).reshape(-1)
+        x = xq
+        lams = [l + rho * (u - x) for u, l in zip(us, lams)]
+    return x.reshape(n, n), [u.reshape(n, n) for u in us], [l.reshape(n, n) for l in lams]
+
+
+@pytest.mark.parametrize("mode", ["seg", "avg"])
+@pytest.mark.parametrize("kind", ["kmeans", "dct"])
+def test_quantized_iterations_by_dense_algebra(mode, kind):
+    """Three dADMM iterations with a quantizer in the exchange (Eq. 23-24,
+    Alg. 5 or the DCT codec) against the dense-matrix restatement above.  A
+    quantizer applied to the whole image instead of per segment, before the
+    x-update, or skipped on the owner's segment, or a dual formed with the
+    unquantized x, fails this (the quantized x is far from x~ at 4 levels /
+    quality 10)."""
+    if kind == "kmeans":
+        prob, _, _ = _tiny_problem(n=6, n_angles=9, n_bins=9, n_nodes=2)
+        from oracle.kmeans import kmeans_quantize
+        levels = 4
+
+        def q(seg):
+            return kmeans_quantize(seg.astype(np.float32).reshape(-1), levels, 30).a_hat.reshape(seg.shape)
+        oq = admm.Quantizer("kmeans", levels, 30, 50)
+    else:
+        prob, _, _ = _tiny_problem(n=16, n_angles=20, n_bins=23, n_nodes=2)
+        from oracle.dct import dct_quantize
+
+        def q(seg):
+            return dct_quantize(seg.astype(np.float32), 10).a_hat
+        oq = admm.Quantizer("dct", 16, 30, 10)
+    rho, eta1, e1, eta2, e2 = 1.0, 0.01, 5, 0.2, 10
+    x, us, lams, _ = admm.run(prob, 3, rho, eta1, e1, eta2, e2, mode=mode, quant=oq)
+    xr, ur, lr = _dense_quantized_iterations(prob, 3, rho, eta1, e1, eta2, e2, mode, q)
+    np.testing.assert_allclose(x, xr, atol=1e-10)
+    for m in range(2):
+        np.testing.assert_allclose(us[m], ur[m], atol=1e-10)
+        np.testing.assert_allclose(lams[m], lr[m], atol=1e-10)
+    # the quantizer changed the exchanged image (the test is not vacuous)
+    xn, _, _, _ = admm.run(prob, 3, rho, eta1, e1, eta2, e2, mode=mode)
+    assert np.abs(x - xn).max() > 1e-3
+    # every segment of x^K holds at most `levels` values (K-means) and each is
+    # its own quantization (Q is idempotent on a quantized segment only approximately
+    # for DCT, so this part is K-means only)
+    if kind == "kmeans":
+        for r0, nr in prob.segments:
+            assert np.unique(x[r0:r0 + nr].astype(np.float32)).size <= levels

@@ -12,7 +12,7 @@ from fractions import Fraction
 import numpy as np
 import pytest
 
-from oracle.kmeans import assign, kmeans_quantize
+from oracle.kmeans import assign, initial_centres, kmeans_quantize
 
 
 def _brute_force_distortion(a, k):
@@ -126,3 +126,32 @@ def test_assignment_is_the_exact_nearest_centre(seed):
     for v, lab in zip(a, got):
         d = [abs(Fraction(float(v)) - x) for x in cf]
         assert lab == d.index(min(d)), (v, lab)
+
+
+def test_initial_centres_are_the_cell_midpoints():
+    """Alg. 5's initialisation (reading R14): the centres of k equal cells of
+    [lo, hi].  Values chosen so that every centre is exact in float32."""
+    np.testing.assert_array_equal(initial_centres(0.0, 1.0, 4), [0.125, 0.375, 0.625, 0.875])
+    np.testing.assert_array_equal(initial_centres(-3.0, 1.0, 4), [-2.5, -1.5, -0.5, 0.5])
+    np.testing.assert_array_equal(initial_centres(-8.0, -6.0, 2), [-7.5, -6.5])
+    np.testing.assert_array_equal(initial_centres(2.0, 6.0, 1), [4.0])
+
+
+@pytest.mark.parametrize("lo,hi,k", [(0.0, 1.0, 4), (-3.0, 1.0, 4), (-8.0, -6.0, 8), (-1.0, 3.0, 16)])
+def test_zero_lloyd_iterations_is_the_uniform_quantizer(lo, hi, k):
+    """With max_iter = 0 the output is the initial quantizer: the uniform
+    k-cell quantizer of [lo, hi] (textbook midrise form), every value mapped to
+    the midpoint of its cell, cell edges lo + (hi - lo) j / k.  Values sit away
+    from the edges so the float32 rounding of a value cannot move it across."""
+    rng = np.random.default_rng(k + int(hi - lo))
+    w = (hi - lo) / k
+    cell = rng.integers(0, k, 2000)
+    frac = rng.uniform(0.01, 0.99, 2000)
+    a = (lo + (cell + frac) * w).astype(np.float32)
+    a[0], a[1] = lo, hi                   # the range is exactly [lo, hi]
+    cell[0], cell[1] = 0, k - 1
+    res = kmeans_quantize(a, k, max_iter=0)
+    assert res.iters == 0
+    np.testing.assert_array_equal(res.centroids, lo + (np.arange(k) + 0.5) * w)
+    np.testing.assert_array_equal(res.labels, cell)
+    np.testing.assert_array_equal(res.a_hat, (lo + (cell + 0.5) * w).astype(np.float32))
