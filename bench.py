@@ -181,6 +181,75 @@ def build(which, ctx, A, T, synthdata, log):
     raise SystemExit(f"unknown workload {which}")
 
 
+def batching_line(A, T, synthdata, autotune, log, iters=2, steps=4):
+    """The batching workload's comparison for the default run: 256 slices of
+    sizes 128..1024 (1.5 N angles, ceil(1.414 N) bins, 2..16 interleaved nodes),
+    K-means with 16 levels; ``iters`` iterations of the plain per-slice,
+    per-node launch loop, then the same iterations from the same start by the
+    batched one-iteration graph (same kernels, so the slices' RMSEs are equal
+    bit for bit), then ``steps`` timed replays.  A context of its own, so the
+    autotuned tiles of the main workload are untouched."""
+    import numpy as np
+    import torch
+
+    ctx = T.Context(0)
+    t0 = time.perf_counter()
+    slices, ws, q, desc, cfg, _, _ = build("batch", ctx, A, T, synthdata, log)
+    run = A.DADMM(ctx, slices, rho=1.0, eta2=0.2, e1=5, e2=10, mode=T.TOMO_XUPDATE_SEGMENT, quant=q)
+    choice = autotune.tune(ctx, run.nodes, resident=True)
+    setup_s = time.perf_counter() - t0
+
+    def zero_all():
+        for s in slices:
+            s.zero()
+
+    zero_all()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        run.step_plain()
+    torch.cuda.synchronize()
+    plain_s = (time.perf_counter() - t0) / iters
+    rmse_plain = [run.rmse(i) for i in range(len(slices))]
+    x_plain = [s.x.clone() for s in slices]
+    zero_all()
+    run.step()                                   # builds the batched plans outside capture
+    zero_all()
+    torch.cuda.synchronize()
+    g = run.capture(1)
+    zero_all()
+    for _ in range(iters):
+        g.replay()
+    torch.cuda.synchronize()
+    rmse_batched = [run.rmse(i) for i in range(len(slices))]
+    identical = all(bool(torch.equal(xp, s.x)) for xp, s in zip(x_plain, slices))
+    del x_plain
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    batched_s = max(e0.elapsed_time(e1) * 1e-3, time.perf_counter() - t0) / steps
+    n = len(slices)
+    rel = max(abs(a - b) / b if b > 0 else 0.0 for a, b in zip(rmse_batched, rmse_plain))
+    out = {"workload": desc, "slices": n, "nodes": cfg["nodes"], "iterations_compared": iters,
+           "timed_replays": steps,
+           "batched_graph": n / batched_s, "plain_loop": n / plain_s, "unit": "slice-iterations/s",
+           "speedup": plain_s / batched_s, "bit_identical": identical, "max_rel_rmse_diff": rel,
+           "rmse_mean_plain": float(np.mean(rmse_plain)), "rmse_mean_batched": float(np.mean(rmse_batched)),
+           "updates_per_s": sum(2 * w.inner_iters * w.n_angles * w.n * w.n for w in ws) / batched_s,
+           "projector_tiles": {k: choice[k] for k in ("kernel", "band", "job_wgs")}, "setup_s": setup_s}
+    log(f"batching: {n} slices, batched graph {out['batched_graph']:.1f} vs plain loop {out['plain_loop']:.1f} "
+        f"slice-iterations/s ({out['speedup']:.2f}x), mean rmse {out['rmse_mean_batched']:.6g} "
+        f"(identical={identical})")
+    del run, slices, g
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_diff(args, steps, ctx, log):
     """Form (3): K = 10 unrolled ADMM iterations of the 1024^2, 1080-angle,
     32-node workload with learnable (rho_k, eta_k), trained by Adam on seeded
@@ -289,6 +358,8 @@ def main():
     ap.add_argument("--reg-mu", type=float, default=0.02)
     ap.add_argument("--reg-iters", type=int, default=10, help="Chambolle iterations per z-update (TV)")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--no-batch-line", action="store_true",
+                    help="skip the batching workload's batched-vs-plain comparison of the default run")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only launch the projector and backprojector of the workload a few times, and a "
                          "device copy of known size (for counter runs); prints their launch counts")
@@ -531,6 +602,10 @@ def main():
         cpu = {"value": v_cpu, "unit": "updates/s", "cores": 1, "kind": "oracle",
                "sample": f"Alg. 2 local update (E1=5: P and P^T) of {sample_desc}, float64 NumPy, {dt:.1f} s"}
 
+    batching = None
+    if args.workload == "single" and not args.no_batch_line:
+        batching = batching_line(A, T, synthdata, autotune, log)
+
     rel = [abs(a - b) / b if b > 0 else 0.0 for a, b in zip(rmse_batched, rmse_plain)]
     out = {
         "metric": "proj+backproj ray-voxel updates/s; ADMM iter/s batched vs plain @ equal RMSE",
@@ -552,6 +627,7 @@ def main():
         "equal_rmse": {"iterations": n_eq, "bit_identical": identical, "max_rel_rmse_diff": max(rel),
                        "plain_slice0": rmse_plain[0], "batched_slice0": rmse_batched[0]},
         "rmse_after_timed_steps": {"slice0": rmse_final[0], "mean": float(np.mean(rmse_final))},
+        "batching": batching,
         "kmeans_lloyd_iters_last_step": lloyd,
         "projector_tiles": tiles,
         "iteration_graph": {"form": form, "trial_us": trial_us},

@@ -253,6 +253,8 @@ typedef struct {
   int32_t* iters;      /* K-means: int32 [1] Lloyd iterations run                */
   int16_t* coeffs;     /* DCT: int16 [seg_rows][n] quantized coefficients        */
   float* lohi;         /* DCT: float32 [2] level-map range                       */
+  float* x_tilde;      /* float32 [seg_rows][n]: the segment after the x-update  */
+                       /* and before Q (Alg. 3 or Eq. 9 output; any quantizer)   */
 } tomo_msg;
 
 /*
@@ -405,7 +407,11 @@ int tomo_dct_decode(tomo_ctx* ctx, const uint32_t* words, int64_t n_words, const
  * 200-2q; step = clamp(floor((T*scale+50)/100), 1, 255)), dequantize, inverse
  * DCT, unmap.  rows, cols multiples of 8.  Outputs: a_hat float32 [rows][ld]
  * (may alias a), coeffs int16 [rows][cols] (nullable), lohi float32 [2]
- * (nullable).  hi == lo: a_hat = a, coeffs 0.
+ * (nullable).  hi == lo: a_hat = a, coeffs 0.  A code within float32 error of
+ * a rounding tie is decided on the coefficient recomputed in float64.  Two
+ * launches over many workgroups (the range, then the coding); the range
+ * partials live in a context workspace of 1 KiB (allocated on first use, kept
+ * until tomo_destroy or tomo_release).
  */
 int quantize_dct(tomo_ctx* ctx, const float* a, int32_t rows, int32_t cols, int32_t ld,
                  int32_t quality, int16_t* coeffs, float* a_hat, float* lohi, void* stream);

@@ -20,8 +20,8 @@ template <class Src> __global__ void k_project_res_reduce(Src);
 template <class Src, bool CHORD> __global__ void k_backproject(Src);
 __global__ void k_seg_none(const SegJob*, int, int);
 template <bool REG, bool TZ> __global__ void k_kmeans(const KMJob*, KMJob, int, int, int, const KMBlock*);
-__global__ void k_seg_dct(const SegJob*, int, int, int);
-__global__ void k_dct(const float*, int, int, int, int, int16_t*, float*, float*);
+__global__ void k_dct_range(const SegJob*, int, SegJob, int, int);
+__global__ void k_dct_code(const SegJob*, int, SegJob, int);
 __global__ void k_avg(Many<AvgJob>, const NodeRef*);
 __global__ void k_dual(Many<NodeRef>);
 __global__ void k_reg_step(Many<RegJob>, int);
@@ -39,7 +39,7 @@ __global__ void k_unpack_labels(const unsigned*, int, int, const float*, int, ui
 using namespace tomo;
 
 static_assert(sizeof(tomo_node) == 80, "tomo_node must have no padding (plans compare it bytewise)");
-static_assert(sizeof(tomo_msg) == 40, "tomo_msg must have no padding");
+static_assert(sizeof(tomo_msg) == 48, "tomo_msg must have no padding");
 static_assert(sizeof(tomo_proj_item) == 40, "tomo_proj_item must have no padding (plans compare it bytewise)");
 
 namespace {
@@ -316,8 +316,10 @@ struct ConsPlan {
   std::vector<tomo_node> key;
   std::vector<tomo_msg> msg_key;
   std::vector<tomo_reg> reg_key;
-  DevBuf seg, avg, noderefs, labels, kmjobs, kmwork, kmblocks;
+  DevBuf seg, avg, noderefs, labels, kmjobs, kmwork, kmblocks, dctpart;
+  int dct_range_wgs = 0, dct_code_wgs = 0;   // DCT codec launches
   int n_seg = 0, n_avg = 0, avg_wgs = 0, dual_wgs = 0;
+  bool any_xt = false;   // some message asks for the segment before Q
   int n_refs = 0;                 // dual-update entries: the nodes, then the regularization blocks
   int km_small = 0, km_big = 0;   // K-means jobs regrouping in LDS, then those using the workspace
 };
@@ -361,6 +363,7 @@ struct tomo_ctx {
   DevBuf partial;                                // standalone projector workspace
   DevBuf pbbase;                                 // standalone projector: region bin bases
   DevBuf km_work;                                // standalone K-means workspace
+  DevBuf dct_part;                               // standalone DCT codec: range partials
   DevBuf ctr_resid;                              // residual of tomo_ctr_gd
   DevBuf ecode_off;                              // block offsets of tomo_dct_encode
   std::vector<std::unique_ptr<LocalPlan>> lplans;
@@ -948,8 +951,18 @@ ConsPlan* get_cons_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, cons
     s.rho = N.rho; s.eta2 = N.eta2;
     if (msg) {
       s.labels = msg[i].labels; s.centroids = msg[i].centroids; s.iters = msg[i].iters;
-      s.coeffs = msg[i].coeffs; s.lohi = msg[i].lohi;
+      s.coeffs = msg[i].coeffs; s.lohi = msg[i].lohi; s.xt = msg[i].x_tilde;
+      plan->any_xt = plan->any_xt || s.xt;
     }
+    s.src = N.x + (size_t)N.seg_row0 * N.g.n;
+    s.dst = N.x + (size_t)N.seg_row0 * N.g.n;
+    s.cols = s.ld = N.g.n;
+    s.chunk_rows = dct_chunk_rows(N.seg_rows, N.g.n);
+    s.n_chunks = (N.seg_rows + s.chunk_rows - 1) / s.chunk_rows;
+    s.range_wg = plan->dct_range_wgs;
+    s.code_wg = plan->dct_code_wgs;
+    plan->dct_range_wgs += s.n_chunks;
+    plan->dct_code_wgs += dct_code_wgs(N.seg_rows, N.g.n);
     seg.push_back(s);
     NodeRef r{};
     r.u = N.u; r.lam = N.lam; r.x = N.x; r.n = N.g.n; r.rho = N.rho;
@@ -992,6 +1005,14 @@ ConsPlan* get_cons_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, cons
       work_elems += (size_t)(segn + 63) / 64 * 64;
     }
   }
+  if (!plan->dctpart.ensure((size_t)plan->dct_range_wgs * sizeof(float4))) {
+    rc = ctx->fail(TOMO_ENOMEM, "consensus plan allocation failed");
+    return nullptr;
+  }
+  {
+    float4* part = static_cast<float4*>(plan->dctpart.p);
+    for (auto& s : seg) s.part = part + s.range_wg;
+  }
   if (!plan->seg.ensure(seg.size() * sizeof(SegJob)) || !plan->avg.ensure(avg.size() * sizeof(AvgJob)) ||
       !plan->noderefs.ensure(refs.size() * sizeof(NodeRef)) ||
       !plan->labels.ensure(std::max<size_t>(label_elems, 1)) ||
@@ -1020,6 +1041,7 @@ ConsPlan* get_cons_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, cons
     j.labels = (msg && msg[i].labels) ? msg[i].labels : static_cast<uint8_t*>(plan->labels.p) + label_off[i];
     j.cent = msg ? msg[i].centroids : nullptr;
     j.iters = msg ? msg[i].iters : nullptr;
+    j.xt = msg ? msg[i].x_tilde : nullptr;
     if (j.n > KM_LDS_VALUES) {
       j.work = static_cast<float*>(plan->kmwork.p) + work_off[i];
       km_big.push_back(j);
@@ -1150,8 +1172,8 @@ int tomo_release(tomo_ctx* ctx) {
   ctx->rplans.clear();
   ctx->lindex.clear();
   ctx->cindex.clear();
-  for (DevBuf* b : {&ctx->partial, &ctx->pbbase, &ctx->km_work, &ctx->ctr_resid, &ctx->ecode_off, &ctx->btable,
-                    &ctx->bpartial, &ctx->bbbase})
+  for (DevBuf* b : {&ctx->partial, &ctx->pbbase, &ctx->km_work, &ctx->dct_part, &ctx->ctr_resid, &ctx->ecode_off,
+                    &ctx->btable, &ctx->bpartial, &ctx->bbbase})
     b->release();
   return TOMO_OK;
 }
@@ -1327,8 +1349,11 @@ int admm_consensus_reg(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, i
                          dim3(kKmThreads), 0, s, kj + plan->km_small, KMJob{}, q->levels, q->max_iter, ex,
                          kb ? kb + plan->km_small : nullptr);
   } else if (kind == TOMO_QUANT_DCT) {
-    hipLaunchKernelGGL(k_seg_dct, dim3(plan->n_seg), dim3(256), 0, s, seg, do_x, e2, q->quality);
-  } else if (do_x) {
+    hipLaunchKernelGGL(k_dct_range, dim3(plan->dct_range_wgs), dim3(DCT_THREADS), 0, s, seg, plan->n_seg, SegJob{},
+                       do_x, e2);
+    hipLaunchKernelGGL(k_dct_code, dim3(plan->dct_code_wgs), dim3(DCT_THREADS), 0, s, seg, plan->n_seg, SegJob{},
+                       q->quality);
+  } else if (do_x || plan->any_xt) {
     hipLaunchKernelGGL(k_seg_none, dim3(plan->n_seg), dim3(256), 0, s, seg, do_x, e2);
   }
   Many<NodeRef> ds{refs, plan->n_refs};
@@ -1394,8 +1419,22 @@ int quantize_dct(tomo_ctx* ctx, const float* a, int32_t rows, int32_t cols, int3
   if (a_hat != a && overlaps(a, (size_t)rows * ld * 4, a_hat, (size_t)rows * ld * 4))
     return ctx->fail(TOMO_EINVAL, "a_hat partially overlaps a");
   if (int rc = set_device(ctx)) return rc;
-  hipLaunchKernelGGL(k_dct, dim3(1), dim3(256), 0, (hipStream_t)stream, a, rows, cols, ld, quality, coeffs, a_hat,
-                     lohi);
+  SegJob j{};
+  j.src = a;
+  j.dst = a_hat;
+  j.rows = rows;
+  j.cols = cols;
+  j.ld = ld;
+  j.coeffs = coeffs;
+  j.lohi = lohi;
+  j.rho = 1.f;
+  j.chunk_rows = dct_chunk_rows(rows, cols);
+  j.n_chunks = (rows + j.chunk_rows - 1) / j.chunk_rows;
+  if (!ctx->dct_part.ensure((size_t)DCT_MAX_CHUNKS * sizeof(float4))) return ctx->fail(TOMO_ENOMEM, "workspace");
+  j.part = static_cast<float4*>(ctx->dct_part.p);
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_dct_range, dim3(j.n_chunks), dim3(DCT_THREADS), 0, s, nullptr, 1, j, 0, 0);
+  hipLaunchKernelGGL(k_dct_code, dim3(dct_code_wgs(rows, cols)), dim3(DCT_THREADS), 0, s, nullptr, 1, j, quality);
   return launch_status(ctx, "quantize_dct");
 }
 

@@ -25,7 +25,33 @@ struct SegJob {
   int32_t* iters;
   int16_t* coeffs;
   float* lohi;
+  float* xt;            // the segment before Q (nullable)
+  // DCT codec (k_dct_range, then k_dct_code): the matrix coded is src[rows][cols]
+  // with leading dimension ld, written to dst (in the consensus both are the
+  // segment of x, ld = cols = n)
+  const float* src;
+  float* dst;
+  int cols, ld;
+  int chunk_rows, n_chunks;   // range partials: rows per chunk, chunks (<= DCT_MAX_CHUNKS)
+  float4* part;               // [n_chunks] (lo, hi, non-finite flag, unused)
+  int range_wg, code_wg;      // first workgroup of the job in the two launches
 };
+
+// DCT codec launch shapes: the range launch gives each workgroup at least
+// DCT_CHUNK values (whole rows) and a segment at most DCT_MAX_CHUNKS
+// workgroups; the coding launch gives each workgroup a strip of 16 rows x
+// DCT_STRIP columns (a 16 x 64 sub-strip per wave).
+constexpr int DCT_THREADS = 256;
+constexpr int DCT_CHUNK = 2048;
+constexpr int DCT_MAX_CHUNKS = 64;
+constexpr int DCT_STRIP = 256;
+__host__ __device__ inline int dct_chunk_rows(int rows, int cols) {
+  const int a = (DCT_CHUNK + cols - 1) / cols, b = (rows + DCT_MAX_CHUNKS - 1) / DCT_MAX_CHUNKS;
+  return a > b ? a : b;
+}
+__host__ __device__ inline int dct_code_wgs(int rows, int cols) {
+  return ((rows + 15) / 16) * ((cols + DCT_STRIP - 1) / DCT_STRIP);
+}
 
 struct NodeRef {        // u, lambda of one node (AVG gather, dual update)
   float* u;
@@ -57,6 +83,7 @@ struct KMJob {
   float* cent;          // [k] (nullable)
   int32_t* iters;       // [1] (nullable)
   float* work;          // [n] regrouping workspace, required when n > KM_LDS_VALUES
+  float* xt;            // [n] the values before Q (nullable)
   long long n;          // < 2^31
   float rho, eta2;
 };
@@ -97,10 +124,14 @@ __host__ __device__ inline int tv_launch_iters(int T, int L, int l) {
   return T / L + (l < T % L ? 1 : 0);
 }
 
-// One Alg. 3 step with a block's term, x - eta2 (rho (x - t_m) + rho_z (x - t_z)),
-// t_m = u + lambda/rho formed once per value (reg_target), with every fused
-// multiply-add explicit so that each kernel running it rounds the same way.
+// One Alg. 3 step x - eta2 rho (x - t_m), t_m = u + lambda/rho formed once per
+// value (reg_target); with a block's term x - eta2 (rho (x - t_m) + rho_z (x - t_z)).
+// Every fused multiply-add is explicit so that each kernel running a step
+// rounds the same way.
 __device__ __forceinline__ float reg_target(float uv, float lv, float irho) { return fmaf(lv, irho, uv); }
+__device__ __forceinline__ float xstep(float xv, float tm, float rho, float eta2) {
+  return fmaf(-eta2, rho * (xv - tm), xv);
+}
 __device__ __forceinline__ float xstep_reg(float xv, float tm, float tv, float rho, float rho_z, float eta2) {
   const float delta = fmaf(rho, xv - tm, rho_z * (xv - tv));
   return fmaf(-eta2, delta, xv);

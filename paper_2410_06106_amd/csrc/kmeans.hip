@@ -66,10 +66,8 @@ __device__ __forceinline__ int km_fixed(float v, int S) {
 
 __device__ __forceinline__ float km_xupdate(float xv, float uv, float lv, float rho, float irho, float eta2,
                                             int e2) {
-  for (int e = 0; e < e2; ++e) {
-    float delta = rho * (xv - uv - lv * irho);
-    xv = xv - eta2 * delta;
-  }
+  const float tm = reg_target(uv, lv, irho);
+  for (int e = 0; e < e2; ++e) xv = xstep(xv, tm, rho, eta2);
   return xv;
 }
 
@@ -303,6 +301,13 @@ __global__ __launch_bounds__(KT) void k_kmeans(const KMJob* jobs, KMJob single, 
           a[e] = km_xupdate(a[e], uv[e], lv[e], J.rho, irho, J.eta2, e2);
           if (i < n) xo[i] = a[e];
         }
+      }
+    }
+    if (J.xt) {
+#pragma unroll
+      for (int e = 0; e < KVPT; ++e) {
+        const long long i = base + tid + (long long)e * KT;
+        if (i < n) gptr(J.xt)[i] = a[e];
       }
     }
 #pragma unroll

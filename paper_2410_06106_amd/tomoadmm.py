@@ -57,7 +57,7 @@ class tomo_quant(ctypes.Structure):
 
 class tomo_msg(ctypes.Structure):
     _fields_ = [("labels", ctypes.c_void_p), ("centroids", ctypes.c_void_p), ("iters", ctypes.c_void_p),
-                ("coeffs", ctypes.c_void_p), ("lohi", ctypes.c_void_p)]
+                ("coeffs", ctypes.c_void_p), ("lohi", ctypes.c_void_p), ("x_tilde", ctypes.c_void_p)]
 
 
 class tomo_proj_item(ctypes.Structure):
@@ -71,7 +71,7 @@ class tomo_reg(ctypes.Structure):
                 ("z", ctypes.c_void_p), ("nu", ctypes.c_void_p), ("tz", ctypes.c_void_p), ("p", ctypes.c_void_p)]
 
 
-assert ctypes.sizeof(tomo_node) == 80 and ctypes.sizeof(tomo_msg) == 40 and ctypes.sizeof(tomo_proj_item) == 40
+assert ctypes.sizeof(tomo_node) == 80 and ctypes.sizeof(tomo_msg) == 48 and ctypes.sizeof(tomo_proj_item) == 40
 assert ctypes.sizeof(tomo_reg) == 56
 
 _P = ctypes.c_void_p
@@ -425,11 +425,11 @@ def make_regs(entries):
 
 
 def make_msgs(entries):
-    """ctypes tomo_msg array from dicts with optional labels, centroids, iters, coeffs, lohi."""
+    """ctypes tomo_msg array from dicts with optional labels, centroids, iters, coeffs, lohi, x_tilde."""
     arr = (tomo_msg * len(entries))()
     for i, e in enumerate(entries):
         for key, dt in (("labels", torch.uint8), ("centroids", torch.float32), ("iters", torch.int32),
-                        ("coeffs", torch.int16), ("lohi", torch.float32)):
+                        ("coeffs", torch.int16), ("lohi", torch.float32), ("x_tilde", torch.float32)):
             t = e.get(key)
             setattr(arr[i], key, None if t is None else _dev(t, dt, key).value)
     return arr

@@ -45,7 +45,7 @@ def test_binding_covers_every_declared_symbol():
 def test_struct_layouts():
     from paper_2410_06106_amd import tomoadmm as T
     assert ctypes.sizeof(T.tomo_node) == 80
-    assert ctypes.sizeof(T.tomo_msg) == 40
+    assert ctypes.sizeof(T.tomo_msg) == 48
     assert ctypes.sizeof(T.tomo_quant) == 16
     assert ctypes.sizeof(T.tomo_geom) == 8
     assert ctypes.sizeof(T.tomo_proj_item) == 40

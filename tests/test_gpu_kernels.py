@@ -245,8 +245,9 @@ def test_dct_codec(T, ctx, rows, cols, q):
     assert np.all(np.abs(got - want)[diff] == 1)
     frac = np.abs(ref.F / qs - np.floor(ref.F / qs) - 0.5)
     assert np.all(frac[diff] <= 2e-3 / qs[diff] + 1e-6), frac[diff]
-    assert diff.mean() <= 1e-3
-    np.testing.assert_allclose(lohi.cpu().numpy(), [a.min(), a.max()])
+    log(f"  codes off by one at ties: {int(diff.sum())} of {diff.size}")
+    assert diff.mean() <= 1e-4
+    np.testing.assert_array_equal(lohi.cpu().numpy(), [a.min(), a.max()])
     blk = diff.reshape(rows // 8, 8, cols // 8, 8).any(axis=(1, 3))
     clean = ~np.repeat(np.repeat(blk, 8, 0), 8, 1)
     assert rel_l2(a_hat[clean], ref.a_hat[clean]) <= 1e-5

@@ -1,0 +1,232 @@
+"""Teacher-forced parity of the quantized exchange (Alg. 2-5, Eq. 9, 23-24).
+
+With a quantizer in the loop the trajectory is not unique under rounding (a
+value within float32 rounding of a cluster boundary may take either label), so
+whole-run RMSE agreement is only a loose check.  Here every iteration starts
+from the GPU's own state: the oracle runs one step from exactly that state and
+each piece is held to its own bar -- the local update and the dual to 1e-5
+rel-L2, the x-update (the segment before Q, read back through tomo_msg.x_tilde)
+to 1e-5 rel-L2, and the quantizer on the GPU's own x~ bit-exact (K-means labels,
+centroids, iteration count and the exchanged x) or, for the DCT codec, codes
+equal except for off-by-one codes at float64 rounding ties, at most 1e-4 of
+all codes."""
+import numpy as np
+import pytest
+import torch
+
+import synthdata
+from gpu_common import log, rel_l2, require_gpu, to_dev
+from oracle import admm as oadmm
+from oracle import dct as odct
+from oracle import joseph, stepsize
+from oracle.kmeans import kmeans_quantize
+
+pytestmark = pytest.mark.gpu
+
+DCT_TIE_BUDGET = 1e-4          # share of codes allowed off by one (float64 ties only)
+
+
+@pytest.fixture(scope="module")
+def T():
+    require_gpu()
+    from paper_2410_06106_amd import tomoadmm
+    return tomoadmm
+
+
+@pytest.fixture(scope="module")
+def ctx(T):
+    return T.Context(0)
+
+
+def _np(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _check_dct_codes(got, ref, q):
+    """Codes equal except off by one where the float64 coefficient sits at a
+    rounding tie; returns (number of differing codes, mask of their blocks)."""
+    got = got.astype(np.int64)
+    want = ref.coeffs.astype(np.int64)
+    diff = got != want
+    if diff.any():
+        assert np.all(np.abs(got - want)[diff] == 1)
+        rows, cols = got.shape
+        qs = np.tile(odct.quant_steps(q), (rows // 8, cols // 8))
+        r = ref.F / qs
+        frac = np.abs(r - np.floor(r) - 0.5)
+        assert np.all(frac[diff] <= 2e-3 / qs[diff] + 1e-6), frac[diff]
+    rows, cols = got.shape
+    blk = diff.reshape(rows // 8, 8, cols // 8, 8).any(axis=(1, 3))
+    return int(diff.sum()), np.repeat(np.repeat(blk, 8, 0), 8, 1)
+
+
+def _tiny_setup(T, ctx, mode, c):
+    w = synthdata.WORKLOADS["tiny"]
+    truth = synthdata.phantom(w)
+    th = synthdata.angles(w.n_angles)
+    d = synthdata.add_gaussian_noise(joseph.project(truth, th, w.n_bins), w.noise_level,
+                                     synthdata.sinogram_seed(w))
+    parts = synthdata.partition_angles(w.n_angles, w.n_nodes, w.split)
+    v0 = np.random.default_rng(0).standard_normal((w.n, w.n))
+    L = max(stepsize.normal_operator_norm(th[p], w.n, w.n_bins, v0) for p in parts)
+    rho = 1.0
+    eta1 = float(np.float32(c / (L + rho)))
+    segs = synthdata.segment_rows(w.n, w.n_nodes)
+    n, nb = w.n, w.n_bins
+    x = torch.zeros((n, n), dtype=torch.float32, device="cuda")
+    us = [torch.zeros_like(x) for _ in parts]
+    lams = [torch.zeros_like(x) for _ in parts]
+    ents = [dict(n=n, n_bins=nb, angles=to_dev(th[p], torch.float64), slice=0, d=to_dev(d[p]), u=us[m],
+                 lam=lams[m], x=x, seg_row0=segs[m][0], seg_rows=segs[m][1], rho=rho, eta1=eta1, eta2=w.eta2)
+            for m, p in enumerate(parts)]
+    # the node array holds raw device pointers: the entries (which own the
+    # angle and data tensors) go back to the caller with it
+    return w, th, d, parts, segs, rho, eta1, x, us, lams, T.make_nodes(ents), ents
+
+
+@pytest.mark.parametrize("quant", ["kmeans16", "dct50"])
+@pytest.mark.parametrize("mode", ["seg", "avg"])
+def test_tiny_workload_teacher_forced(T, ctx, mode, quant):
+    """All 50 iterations of the tiny workload (64^2, 90 angles, 4 interleaved
+    nodes, E1 = 5, E2 = 10), each checked against one oracle iteration from the
+    GPU's state."""
+    c = 0.1 if mode == "seg" else 1.0
+    w, th, d, parts, segs, rho, eta1, x, us, lams, nodes, _keep = _tiny_setup(T, ctx, mode, c)
+    n, M = w.n, w.n_nodes
+    if quant == "kmeans16":
+        q = T.tomo_quant(T.TOMO_QUANT_KMEANS, 16, 30, 50)
+        labels = [torch.empty(r * n, dtype=torch.uint8, device="cuda") for _, r in segs]
+        cents = [torch.empty(16, dtype=torch.float32, device="cuda") for _ in segs]
+        iters = [torch.empty(1, dtype=torch.int32, device="cuda") for _ in segs]
+        coeffs = lohi = None
+    else:
+        q = T.tomo_quant(T.TOMO_QUANT_DCT, 16, 30, 50)
+        coeffs = [torch.empty((r, n), dtype=torch.int16, device="cuda") for _, r in segs]
+        lohi = [torch.empty(2, dtype=torch.float32, device="cuda") for _ in segs]
+    xts = [torch.empty((r, n), dtype=torch.float32, device="cuda") for _, r in segs]
+    msg_ents = []
+    for m in range(M):
+        e = dict(x_tilde=xts[m])
+        if quant == "kmeans16":
+            e.update(labels=labels[m], centroids=cents[m], iters=iters[m])
+        else:
+            e.update(coeffs=coeffs[m], lohi=lohi[m])
+        msg_ents.append(e)
+    msgs = T.make_msgs(msg_ents)
+    xmode = T.TOMO_XUPDATE_SEGMENT if mode == "seg" else T.TOMO_XUPDATE_AVERAGE
+    worst = dict(u=0.0, xt=0.0, lam=0.0)
+    n_ties = n_codes = 0
+    for k in range(w.outer_iters):
+        log(f"case tiny {mode} {quant} iteration {k}")
+        x0, u0, l0 = _np(x), [_np(u) for u in us], [_np(l) for l in lams]
+        T.admm_local_update(ctx, nodes, w.inner_iters)
+        u1 = [_np(u) for u in us]
+        for m, p in enumerate(parts):
+            ref = oadmm.local_update(u0[m], x0, l0[m], d[p].astype(np.float64), th[p], rho, eta1, w.inner_iters)
+            err = rel_l2(u1[m], ref)
+            worst["u"] = max(worst["u"], err)
+            assert err <= 1e-5, (k, m, err)
+        T.admm_consensus(ctx, nodes, xmode, w.x_iters, q, msgs)
+        x1 = _np(x)
+        if mode == "avg":
+            xt_ref = oadmm.x_update_average(u1, l0, rho)
+        for m, (r0, nr) in enumerate(segs):
+            sl = slice(r0, r0 + nr)
+            if mode == "seg":
+                ref_xt = oadmm.x_update_segment(x0[sl], u1[m][sl], l0[m][sl], rho, w.eta2, w.x_iters)
+            else:
+                ref_xt = xt_ref[sl]
+            xt = xts[m].cpu().numpy()
+            err = rel_l2(xt, ref_xt)
+            worst["xt"] = max(worst["xt"], err)
+            assert err <= 1e-5, (k, m, err)
+            if quant == "kmeans16":
+                ref = kmeans_quantize(xt.reshape(-1), 16, 30)
+                np.testing.assert_array_equal(labels[m].cpu().numpy(), ref.labels)
+                np.testing.assert_array_equal(cents[m].cpu().numpy(), ref.centroids)
+                assert int(iters[m].item()) == ref.iters
+                np.testing.assert_array_equal(x1[sl].astype(np.float32).reshape(-1), ref.a_hat)
+            else:
+                ref = odct.dct_quantize(xt, 50)
+                nd, bad_blocks = _check_dct_codes(coeffs[m].cpu().numpy(), ref, 50)
+                n_ties += nd
+                n_codes += xt.size
+                np.testing.assert_array_equal(lohi[m].cpu().numpy(), [xt.min(), xt.max()])
+                good = ~bad_blocks
+                assert rel_l2(x1[sl][good], ref.a_hat.astype(np.float64)[good]) <= 1e-5
+        for m in range(M):
+            ref = oadmm.dual_update(l0[m], u1[m], x1, rho)
+            err = rel_l2(_np(lams[m]), ref)
+            worst["lam"] = max(worst["lam"], err)
+            assert err <= 1e-5, (k, m, err)
+    log(f"  worst rel-L2 over {w.outer_iters} iterations: {worst}" +
+        (f"; DCT codes at ties {n_ties} of {n_codes}" if n_codes else ""))
+    if n_codes:
+        assert n_ties <= DCT_TIE_BUDGET * n_codes
+
+
+@pytest.mark.parametrize("quality", [25, 50, 90])
+def test_large_workload_dct_consensus_teacher_forced(T, ctx, quality):
+    """The 2048^2, 64-node slice in one batched consensus call with the fused
+    SEG x-update and the DCT codec (64 segments of 32 x 2048): the GPU's x~ against
+    the oracle's Alg. 3, the codec on the GPU's own x~ against the oracle's
+    (codes off by one only at ties, at most 1e-4 of all codes; the exchanged x
+    outside blocks with such codes to 1e-5), and the dual update."""
+    w = synthdata.WORKLOADS["large"]
+    n, M, rows = w.n, w.n_nodes, w.n // w.n_nodes
+    rng = np.random.default_rng(quality)
+    truth = synthdata.phantom(w).astype(np.float32)
+    x = to_dev(truth)
+    x0 = truth.astype(np.float64)
+    us, lams, useg, lseg = [], [], [], []
+    for m in range(M):
+        sl = slice(m * rows, (m + 1) * rows)
+        ub = (truth[sl] + 0.05 * rng.standard_normal((rows, n))).astype(np.float32)
+        lb = (0.02 * rng.standard_normal((rows, n))).astype(np.float32)
+        u = torch.zeros((n, n), dtype=torch.float32, device="cuda")
+        lam = torch.zeros((n, n), dtype=torch.float32, device="cuda")
+        u[sl] = to_dev(ub)
+        lam[sl] = to_dev(lb)
+        us.append(u)
+        lams.append(lam)
+        useg.append(ub.astype(np.float64))
+        lseg.append(lb.astype(np.float64))
+    ang = to_dev(np.zeros(1), torch.float64)
+    dd = torch.zeros((1, w.n_bins), dtype=torch.float32, device="cuda")
+    ents = [dict(n=n, n_bins=w.n_bins, angles=ang, slice=0, d=dd, u=us[m], lam=lams[m], x=x,
+                 seg_row0=m * rows, seg_rows=rows, rho=1.0, eta1=0.0, eta2=w.eta2) for m in range(M)]
+    coeffs = [torch.empty((rows, n), dtype=torch.int16, device="cuda") for _ in range(M)]
+    lohi = [torch.empty(2, dtype=torch.float32, device="cuda") for _ in range(M)]
+    xts = [torch.empty((rows, n), dtype=torch.float32, device="cuda") for _ in range(M)]
+    msgs = T.make_msgs([dict(coeffs=coeffs[m], lohi=lohi[m], x_tilde=xts[m]) for m in range(M)])
+    log(f"case large DCT consensus q={quality}: 64 segments of {rows} x {n}")
+    T.admm_consensus(ctx, T.make_nodes(ents), T.TOMO_XUPDATE_SEGMENT, w.x_iters,
+                     T.tomo_quant(T.TOMO_QUANT_DCT, 16, 30, quality), msgs)
+    torch.cuda.synchronize()
+    x1 = _np(x)
+    n_ties = 0
+    worst_xt = 0.0
+    for m in range(M):
+        sl = slice(m * rows, (m + 1) * rows)
+        ref_xt = oadmm.x_update_segment(x0[sl], useg[m], lseg[m], 1.0, w.eta2, w.x_iters)
+        xt = xts[m].cpu().numpy()
+        err = rel_l2(xt, ref_xt)
+        worst_xt = max(worst_xt, err)
+        assert err <= 1e-5, (m, err)
+        ref = odct.dct_quantize(xt, quality)
+        nd, bad_blocks = _check_dct_codes(coeffs[m].cpu().numpy(), ref, quality)
+        n_ties += nd
+        np.testing.assert_array_equal(lohi[m].cpu().numpy(), [xt.min(), xt.max()])
+        good = ~bad_blocks
+        assert rel_l2(x1[sl][good], ref.a_hat.astype(np.float64)[good]) <= 1e-5, m
+    for m in (0, 21, 63):
+        sl = slice(m * rows, (m + 1) * rows)
+        ub = np.zeros((n, n))
+        ub[sl] = useg[m]
+        lb = np.zeros((n, n))
+        lb[sl] = lseg[m]
+        ref = oadmm.dual_update(lb, ub, x1, 1.0)
+        assert rel_l2(_np(lams[m]), ref) <= 1e-5, m
+    total = M * rows * n
+    log(f"  x~ worst rel-L2 {worst_xt:.2e}; DCT codes at ties {n_ties} of {total} ({n_ties / total:.2e})")
+    assert n_ties <= DCT_TIE_BUDGET * total
