@@ -417,6 +417,21 @@ int quantize_dct(tomo_ctx* ctx, const float* a, int32_t rows, int32_t cols, int3
                  int32_t quality, int16_t* coeffs, float* a_hat, float* lohi, void* stream);
 
 /*
+ * quantize_dct for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments, kernels and results, but the range partials live in a
+ * library-owned device array of DCT_MAX_CHUNKS = 64 float4 (1 KiB) per GPU,
+ * resolved by tomo_create and held until the process ends; no call allocates.
+ * Every input size fits it (a matrix is cut into at most 64 row chunks); the
+ * call still returns TOMO_EINVAL should a size need more.  All calls on one
+ * GPU share that array and it keeps the last call's partials: calls that
+ * overlap in time on one GPU (different streams, or contexts used from
+ * different host threads) race and must be ordered by the caller.
+ */
+int quantize_dct_noalloc(tomo_ctx* ctx, const float* a, int32_t rows, int32_t cols, int32_t ld,
+                         int32_t quality, int16_t* coeffs, float* a_hat, float* lohi, void* stream);
+
+/*
  * Sum of squared differences sum_i (a_i - b_i)^2 accumulated in float64 into
  * out[0] (overwritten).  Used for RMSE (Eq. 25) and relative-change traces.
  */

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <unordered_map>
@@ -37,6 +38,12 @@ __global__ void k_unpack_labels(const unsigned*, int, int, const float*, int, ui
 }  // namespace tomo
 
 using namespace tomo;
+
+// Range partials of quantize_dct_noalloc: one array per device, held until the
+// process ends and shared by every call on that device.  In host code its name
+// is only a stand-in for the symbol: kernels get the device address that
+// hipGetSymbolAddress returns, looked up once per device by tomo_create.
+static __device__ __align__(256) float4 scratch[DCT_MAX_CHUNKS];
 
 static_assert(sizeof(tomo_node) == 80, "tomo_node must have no padding (plans compare it bytewise)");
 static_assert(sizeof(tomo_msg) == 48, "tomo_msg must have no padding");
@@ -392,6 +399,26 @@ int launch_status(tomo_ctx* ctx, const char* what) {
 int set_device(tomo_ctx* ctx) {
   if (hipSetDevice(ctx->device) != hipSuccess) return ctx->fail(TOMO_EDEVICE, "hipSetDevice failed");
   return TOMO_OK;
+}
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float4* g_scratch_ptr[kMaxDevices] = {};
+
+// With the device current: the device address of its scratch array (once).
+int resolve_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return TOMO_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return TOMO_OK;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return TOMO_EDEVICE;
+  g_scratch_ptr[device] = static_cast<float4*>(p);
+  return TOMO_OK;
+}
+
+float4* scratch_of(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return device >= 0 && device < kMaxDevices ? g_scratch_ptr[device] : nullptr;
 }
 
 int check_geom(tomo_ctx* ctx, tomo_geom g) {
@@ -1114,6 +1141,10 @@ int tomo_create(tomo_ctx** out, int device) {
   int xcc = 1;
   if (hipDeviceGetAttribute(&xcc, hipDeviceAttributeNumberOfXccs, device) == hipSuccess) c->n_xcc = std::max(1, xcc);
   (void)hipGetLastError();
+  if (int rc = resolve_scratch(device)) {
+    delete c;
+    return rc;
+  }
   *out = c;
   return TOMO_OK;
 }
@@ -1409,8 +1440,10 @@ int quantize_kmeans(tomo_ctx* ctx, const float* a, int64_t n, int32_t k, int32_t
   return launch_status(ctx, "quantize_kmeans");
 }
 
-int quantize_dct(tomo_ctx* ctx, const float* a, int32_t rows, int32_t cols, int32_t ld, int32_t quality,
-                 int16_t* coeffs, float* a_hat, float* lohi, void* stream) {
+// Argument checks and the two launches of the DCT codec; `part` holds the range
+// partials (null: the context's workspace, allocated on first use).
+static int dct_codec(tomo_ctx* ctx, const float* a, int32_t rows, int32_t cols, int32_t ld, int32_t quality,
+                     int16_t* coeffs, float* a_hat, float* lohi, float4* part, void* stream, const char* what) {
   if (!ctx) return TOMO_EINVAL;
   if (rows < 8 || cols < 8 || rows % 8 || cols % 8 || ld < cols)
     return ctx->fail(TOMO_EINVAL, "rows, cols must be positive multiples of 8 and ld >= cols");
@@ -1430,12 +1463,29 @@ int quantize_dct(tomo_ctx* ctx, const float* a, int32_t rows, int32_t cols, int3
   j.rho = 1.f;
   j.chunk_rows = dct_chunk_rows(rows, cols);
   j.n_chunks = (rows + j.chunk_rows - 1) / j.chunk_rows;
-  if (!ctx->dct_part.ensure((size_t)DCT_MAX_CHUNKS * sizeof(float4))) return ctx->fail(TOMO_ENOMEM, "workspace");
-  j.part = static_cast<float4*>(ctx->dct_part.p);
+  if (j.n_chunks > DCT_MAX_CHUNKS) return ctx->fail(TOMO_EINVAL, "more range partials than the scratch holds");
+  if (!part) {
+    if (!ctx->dct_part.ensure((size_t)DCT_MAX_CHUNKS * sizeof(float4))) return ctx->fail(TOMO_ENOMEM, "workspace");
+    part = static_cast<float4*>(ctx->dct_part.p);
+  }
+  j.part = part;
   hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(k_dct_range, dim3(j.n_chunks), dim3(DCT_THREADS), 0, s, nullptr, 1, j, 0, 0);
   hipLaunchKernelGGL(k_dct_code, dim3(dct_code_wgs(rows, cols)), dim3(DCT_THREADS), 0, s, nullptr, 1, j, quality);
-  return launch_status(ctx, "quantize_dct");
+  return launch_status(ctx, what);
+}
+
+int quantize_dct(tomo_ctx* ctx, const float* a, int32_t rows, int32_t cols, int32_t ld, int32_t quality,
+                 int16_t* coeffs, float* a_hat, float* lohi, void* stream) {
+  return dct_codec(ctx, a, rows, cols, ld, quality, coeffs, a_hat, lohi, nullptr, stream, "quantize_dct");
+}
+
+int quantize_dct_noalloc(tomo_ctx* ctx, const float* a, int32_t rows, int32_t cols, int32_t ld, int32_t quality,
+                         int16_t* coeffs, float* a_hat, float* lohi, void* stream) {
+  if (!ctx) return TOMO_EINVAL;
+  float4* part = scratch_of(ctx->device);
+  if (!part) return ctx->fail(TOMO_EDEVICE, "device scratch not resolved");
+  return dct_codec(ctx, a, rows, cols, ld, quality, coeffs, a_hat, lohi, part, stream, "quantize_dct_noalloc");
 }
 
 int tomo_pack_labels(tomo_ctx* ctx, const uint8_t* labels, int64_t n, int32_t bits, uint32_t* packed,

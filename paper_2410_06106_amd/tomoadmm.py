@@ -30,7 +30,7 @@ EXPORTED = ("tomo_create", "tomo_destroy", "tomo_status_string", "tomo_last_erro
             "tomo_project",
             "tomo_backproject", "tomo_project_many", "tomo_backproject_many", "tomo_ctr_gd", "admm_local_update", "admm_local_phase", "admm_consensus",
             "admm_reg_update", "admm_consensus_reg",
-            "quantize_kmeans", "quantize_dct", "tomo_pack_labels", "tomo_unpack_labels",
+            "quantize_kmeans", "quantize_dct", "quantize_dct_noalloc", "tomo_pack_labels", "tomo_unpack_labels",
             "tomo_dct_encode_words", "tomo_dct_encode", "tomo_dct_decode", "tomo_sqdiff")
 
 
@@ -102,6 +102,7 @@ _lib.admm_consensus_reg.argtypes = [_P, ctypes.POINTER(tomo_node), ctypes.c_int3
 _lib.quantize_kmeans.argtypes = [_P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P]
 _lib.quantize_dct.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                               _P, _P, _P, _P]
+_lib.quantize_dct_noalloc.argtypes = _lib.quantize_dct.argtypes
 _lib.tomo_sqdiff.argtypes = [_P, _P, _P, ctypes.c_int64, _P, _P]
 _lib.tomo_pack_labels.argtypes = [_P, _P, ctypes.c_int64, ctypes.c_int32, _P, _P]
 _lib.tomo_dct_encode_words.argtypes = [ctypes.c_int32, ctypes.c_int32]
@@ -301,15 +302,18 @@ def quantize_kmeans(ctx: Context, a, k: int, max_iter: int = 30, labels=None, ce
     return labels, centroids
 
 
-def quantize_dct(ctx: Context, a, quality: int, coeffs=None, a_hat=None, lohi=None, stream=None):
+def quantize_dct(ctx: Context, a, quality: int, coeffs=None, a_hat=None, lohi=None, stream=None, noalloc=False):
+    """JPEG-style codec of a [rows][cols] matrix; ``noalloc`` calls
+    quantize_dct_noalloc (no device allocation; the library's per-GPU scratch)."""
     rows, cols = a.shape
     if a_hat is None:
         a_hat = torch.empty_like(a)
-    rc = _lib.quantize_dct(ctx.handle, _dev(a, torch.float32, "a"), rows, cols, cols, int(quality),
-                           _opt(coeffs, torch.int16, "coeffs", (rows, cols)),
-                           _dev(a_hat, torch.float32, "a_hat", (rows, cols)),
-                           _opt(lohi, torch.float32, "lohi", (2,)), _stream(stream))
-    ctx.check(rc, "quantize_dct")
+    fn = _lib.quantize_dct_noalloc if noalloc else _lib.quantize_dct
+    rc = fn(ctx.handle, _dev(a, torch.float32, "a"), rows, cols, cols, int(quality),
+            _opt(coeffs, torch.int16, "coeffs", (rows, cols)),
+            _dev(a_hat, torch.float32, "a_hat", (rows, cols)),
+            _opt(lohi, torch.float32, "lohi", (2,)), _stream(stream))
+    ctx.check(rc, "quantize_dct_noalloc" if noalloc else "quantize_dct")
     return a_hat
 
 
