@@ -52,8 +52,6 @@ struct KMShared {
   float upd[KM_MAX_K];            // updated centres before sorting
   int cb[2][KM_MAX_K + 1];        // values at or below threshold j-1 (label < j), two generations
   long long sb[KM_MAX_K + 1];     // their code sums
-  int cb3[3][65];                 // the same for k <= 64, three generations
-  long long sb3[3][65];
   long long wsum[KWAVES];
   int wcnt[KWAVES];
   float red[2 * KWAVES];
@@ -159,6 +157,14 @@ __device__ __forceinline__ long long dpp_add_i64(long long v) {
   return v + (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
+__device__ __forceinline__ long long group_sum(long long v, int G) {
+  if (G >= 2) v = dpp_add_i64<0xB1>(v);
+  if (G >= 4) v = dpp_add_i64<0x4E>(v);
+  if (G >= 8) v = dpp_add_i64<0x141>(v);
+  if (G >= 16) v = dpp_add_i64<0x140>(v);
+  return v;
+}
+
 __device__ __forceinline__ long long wave_sum_i64(long long v) {
   v = dpp_add_i64<0xB1>(v);    // quad_perm [1, 0, 3, 2]: pairs
   v = dpp_add_i64<0x4E>(v);    // quad_perm [2, 3, 0, 1]: quads
@@ -170,6 +176,65 @@ __device__ __forceinline__ long long wave_sum_i64(long long v) {
     return (long long)(((unsigned long long)hi << 32) | lo);
   };
   return lane(0) + lane(16) + lane(32) + lane(48);
+}
+
+// Value of lane `src` (an explicit cross-lane permute, ds_bpermute); every
+// lane of the wave must be active, since a permute reads zero from an inactive
+// lane.
+__device__ __forceinline__ int lane_from(int v, int src) { return __builtin_amdgcn_ds_bpermute(src << 2, v); }
+__device__ __forceinline__ float lane_from(float v, int src) { return __int_as_float(lane_from(__float_as_int(v), src)); }
+__device__ __forceinline__ long long lane_from(long long v, int src) {
+  const unsigned lo = (unsigned)lane_from((int)v, src), hi = (unsigned)lane_from((int)(v >> 32), src);
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
+// Sums over aligned groups of G lanes (G = 1, 2, 4, 8 or 16; all lanes active),
+// returned to every lane of the group: butterflies within rows of 16 lanes.
+__device__ __forceinline__ int group_sum(int v, int G) {
+  if (G >= 2) v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);    // quad_perm [1, 0, 3, 2]
+  if (G >= 4) v += __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);    // quad_perm [2, 3, 0, 1]
+  if (G >= 8) v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);   // row_half_mirror
+  if (G >= 16) v += __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false);  // row_mirror
+  return v;
+}
+// Count and code sum of the values a <= x for the threshold x of a group of G
+// lanes (every lane of the wave active; the G lanes of a group hold the same
+// x): the buckets left of x's bucket from the prefix tables, plus the values of
+// that bucket at or below x, which the group's lanes read G apart and add up
+// with butterflies.  Every lane of the group gets the totals.
+template <class VP>
+__device__ __forceinline__ void group_at_or_below(const KMShared& sh, VP V, float x, const Buckets& bk, float lo,
+                                                  float hi, int n, long long tot, int S, int G, int& cnt,
+                                                  long long& sum) {
+  const int sub = (threadIdx.x & 63) & (G - 1);
+  int c0 = 0, p0 = 0, p1 = 0;
+  long long s0 = 0;
+  if (x >= hi) {
+    c0 = n;
+    s0 = tot;
+  } else if (x >= lo) {
+    const int b = bk.of(x);
+    p0 = sh.start[b];
+    p1 = sh.start[b + 1];
+    c0 = p0;
+    s0 = sh.psum[b];
+  }
+  int c = 0;
+  long long s = 0;
+  for (int p = p0 + sub; p < p1; p += 2 * G) {   // two reads per trip, both in flight
+    const float a0 = V[p];
+    const float a1 = V[min(p + G, p1 - 1)];
+    if (a0 <= x) {
+      ++c;
+      s += km_fixed(a0, S);
+    }
+    if (p + G < p1 && a1 <= x) {
+      ++c;
+      s += km_fixed(a1, S);
+    }
+  }
+  cnt = c0 + group_sum(c, G);
+  sum = s0 + group_sum(s, G);
 }
 
 // Count and code sum of the values a <= x, by one wave (every lane active and
@@ -292,14 +357,14 @@ __global__ __launch_bounds__(KT) void k_kmeans(const KMJob* jobs, KMJob single, 
         for (int e = 0; e < KVPT; ++e) {
           const long long i = base + tid + (long long)e * KT;
           a[e] = km_xupdate_reg(a[e], uv[e], lv[e], J.rho, RB.rho_z, J.eta2, e2);
-          if (i < n) xo[i] = a[e];
+          if (!REG && i < n) xo[i] = a[e];   // re-read by the later passes
         }
       } else {
 #pragma unroll
         for (int e = 0; e < KVPT; ++e) {
           const long long i = base + tid + (long long)e * KT;
           a[e] = km_xupdate(a[e], uv[e], lv[e], J.rho, irho, J.eta2, e2);
-          if (i < n) xo[i] = a[e];
+          if (!REG && i < n) xo[i] = a[e];   // re-read by the later passes
         }
       }
     }
@@ -335,8 +400,9 @@ __global__ __launch_bounds__(KT) void k_kmeans(const KMJob* jobs, KMJob single, 
     bad |= sh.redb[q];
   }
   if (bad || hi == lo) {
-    // constant segment: one cluster at lo; non-finite input: flagged
-    const bool copy = J.a_hat && J.a_hat != (do_x ? J.x : J.src);
+    // constant segment: one cluster at lo; non-finite input: flagged (values
+    // held in registers are always written: x~ was not stored in pass 1)
+    const bool copy = J.a_hat && (REG || J.a_hat != (do_x ? J.x : J.src));
     each([&](int i, float a) {
       if (J.labels) labels[i] = 0;
       if (copy) ahat[i] = a;
@@ -393,72 +459,66 @@ __global__ __launch_bounds__(KT) void k_kmeans(const KMJob* jobs, KMJob single, 
 
   int it = 0;
   if (k <= 64) {
-    // Lloyd iterations with one workgroup barrier each: every wave holds the
-    // k centres in its lanes and updates them redundantly from the shared
-    // boundary counts; wave w scans the buckets of thresholds w, w + 16, ...
-    // The counts rotate through three generations, so the one written in an
-    // iteration was last read two barriers earlier.
-    // Lane l holds centre l and the threshold between centres l and l + 1
-    // (its right neighbour's centre comes in with one shuffle).
-    float cj = l < k ? sh.cent[l] : 0.f;
-    float xt = threshold((double)cj + (double)__shfl_down(cj, 1, 64));
-    int gen = 0;
-    for (int t = 0;; ++t) {
-      for (int j = w; j < k - 1; j += KWAVES) {
-        const float x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(xt), j));
-        int c;
-        long long sm;
-        scan_bucket(x, c, sm);
-        if (l == 0) {
-          sh.cb3[gen][j + 1] = c;
-          sh.sb3[gen][j + 1] = sm;
-          sh.thr[j] = x;
+    // Lloyd iterations in wave 0 alone, with no barrier inside the loop.  The
+    // wave is cut into k groups of G lanes (G <= 16, G k <= 64): group j holds
+    // centre j and, for j < k - 1, the threshold between centres j and j + 1,
+    // whose count and code sum at or below it the group's lanes find together.
+    // Cluster j is the values between thresholds j - 1 and j; its totals take
+    // the previous group's by a permute.  Groups from k - 1 up hold no
+    // threshold (+inf: all n values, the total code sum).  Every cross-lane
+    // operation runs with all 64 lanes active.
+    if (w == 0) {
+      int G = 16;
+      while (G > 1 && G * k > 64) G >>= 1;
+      const int grp = l / G;
+      const bool has_c = grp < k, has_t = grp < k - 1;
+      float cj = has_c ? sh.cent[grp] : 0.f;
+      const float c1 = lane_from(cj, min(l + G, 63));
+      float xt = has_t ? threshold((double)cj + (double)c1) : INFINITY;
+      int prev = 0;
+      for (int t = 0;; ++t) {
+        int cb;
+        long long sb;
+        if constexpr (REG) group_at_or_below(sh, vlds, xt, bk, lo, hi, n, tot, S, G, cb, sb);
+        else group_at_or_below(sh, gptr((const float*)wv), xt, bk, lo, hi, n, tot, S, G, cb, sb);
+        if (t > 0) {
+          it = t;
+          if (__ballot(has_t && cb != prev) == 0) break;   // no label changed
         }
-      }
-      if (tid == 0) {
-        sh.cb3[gen][0] = 0;
-        sh.cb3[gen][k] = n;
-        sh.sb3[gen][0] = 0;
-        sh.sb3[gen][k] = tot;
-      }
-      __syncthreads();
-      // every count this iteration needs, read at once (the previous
-      // generation is read but unused at t = 0)
-      const int prev = gen == 0 ? 2 : gen - 1;
-      const int b0 = sh.cb3[gen][l], b1 = sh.cb3[gen][l + 1], bp = sh.cb3[prev][l + 1];
-      const long long s0 = sh.sb3[gen][l], s1 = sh.sb3[gen][l + 1];
-      if (t > 0) {
-        it = t;
-        const bool moved = __ballot(l + 1 < k && b1 != bp) != 0;
-        if (!moved) break;
-      }
-      if (t == max_iter) break;
-      // centres of the current labels, then their stable sort: when they are
-      // already non-decreasing the sort is the identity; otherwise every lane
-      // finds its stable rank (broadcast one lane at a time) and picks the
-      // centre ranked l
-      const int c = l < k ? b1 - b0 : 0;
-      float u = cj;
-      if (c > 0) u = (float)(ldexp((double)(s1 - s0), -S) / (double)c);
-      float un = __shfl_down(u, 1, 64);
-      if (__ballot(l + 1 < k && un < u) == 0) {
-        cj = u;
-      } else {
-        int r = 0;
-        for (int i = 0; i < k; ++i) {
-          const float ui = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(u), i));
-          r += (ui < u) || (ui == u && i < l);
+        if (t == max_iter) break;
+        prev = cb;
+        // centres of the current labels, then their stable sort: when they are
+        // already non-decreasing the sort is the identity; otherwise every group
+        // finds its stable rank (the groups' first lanes broadcast one at a
+        // time) and picks the centre ranked grp
+        const int cprev = lane_from(cb, max(l - G, 0));
+        const long long sprev = lane_from(sb, max(l - G, 0));
+        const int c = has_c ? cb - (grp > 0 ? cprev : 0) : 0;
+        const long long q = sb - (grp > 0 ? sprev : 0);
+        float u = cj;
+        if (c > 0) u = (float)(ldexp((double)q, -S) / (double)c);
+        float un = lane_from(u, min(l + G, 63));
+        if (__ballot(grp + 1 < k && un < u) == 0) {
+          cj = u;
+        } else {
+          int r = 0;
+          for (int i = 0; i < k; ++i) {
+            const float ui = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(u), i * G));
+            r += (ui < u) || (ui == u && i < grp);
+          }
+          for (int i = 0; i < k; ++i) {
+            const float ui = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(u), i * G));
+            cj = __builtin_amdgcn_readlane(r, i * G) == grp ? ui : cj;
+          }
+          un = lane_from(cj, min(l + G, 63));
         }
-        for (int i = 0; i < k; ++i) {
-          const float ui = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(u), i));
-          cj = __builtin_amdgcn_readlane(r, i) == l ? ui : cj;
-        }
-        un = __shfl_down(cj, 1, 64);
+        xt = has_t ? threshold((double)cj + (double)un) : INFINITY;
       }
-      xt = threshold((double)cj + (double)un);
-      gen = gen == 2 ? 0 : gen + 1;
+      if ((l & (G - 1)) == 0) {
+        if (has_c) sh.cent[grp] = cj;
+        if (has_t) sh.thr[grp] = xt;
+      }
     }
-    if (tid < k) sh.cent[tid] = cj;
     __syncthreads();
   } else {
     auto boundaries = [&](int gen) {
@@ -506,10 +566,19 @@ __global__ __launch_bounds__(KT) void k_kmeans(const KMJob* jobs, KMJob single, 
     float th[15];
 #pragma unroll
     for (int j = 0; j < 15; ++j) th[j] = j < k - 1 ? sh.thr[j] : INFINITY;
-    each([&](int i, float a) {
+    auto label = [&](float a) {
       int p = 0;
+      if (k <= 8) {
 #pragma unroll
-      for (int j = 0; j < 15; ++j) p += th[j] < a ? 1 : 0;
+        for (int j = 0; j < 7; ++j) p += th[j] < a ? 1 : 0;
+      } else {
+#pragma unroll
+        for (int j = 0; j < 15; ++j) p += th[j] < a ? 1 : 0;
+      }
+      return p;
+    };
+    each([&](int i, float a) {
+      const int p = label(a);
       if (J.labels) labels[i] = (uint8_t)p;
       if (J.a_hat) ahat[i] = sh.cent[p];
     });

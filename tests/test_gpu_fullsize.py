@@ -141,24 +141,25 @@ def test_large_workload_local_update_sampled_node(mods):
     assert err <= 1e-5
 
 
-def test_single_workload_tv_block_z_update(mods):
+@pytest.mark.parametrize("tv_iters", [10, 11])
+def test_single_workload_tv_block_z_update(mods, tv_iters):
     """The regularization block at bench.py --reg tv's settings on the 512^2,
     16-node slice (TV, mu = 0.02, 10 Chambolle iterations: two launches of 5
-    iterations, the second also forming z and t_z): z, t_z and the field after
-    two z-updates (the
-    second warm-started from the first's field) against the oracle on the
-    whole image."""
+    iterations, the second also forming z and t_z; 11: launches of 6 and 5, the
+    first using the whole halo of the tile): z, t_z and the field after two
+    z-updates (the second warm-started from the first's field) against the
+    oracle on the whole image."""
     from oracle import reg as oreg
     T, A = mods
     ctx = T.Context(0)
     w = synthdata.WORKLOADS["single"]
     s = _slice(T, A, ctx, w)
-    run = A.DADMM(ctx, [s], reg=dict(kind=T.TOMO_REG_TV, mu=0.02, tv_iters=10))
+    run = A.DADMM(ctx, [s], reg=dict(kind=T.TOMO_REG_TV, mu=0.02, tv_iters=tv_iters))
     rng = np.random.default_rng(7)
     nu = (0.05 * rng.standard_normal((w.n, w.n))).astype(np.float32)
     s.reg["nu"].copy_(to_dev(nu))
     x = s.x.cpu().numpy().astype(np.float64)
-    r = oreg.Reg(kind=oreg.TV, mu=0.02, rho=1.0, tv_iters=10)
+    r = oreg.Reg(kind=oreg.TV, mu=0.02, rho=1.0, tv_iters=tv_iters)
     p = None
     for k in range(2):
         T.admm_reg_update(ctx, run.nodes, run.regs)

@@ -40,10 +40,12 @@ def _slice_nodes(T, n, n_nodes, x, us, lams, rho=1.0, eta2=0.2, slice_id=0):
     return ents
 
 
-@pytest.mark.parametrize("iters", [0, 1, 7, 10, 16, 17])
+@pytest.mark.parametrize("iters", [0, 1, 7, 10, 11, 16, 17, 23])
 def test_z_update_matches_oracle(mods, ctx, iters):
     """Two blocks in one call: TV on a 130 x 130 slice (several workgroups, a
-    ragged tail) from a non-zero field, Tikhonov on a 37 x 37 slice."""
+    ragged tail) from a non-zero field, Tikhonov on a 37 x 37 slice.  11 and 23
+    iterations make launches of 6 + 5 and 6 + 6 + 6 + 5: a launch of the full
+    six iterations uses up the whole halo of the tile."""
     T, _ = mods
     rng = np.random.default_rng(10 + iters)
     blocks, ents = [], []
