@@ -432,6 +432,61 @@ int quantize_dct_noalloc(tomo_ctx* ctx, const float* a, int32_t rows, int32_t co
                          int32_t quality, int16_t* coeffs, float* a_hat, float* lohi, void* stream);
 
 /*
+ * Elementwise steps of the unrolled (differentiable) decentralized ADMM and
+ * their exact gradients, for a learned penalty rho_k and step eta_k per
+ * iteration.  The M nodes' images are stacked: U, L, B, G, dU, dL are float32
+ * [M][npix], npix = n * n, node m at offset m * npix; x, dx are float32 [npix];
+ * scal is float32 [2] in device memory = (rho, eta) (eta unused by the x-update
+ * and dual calls); dscal is float32 [2] device output = (d rho, d eta).  All
+ * pointers are device pointers owned by the caller; outputs must not overlap
+ * inputs.  The scalar gradients are float64 sums reduced in a fixed order (a
+ * context workspace of 96 KiB, allocated on first use).  Errors: TOMO_EINVAL
+ * for m < 1, npix < 1, a null pointer or e2 < 0.
+ *   tomo_unroll_ustep       Alg. 2 step: Uo = U - eta (B + rho (U - x) + L),
+ *                           B = P^T (P U - D) computed by the caller with the
+ *                           batched projector pair (tomo_axpby forms P U - D).
+ *   tomo_unroll_ustep_grad  given G = dLoss/dUo, PG = P G, PtPG = P^T P G and the
+ *                           forward residual R = P U - D (nsino values, stacked
+ *                           like PG): dU = G - eta (PtPG + rho G), dL = -eta G,
+ *                           dx = eta rho sum_m G_m, d rho = -eta <G, U - x>,
+ *                           d eta = -(<PG, R> + rho <G, U - x> + <G, L>).
+ *   tomo_unroll_xseg        Alg. 3 on every row r from x: E2 steps
+ *                           x <- x - eta2 rho (x - t), t = U_o + L_o / rho,
+ *                           o = owner[r] (int32 [n], the node owning row r).
+ *   tomo_unroll_xseg_grad   with a = 1 - eta2 rho: dx = a^E2 G, dU_o = (1 - a^E2) G,
+ *                           dL_o = (1 - a^E2) G / rho (zero on rows a node does
+ *                           not own), d rho = sum G ((1 - a^E2)(-L_o / rho^2)
+ *                           - E2 eta2 a^(E2-1) (x - t)).
+ *   tomo_unroll_xavg        Eq. 9: xo = (1/M) sum_m (U_m + L_m / rho).
+ *   tomo_unroll_xavg_grad   dU_m = G / M, dL_m = G / (M rho),
+ *                           d rho = -sum_m <G, L_m> / (M rho^2).
+ *   tomo_unroll_dual        Eq. 24: Lo = L + rho (U - xn).
+ *   tomo_unroll_dual_grad   dL = G, dU = rho G, dxn = -rho sum_m G_m,
+ *                           d rho = <G, U - xn>.
+ *   tomo_axpby              out = alpha a + beta b over n values (out may be a or b).
+ */
+int tomo_axpby(tomo_ctx* ctx, int64_t n, float alpha, const float* a, float beta, const float* b, float* out,
+               void* stream);
+int tomo_unroll_ustep(tomo_ctx* ctx, int32_t m, int64_t npix, const float* U, const float* B, const float* x,
+                      const float* L, const float* scal, float* Uo, void* stream);
+int tomo_unroll_ustep_grad(tomo_ctx* ctx, int32_t m, int64_t npix, const float* G, const float* PtPG, const float* PG,
+                           const float* R, int64_t nsino, const float* U, const float* x, const float* L,
+                           const float* scal, float* dU, float* dL, float* dx, float* dscal, void* stream);
+int tomo_unroll_xseg(tomo_ctx* ctx, int32_t m, int32_t n, const int32_t* owner, const float* U, const float* L,
+                     const float* x, const float* scal, float eta2, int32_t e2, float* xo, void* stream);
+int tomo_unroll_xseg_grad(tomo_ctx* ctx, int32_t m, int32_t n, const int32_t* owner, const float* G, const float* U,
+                          const float* L, const float* x, const float* scal, float eta2, int32_t e2, float* dU,
+                          float* dL, float* dx, float* dscal, void* stream);
+int tomo_unroll_xavg(tomo_ctx* ctx, int32_t m, int64_t npix, const float* U, const float* L, const float* scal,
+                     float* xo, void* stream);
+int tomo_unroll_xavg_grad(tomo_ctx* ctx, int32_t m, int64_t npix, const float* G, const float* L, const float* scal,
+                          float* dU, float* dL, float* dscal, void* stream);
+int tomo_unroll_dual(tomo_ctx* ctx, int32_t m, int64_t npix, const float* L, const float* U, const float* xn,
+                     const float* scal, float* Lo, void* stream);
+int tomo_unroll_dual_grad(tomo_ctx* ctx, int32_t m, int64_t npix, const float* G, const float* U, const float* xn,
+                          const float* scal, float* dL, float* dU, float* dxn, float* dscal, void* stream);
+
+/*
  * Sum of squared differences sum_i (a_i - b_i)^2 accumulated in float64 into
  * out[0] (overwritten).  Used for RMSE (Eq. 25) and relative-change traces.
  */

@@ -14,7 +14,13 @@ iteration (2K scalars), and checkpoints the iterates (x, u_m, lambda_m) every
 ``ckpt`` iterations: only the checkpointed states are kept for the backward
 pass, the iterations in between are recomputed.  The nodes' u_m and lambda_m
 are stacked into [M][n][n] tensors, so every operator and every elementwise
-step of an iteration is one launch for all nodes.
+step of an iteration is one launch for all nodes.  Every step of an iteration
+is a Function whose forward and backward are HIP kernels (the tomo_unroll_*
+calls): ``LocalStep`` (Alg. 2: P, the residual, P^T and the u-step; its
+backward applies P^T P to the incoming gradient and forms the gradients of u,
+x, lambda, rho and eta, the scalar ones as float64 sums), ``XSegment`` (Alg. 3),
+``XAverage`` (Eq. 9) and ``Dual`` (Eq. 24).  (rho_k, eta_k) enter the kernels
+as a two-element device tensor, so learned values never go through the host.
 """
 from __future__ import annotations
 
@@ -107,6 +113,88 @@ class BackprojectMany(torch.autograd.Function):
         return out, None, None, None
 
 
+class LocalStep(torch.autograd.Function):
+    """One Alg. 2 step for all nodes: U' = U - eta (P^T (P U - D) + rho (U - x) + L)."""
+
+    @staticmethod
+    def forward(fctx, U, x, L, scal, D, tctx, angles, n_bins):
+        U = U.contiguous()
+        sizes = [int(a.numel()) for a in angles]
+        R = torch.empty((sum(sizes), n_bins), dtype=torch.float32, device=U.device)
+        T.tomo_project_many(tctx, _items(angles, U, R, sizes))
+        T.tomo_axpby(tctx, 1.0, R, -1.0, D, out=R)                       # R = P U - D
+        B = torch.empty_like(U)
+        T.tomo_backproject_many(tctx, _items(angles, B, R, sizes), 1.0, 0.0)
+        Uo = T.tomo_unroll_ustep(tctx, U, B, x.contiguous(), L.contiguous(), scal.contiguous())
+        fctx.save_for_backward(U, x, L, scal, R)
+        fctx.tctx, fctx.angles, fctx.sizes, fctx.n_bins = tctx, angles, sizes, n_bins
+        return Uo
+
+    @staticmethod
+    def backward(fctx, G):
+        U, x, L, scal, R = fctx.saved_tensors
+        G = G.contiguous()
+        PG = torch.empty_like(R)
+        T.tomo_project_many(fctx.tctx, _items(fctx.angles, G, PG, fctx.sizes))
+        PtPG = torch.empty_like(U)
+        T.tomo_backproject_many(fctx.tctx, _items(fctx.angles, PtPG, PG, fctx.sizes), 1.0, 0.0)
+        dU, dL, dx, ds = T.tomo_unroll_ustep_grad(fctx.tctx, G, PtPG, PG, R, U, x.contiguous(), L.contiguous(),
+                                                  scal.contiguous())
+        return dU, dx, dL, ds, None, None, None, None
+
+
+class XSegment(torch.autograd.Function):
+    """Alg. 3 on every node's own rows: E2 steps x <- x - eta2 rho (x - t), t = U_o + L_o / rho."""
+
+    @staticmethod
+    def forward(fctx, U, L, x, scal, owner, tctx, eta2, e2):
+        U, L, x, scal = U.contiguous(), L.contiguous(), x.contiguous(), scal.contiguous()
+        xo = T.tomo_unroll_xseg(tctx, owner, U, L, x, scal, eta2, e2)
+        fctx.save_for_backward(U, L, x, scal, owner)
+        fctx.tctx, fctx.eta2, fctx.e2 = tctx, eta2, e2
+        return xo
+
+    @staticmethod
+    def backward(fctx, G):
+        U, L, x, scal, owner = fctx.saved_tensors
+        dU, dL, dx, ds = T.tomo_unroll_xseg_grad(fctx.tctx, owner, G.contiguous(), U, L, x, scal, fctx.eta2, fctx.e2)
+        return dU, dL, dx, ds, None, None, None, None
+
+
+class XAverage(torch.autograd.Function):
+    """Eq. 9: x = mean_m (U_m + L_m / rho)."""
+
+    @staticmethod
+    def forward(fctx, U, L, scal, tctx):
+        U, L, scal = U.contiguous(), L.contiguous(), scal.contiguous()
+        fctx.save_for_backward(L, scal)
+        fctx.tctx = tctx
+        return T.tomo_unroll_xavg(tctx, U, L, scal)
+
+    @staticmethod
+    def backward(fctx, G):
+        L, scal = fctx.saved_tensors
+        dU, dL, ds = T.tomo_unroll_xavg_grad(fctx.tctx, G.contiguous(), L, scal)
+        return dU, dL, ds, None
+
+
+class Dual(torch.autograd.Function):
+    """Eq. 24: L' = L + rho (U - x')."""
+
+    @staticmethod
+    def forward(fctx, L, U, xn, scal, tctx):
+        L, U, xn, scal = L.contiguous(), U.contiguous(), xn.contiguous(), scal.contiguous()
+        fctx.save_for_backward(U, xn, scal)
+        fctx.tctx = tctx
+        return T.tomo_unroll_dual(tctx, L, U, xn, scal)
+
+    @staticmethod
+    def backward(fctx, G):
+        U, xn, scal = fctx.saved_tensors
+        dL, dU, dxn, ds = T.tomo_unroll_dual_grad(fctx.tctx, G.contiguous(), U, xn, scal)
+        return dL, dU, dxn, ds, None
+
+
 def project_many(tctx, images, angles, n_bins):
     """images [M][n][n] -> sinograms of all nodes stacked along the angle axis."""
     return ProjectMany.apply(images, tctx, angles, n_bins)
@@ -134,30 +222,21 @@ class UnrolledADMM(torch.nn.Module):
         self.log_rho = torch.nn.Parameter(torch.full((iters,), float(torch.log(torch.tensor(rho0)))))
         self.log_eta = torch.nn.Parameter(torch.full((iters,), float(torch.log(torch.tensor(eta0)))))
         # owner node of every image row (segments are disjoint row strips covering x)
-        owner = torch.empty(n, dtype=torch.long)
+        owner = torch.empty(n, dtype=torch.int32)
         for m, (r0, nr) in enumerate(segments):
             owner[r0:r0 + nr] = m
         self.owner = owner
-        self.rows = torch.arange(n)
 
     def _iteration(self, k, D, x, U, L):
         """One iteration for all nodes: U, L [M][n][n], D the stacked data."""
-        rho = torch.exp(self.log_rho[k])
-        eta = torch.exp(self.log_eta[k])
+        scal = torch.stack([torch.exp(self.log_rho[k]), torch.exp(self.log_eta[k])])   # (rho_k, eta_k)
         for _ in range(self.e1):                                                # Alg. 2
-            R = project_many(self.tctx, U, self.angles, self.n_bins) - D
-            G = backproject_many(self.tctx, R, self.angles, self.n) + rho * (U - x) + L
-            U = U - eta * G
-        if self.mode == "seg":                                                  # Alg. 3
-            # row r of x belongs to the node whose segment holds it
-            t = (U + L / rho)[self.owner, self.rows]
-            xs = x
-            for _ in range(self.e2):
-                xs = xs - self.eta2 * rho * (xs - t)
-            x_new = xs                                                          # Eq. 17
-        else:
-            x_new = (U + L / rho).sum(dim=0) / U.shape[0]                       # Eq. 9
-        L = L + rho * (U - x_new)                                               # Eq. 18
+            U = LocalStep.apply(U, x, L, scal, D, self.tctx, self.angles, self.n_bins)
+        if self.mode == "seg":                                                  # Alg. 3 (Eq. 17)
+            x_new = XSegment.apply(U, L, x, scal, self.owner, self.tctx, self.eta2, self.e2)
+        else:                                                                   # Eq. 9
+            x_new = XAverage.apply(U, L, scal, self.tctx)
+        L = Dual.apply(L, U, x_new, scal, self.tctx)                            # Eq. 18 / 24
         return x_new, U, L
 
     def _segment(self, k0, k1, D, x, U, L):
@@ -171,7 +250,7 @@ class UnrolledADMM(torch.nn.Module):
         m = len(self.angles)
         D = torch.cat([di.reshape(-1, self.n_bins) for di in d], dim=0)
         if self.owner.device != dev:
-            self.owner, self.rows = self.owner.to(dev), self.rows.to(dev)
+            self.owner = self.owner.to(dev)
         x = torch.zeros((n, n), device=dev)
         U = torch.zeros((m, n, n), device=dev)
         L = torch.zeros((m, n, n), device=dev)

@@ -11,7 +11,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtomoadmm.so")
-SOURCES = ["api.hip", "project.hip", "project_res.hip", "backproject.hip", "consensus.hip", "kmeans.hip", "wire.hip", "entropy.hip", "reg.hip"]
+SOURCES = ["api.hip", "project.hip", "project_res.hip", "backproject.hip", "consensus.hip", "kmeans.hip", "wire.hip",
+           "entropy.hip", "reg.hip", "unroll.hip"]
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
     # no packed-FP32 instructions (v_pk_*_f32) in any generated code

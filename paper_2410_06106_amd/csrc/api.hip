@@ -1,5 +1,6 @@
 // C ABI of the tomoadmm library: argument checks, workspace and plans, launches.
 #include <algorithm>
+#include <initializer_list>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -35,6 +36,23 @@ __global__ void k_ecode_write(const int16_t*, int, int, int, const unsigned*, un
 __global__ void k_ecode_decode(const unsigned*, long long, const unsigned*, const unsigned*, int, int, int16_t*, int,
                                int*);
 __global__ void k_unpack_labels(const unsigned*, int, int, const float*, int, uint8_t*, float*);
+__global__ void k_unroll_ustep(int, long long, const float*, const float*, const float*, const float*, const float*,
+                               float*);
+__global__ void k_unroll_ustep_grad(int, long long, const float*, const float*, const float*, const float*,
+                                    const float*, const float*, float*, float*, float*, double*);
+__global__ void k_unroll_dot(long long, const float*, const float*, double*);
+__global__ void k_unroll_xseg(int, const int*, const float*, const float*, const float*, const float*, float, int,
+                              float*);
+__global__ void k_unroll_xseg_grad(int, int, const int*, const float*, const float*, const float*, const float*,
+                                   const float*, float, int, float*, float*, float*, double*);
+__global__ void k_unroll_xavg(int, long long, const float*, const float*, const float*, float*);
+__global__ void k_unroll_xavg_grad(int, long long, const float*, const float*, const float*, float*, float*,
+                                   double*);
+__global__ void k_unroll_dual(int, long long, const float*, const float*, const float*, const float*, float*);
+__global__ void k_unroll_dual_grad(int, long long, const float*, const float*, const float*, const float*, float*,
+                                   float*, float*, double*);
+__global__ void k_unroll_finish(int, const double*, int, const double*, int, const float*, float*);
+__global__ void k_axpby(long long, float, const float*, float, const float*, float*);
 }  // namespace tomo
 
 using namespace tomo;
@@ -371,6 +389,7 @@ struct tomo_ctx {
   DevBuf pbbase;                                 // standalone projector: region bin bases
   DevBuf km_work;                                // standalone K-means workspace
   DevBuf dct_part;                               // standalone DCT codec: range partials
+  DevBuf unroll_part;                            // unrolled form: float64 partial sums
   DevBuf ctr_resid;                              // residual of tomo_ctr_gd
   DevBuf ecode_off;                              // block offsets of tomo_dct_encode
   std::vector<std::unique_ptr<LocalPlan>> lplans;
@@ -1203,8 +1222,8 @@ int tomo_release(tomo_ctx* ctx) {
   ctx->rplans.clear();
   ctx->lindex.clear();
   ctx->cindex.clear();
-  for (DevBuf* b : {&ctx->partial, &ctx->pbbase, &ctx->km_work, &ctx->dct_part, &ctx->ctr_resid, &ctx->ecode_off,
-                    &ctx->btable, &ctx->bpartial, &ctx->bbbase})
+  for (DevBuf* b : {&ctx->partial, &ctx->pbbase, &ctx->km_work, &ctx->dct_part, &ctx->unroll_part, &ctx->ctr_resid,
+                    &ctx->ecode_off, &ctx->btable, &ctx->bpartial, &ctx->bbbase})
     b->release();
   return TOMO_OK;
 }
@@ -1576,6 +1595,130 @@ int tomo_sqdiff(tomo_ctx* ctx, const float* a, const float* b, int64_t n, double
   if (int rc = set_device(ctx)) return rc;
   hipLaunchKernelGGL(k_sqdiff, dim3(1), dim3(1024), 0, (hipStream_t)stream, a, b, (long long)n, out);
   return launch_status(ctx, "tomo_sqdiff");
+}
+
+
+// ---------------------------------------------------------------------------
+// Unrolled (differentiable) ADMM: elementwise steps and their gradients
+// ---------------------------------------------------------------------------
+static constexpr int kUnrollThreads = 256;
+static constexpr int kUnrollMaxWgs = 2048;     // workgroups of a reducing launch (one partial each)
+
+static int unroll_wgs(long long items) {
+  return (int)std::max(1LL, std::min<long long>(kUnrollMaxWgs, (items + kUnrollThreads - 1) / kUnrollThreads));
+}
+
+static int unroll_check(tomo_ctx* ctx, int32_t m, int64_t npix, std::initializer_list<const void*> ptrs) {
+  if (!ctx) return TOMO_EINVAL;
+  if (m < 1 || npix < 1 || (long long)m * npix >= (1ll << 40)) return ctx->fail(TOMO_EINVAL, "bad sizes");
+  for (const void* p : ptrs)
+    if (!p) return ctx->fail(TOMO_EINVAL, "null pointer");
+  return set_device(ctx);
+}
+
+// two blocks of partials (u-step: A and B), each kUnrollMaxWgs * 3 doubles
+static double* unroll_parts(tomo_ctx* ctx) {
+  if (!ctx->unroll_part.ensure((size_t)2 * kUnrollMaxWgs * 3 * sizeof(double))) return nullptr;
+  return static_cast<double*>(ctx->unroll_part.p);
+}
+
+int tomo_axpby(tomo_ctx* ctx, int64_t n, float alpha, const float* a, float beta, const float* b, float* out,
+               void* stream) {
+  if (int rc = unroll_check(ctx, 1, n, {a, b, out})) return rc;
+  hipLaunchKernelGGL(k_axpby, dim3(unroll_wgs(n)), dim3(kUnrollThreads), 0, (hipStream_t)stream, (long long)n, alpha,
+                     a, beta, b, out);
+  return launch_status(ctx, "tomo_axpby");
+}
+
+int tomo_unroll_ustep(tomo_ctx* ctx, int32_t m, int64_t npix, const float* U, const float* B, const float* x,
+                      const float* L, const float* scal, float* Uo, void* stream) {
+  if (int rc = unroll_check(ctx, m, npix, {U, B, x, L, scal, Uo})) return rc;
+  hipLaunchKernelGGL(k_unroll_ustep, dim3(unroll_wgs((long long)m * npix)), dim3(kUnrollThreads), 0,
+                     (hipStream_t)stream, m, (long long)npix, U, B, x, L, scal, Uo);
+  return launch_status(ctx, "tomo_unroll_ustep");
+}
+
+int tomo_unroll_ustep_grad(tomo_ctx* ctx, int32_t m, int64_t npix, const float* G, const float* PtPG, const float* PG,
+                           const float* R, int64_t nsino, const float* U, const float* x, const float* L,
+                           const float* scal, float* dU, float* dL, float* dx, float* dscal, void* stream) {
+  if (int rc = unroll_check(ctx, m, npix, {G, PtPG, PG, R, U, x, L, scal, dU, dL, dx, dscal})) return rc;
+  if (nsino < 1) return ctx->fail(TOMO_EINVAL, "bad sinogram size");
+  double* part = unroll_parts(ctx);
+  if (!part) return ctx->fail(TOMO_ENOMEM, "workspace");
+  hipStream_t s = (hipStream_t)stream;
+  const int na = unroll_wgs(npix), nb = unroll_wgs(nsino);
+  hipLaunchKernelGGL(k_unroll_ustep_grad, dim3(na), dim3(kUnrollThreads), 0, s, m, (long long)npix, G, PtPG, U, x, L,
+                     scal, dU, dL, dx, part);
+  hipLaunchKernelGGL(k_unroll_dot, dim3(nb), dim3(kUnrollThreads), 0, s, (long long)nsino, PG, R,
+                     part + 3 * kUnrollMaxWgs);
+  hipLaunchKernelGGL(k_unroll_finish, dim3(1), dim3(64), 0, s, 0, part, na, part + 3 * kUnrollMaxWgs, nb, scal, dscal);
+  return launch_status(ctx, "tomo_unroll_ustep_grad");
+}
+
+int tomo_unroll_xseg(tomo_ctx* ctx, int32_t m, int32_t n, const int32_t* owner, const float* U, const float* L,
+                     const float* x, const float* scal, float eta2, int32_t e2, float* xo, void* stream) {
+  if (int rc = unroll_check(ctx, m, (int64_t)n * n, {owner, U, L, x, scal, xo})) return rc;
+  if (e2 < 0) return ctx->fail(TOMO_EINVAL, "E2 < 0");
+  hipLaunchKernelGGL(k_unroll_xseg, dim3(unroll_wgs((long long)n * n)), dim3(kUnrollThreads), 0, (hipStream_t)stream,
+                     n, owner, U, L, x, scal, eta2, e2, xo);
+  return launch_status(ctx, "tomo_unroll_xseg");
+}
+
+int tomo_unroll_xseg_grad(tomo_ctx* ctx, int32_t m, int32_t n, const int32_t* owner, const float* G, const float* U,
+                          const float* L, const float* x, const float* scal, float eta2, int32_t e2, float* dU,
+                          float* dL, float* dx, float* dscal, void* stream) {
+  if (int rc = unroll_check(ctx, m, (int64_t)n * n, {owner, G, U, L, x, scal, dU, dL, dx, dscal})) return rc;
+  if (e2 < 0) return ctx->fail(TOMO_EINVAL, "E2 < 0");
+  double* part = unroll_parts(ctx);
+  if (!part) return ctx->fail(TOMO_ENOMEM, "workspace");
+  hipStream_t s = (hipStream_t)stream;
+  const int na = unroll_wgs((long long)n * n);
+  hipLaunchKernelGGL(k_unroll_xseg_grad, dim3(na), dim3(kUnrollThreads), 0, s, m, n, owner, G, U, L, x, scal, eta2, e2,
+                     dU, dL, dx, part);
+  hipLaunchKernelGGL(k_unroll_finish, dim3(1), dim3(64), 0, s, 1, part, na, part, 0, scal, dscal);
+  return launch_status(ctx, "tomo_unroll_xseg_grad");
+}
+
+int tomo_unroll_xavg(tomo_ctx* ctx, int32_t m, int64_t npix, const float* U, const float* L, const float* scal,
+                     float* xo, void* stream) {
+  if (int rc = unroll_check(ctx, m, npix, {U, L, scal, xo})) return rc;
+  hipLaunchKernelGGL(k_unroll_xavg, dim3(unroll_wgs(npix)), dim3(kUnrollThreads), 0, (hipStream_t)stream, m,
+                     (long long)npix, U, L, scal, xo);
+  return launch_status(ctx, "tomo_unroll_xavg");
+}
+
+int tomo_unroll_xavg_grad(tomo_ctx* ctx, int32_t m, int64_t npix, const float* G, const float* L, const float* scal,
+                          float* dU, float* dL, float* dscal, void* stream) {
+  if (int rc = unroll_check(ctx, m, npix, {G, L, scal, dU, dL, dscal})) return rc;
+  double* part = unroll_parts(ctx);
+  if (!part) return ctx->fail(TOMO_ENOMEM, "workspace");
+  hipStream_t s = (hipStream_t)stream;
+  const int na = unroll_wgs(npix);
+  hipLaunchKernelGGL(k_unroll_xavg_grad, dim3(na), dim3(kUnrollThreads), 0, s, m, (long long)npix, G, L, scal, dU, dL,
+                     part);
+  hipLaunchKernelGGL(k_unroll_finish, dim3(1), dim3(64), 0, s, 1, part, na, part, 0, scal, dscal);
+  return launch_status(ctx, "tomo_unroll_xavg_grad");
+}
+
+int tomo_unroll_dual(tomo_ctx* ctx, int32_t m, int64_t npix, const float* L, const float* U, const float* xn,
+                     const float* scal, float* Lo, void* stream) {
+  if (int rc = unroll_check(ctx, m, npix, {L, U, xn, scal, Lo})) return rc;
+  hipLaunchKernelGGL(k_unroll_dual, dim3(unroll_wgs((long long)m * npix)), dim3(kUnrollThreads), 0,
+                     (hipStream_t)stream, m, (long long)npix, L, U, xn, scal, Lo);
+  return launch_status(ctx, "tomo_unroll_dual");
+}
+
+int tomo_unroll_dual_grad(tomo_ctx* ctx, int32_t m, int64_t npix, const float* G, const float* U, const float* xn,
+                          const float* scal, float* dL, float* dU, float* dxn, float* dscal, void* stream) {
+  if (int rc = unroll_check(ctx, m, npix, {G, U, xn, scal, dL, dU, dxn, dscal})) return rc;
+  double* part = unroll_parts(ctx);
+  if (!part) return ctx->fail(TOMO_ENOMEM, "workspace");
+  hipStream_t s = (hipStream_t)stream;
+  const int na = unroll_wgs(npix);
+  hipLaunchKernelGGL(k_unroll_dual_grad, dim3(na), dim3(kUnrollThreads), 0, s, m, (long long)npix, G, U, xn, scal, dL,
+                     dU, dxn, part);
+  hipLaunchKernelGGL(k_unroll_finish, dim3(1), dim3(64), 0, s, 1, part, na, part, 0, scal, dscal);
+  return launch_status(ctx, "tomo_unroll_dual_grad");
 }
 
 }  // extern "C"

@@ -31,7 +31,9 @@ EXPORTED = ("tomo_create", "tomo_destroy", "tomo_status_string", "tomo_last_erro
             "tomo_backproject", "tomo_project_many", "tomo_backproject_many", "tomo_ctr_gd", "admm_local_update", "admm_local_phase", "admm_consensus",
             "admm_reg_update", "admm_consensus_reg",
             "quantize_kmeans", "quantize_dct", "quantize_dct_noalloc", "tomo_pack_labels", "tomo_unpack_labels",
-            "tomo_dct_encode_words", "tomo_dct_encode", "tomo_dct_decode", "tomo_sqdiff")
+            "tomo_dct_encode_words", "tomo_dct_encode", "tomo_dct_decode", "tomo_sqdiff",
+            "tomo_axpby", "tomo_unroll_ustep", "tomo_unroll_ustep_grad", "tomo_unroll_xseg", "tomo_unroll_xseg_grad",
+            "tomo_unroll_xavg", "tomo_unroll_xavg_grad", "tomo_unroll_dual", "tomo_unroll_dual_grad")
 
 
 class TomoError(RuntimeError):
@@ -112,6 +114,16 @@ _lib.tomo_dct_encode.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.
 _lib.tomo_dct_decode.argtypes = [_P, _P, ctypes.c_int64, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P,
                                  _P, _P]
 _lib.tomo_unpack_labels.argtypes = [_P, _P, ctypes.c_int64, ctypes.c_int32, _P, ctypes.c_int32, _P, _P, _P]
+_I32, _I64, _F32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float
+_lib.tomo_axpby.argtypes = [_P, _I64, _F32, _P, _F32, _P, _P, _P]
+_lib.tomo_unroll_ustep.argtypes = [_P, _I32, _I64, _P, _P, _P, _P, _P, _P, _P]
+_lib.tomo_unroll_ustep_grad.argtypes = [_P, _I32, _I64, _P, _P, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P]
+_lib.tomo_unroll_xseg.argtypes = [_P, _I32, _I32, _P, _P, _P, _P, _P, _F32, _I32, _P, _P]
+_lib.tomo_unroll_xseg_grad.argtypes = [_P, _I32, _I32, _P, _P, _P, _P, _P, _P, _F32, _I32, _P, _P, _P, _P, _P]
+_lib.tomo_unroll_xavg.argtypes = [_P, _I32, _I64, _P, _P, _P, _P, _P]
+_lib.tomo_unroll_xavg_grad.argtypes = [_P, _I32, _I64, _P, _P, _P, _P, _P, _P, _P]
+_lib.tomo_unroll_dual.argtypes = [_P, _I32, _I64, _P, _P, _P, _P, _P, _P]
+_lib.tomo_unroll_dual_grad.argtypes = [_P, _I32, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P]
 
 
 def _stream(stream=None):
@@ -437,3 +449,112 @@ def make_msgs(entries):
             t = e.get(key)
             setattr(arr[i], key, None if t is None else _dev(t, dt, key).value)
     return arr
+
+
+# ---------------------------------------------------------------------------
+# unrolled (differentiable) ADMM: elementwise steps and their gradients.  The
+# nodes' images are stacked [M][n][n]; x is [n][n]; scal is a float32 [2]
+# device tensor (rho, eta).  Every call returns freshly allocated outputs.
+# ---------------------------------------------------------------------------
+def _f32(t, name, shape=None):
+    return _dev(t, torch.float32, name, shape)
+
+
+def _stack_dims(U):
+    if U.dim() != 3 or U.shape[1] != U.shape[2]:
+        raise ValueError("stacked images must be [M][n][n]")
+    return U.shape[0], U.shape[1]
+
+
+def tomo_axpby(ctx: Context, alpha: float, a, beta: float, b, out=None, stream=None):
+    if out is None:
+        out = torch.empty_like(a)
+    rc = _lib.tomo_axpby(ctx.handle, a.numel(), float(alpha), _f32(a, "a"), float(beta), _f32(b, "b", a.shape),
+                         _f32(out, "out", a.shape), _stream(stream))
+    ctx.check(rc, "tomo_axpby")
+    return out
+
+
+def tomo_unroll_ustep(ctx: Context, U, B, x, L, scal, stream=None):
+    m, n = _stack_dims(U)
+    Uo = torch.empty_like(U)
+    rc = _lib.tomo_unroll_ustep(ctx.handle, m, n * n, _f32(U, "U"), _f32(B, "B", U.shape), _f32(x, "x", (n, n)),
+                                _f32(L, "L", U.shape), _f32(scal, "scal", (2,)), _f32(Uo, "Uo"), _stream(stream))
+    ctx.check(rc, "tomo_unroll_ustep")
+    return Uo
+
+
+def tomo_unroll_ustep_grad(ctx: Context, G, PtPG, PG, R, U, x, L, scal, stream=None):
+    m, n = _stack_dims(U)
+    dU, dL = torch.empty_like(U), torch.empty_like(U)
+    dx = torch.empty_like(x)
+    ds = torch.empty(2, dtype=torch.float32, device=U.device)
+    rc = _lib.tomo_unroll_ustep_grad(ctx.handle, m, n * n, _f32(G, "G", U.shape), _f32(PtPG, "PtPG", U.shape),
+                                     _f32(PG, "PG"), _f32(R, "R", PG.shape), PG.numel(), _f32(U, "U"),
+                                     _f32(x, "x", (n, n)), _f32(L, "L", U.shape), _f32(scal, "scal", (2,)),
+                                     _f32(dU, "dU"), _f32(dL, "dL"), _f32(dx, "dx"), _f32(ds, "dscal"), _stream(stream))
+    ctx.check(rc, "tomo_unroll_ustep_grad")
+    return dU, dL, dx, ds
+
+
+def tomo_unroll_xseg(ctx: Context, owner, U, L, x, scal, eta2: float, e2: int, stream=None):
+    m, n = _stack_dims(U)
+    xo = torch.empty_like(x)
+    rc = _lib.tomo_unroll_xseg(ctx.handle, m, n, _dev(owner, torch.int32, "owner", (n,)), _f32(U, "U"),
+                               _f32(L, "L", U.shape), _f32(x, "x", (n, n)), _f32(scal, "scal", (2,)), float(eta2),
+                               int(e2), _f32(xo, "xo"), _stream(stream))
+    ctx.check(rc, "tomo_unroll_xseg")
+    return xo
+
+
+def tomo_unroll_xseg_grad(ctx: Context, owner, G, U, L, x, scal, eta2: float, e2: int, stream=None):
+    m, n = _stack_dims(U)
+    dU, dL = torch.empty_like(U), torch.empty_like(U)
+    dx = torch.empty_like(x)
+    ds = torch.empty(2, dtype=torch.float32, device=U.device)
+    rc = _lib.tomo_unroll_xseg_grad(ctx.handle, m, n, _dev(owner, torch.int32, "owner", (n,)), _f32(G, "G", (n, n)),
+                                    _f32(U, "U"), _f32(L, "L", U.shape), _f32(x, "x", (n, n)),
+                                    _f32(scal, "scal", (2,)), float(eta2), int(e2), _f32(dU, "dU"), _f32(dL, "dL"),
+                                    _f32(dx, "dx"), _f32(ds, "dscal"), _stream(stream))
+    ctx.check(rc, "tomo_unroll_xseg_grad")
+    return dU, dL, dx, ds
+
+
+def tomo_unroll_xavg(ctx: Context, U, L, scal, stream=None):
+    m, n = _stack_dims(U)
+    xo = torch.empty((n, n), dtype=torch.float32, device=U.device)
+    rc = _lib.tomo_unroll_xavg(ctx.handle, m, n * n, _f32(U, "U"), _f32(L, "L", U.shape), _f32(scal, "scal", (2,)),
+                               _f32(xo, "xo"), _stream(stream))
+    ctx.check(rc, "tomo_unroll_xavg")
+    return xo
+
+
+def tomo_unroll_xavg_grad(ctx: Context, G, L, scal, stream=None):
+    m, n = _stack_dims(L)
+    dU, dL = torch.empty_like(L), torch.empty_like(L)
+    ds = torch.empty(2, dtype=torch.float32, device=L.device)
+    rc = _lib.tomo_unroll_xavg_grad(ctx.handle, m, n * n, _f32(G, "G", (n, n)), _f32(L, "L"), _f32(scal, "scal", (2,)),
+                                    _f32(dU, "dU"), _f32(dL, "dL"), _f32(ds, "dscal"), _stream(stream))
+    ctx.check(rc, "tomo_unroll_xavg_grad")
+    return dU, dL, ds
+
+
+def tomo_unroll_dual(ctx: Context, L, U, xn, scal, stream=None):
+    m, n = _stack_dims(U)
+    Lo = torch.empty_like(L)
+    rc = _lib.tomo_unroll_dual(ctx.handle, m, n * n, _f32(L, "L", U.shape), _f32(U, "U"), _f32(xn, "xn", (n, n)),
+                               _f32(scal, "scal", (2,)), _f32(Lo, "Lo"), _stream(stream))
+    ctx.check(rc, "tomo_unroll_dual")
+    return Lo
+
+
+def tomo_unroll_dual_grad(ctx: Context, G, U, xn, scal, stream=None):
+    m, n = _stack_dims(U)
+    dL, dU = torch.empty_like(U), torch.empty_like(U)
+    dxn = torch.empty_like(xn)
+    ds = torch.empty(2, dtype=torch.float32, device=U.device)
+    rc = _lib.tomo_unroll_dual_grad(ctx.handle, m, n * n, _f32(G, "G", U.shape), _f32(U, "U"), _f32(xn, "xn", (n, n)),
+                                    _f32(scal, "scal", (2,)), _f32(dL, "dL"), _f32(dU, "dU"), _f32(dxn, "dxn"),
+                                    _f32(ds, "dscal"), _stream(stream))
+    ctx.check(rc, "tomo_unroll_dual_grad")
+    return dL, dU, dxn, ds

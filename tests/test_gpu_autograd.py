@@ -241,3 +241,69 @@ def test_project_many_mixed_geometries_equal_single_calls(mods, model):
     bad[1]["image"] = to_dev(rng.random((64, 64)).astype(np.float32))
     with pytest.raises(T.TomoError):              # both items write the same sinogram
         T.tomo_project_many(c, T.make_items(bad))
+
+
+def test_unrolled_step_functions_match_float64_autograd(mods, tctx):
+    """The HIP forward and backward of LocalStep (Alg. 2), XSegment (Alg. 3),
+    XAverage (Eq. 9) and Dual (Eq. 24) against float64 torch autograd on the CPU
+    with the oracle's dense Joseph matrices: outputs to 1e-5 and the gradients of
+    a random linear functional of all four outputs with respect to U, x, L and
+    (rho, eta) to 1e-4 (rel-L2)."""
+    T, AG = mods
+    rng = np.random.default_rng(21)
+    M, n, nb, K = 3, 16, 23, 30
+    th = synthdata.angles(K)
+    parts = synthdata.partition_angles(K, M, "interleaved")
+    segs = synthdata.segment_rows(n, M)
+    owner = np.concatenate([np.full(r, m) for m, (_, r) in enumerate(segs)]).astype(np.int32)
+    U = rng.standard_normal((M, n, n)).astype(np.float32)
+    L = (0.3 * rng.standard_normal((M, n, n))).astype(np.float32)
+    x = rng.standard_normal((n, n)).astype(np.float32)
+    D = rng.standard_normal((K, nb)).astype(np.float32)
+    Dst = np.concatenate([D[p] for p in parts]).astype(np.float32)
+    sc = np.array([1.3, 0.004], np.float32)
+    W = [rng.standard_normal(s).astype(np.float32) for s in ((M, n, n), (n, n), (M, n, n), (n, n))]
+    eta2, e2 = 0.2, 7
+
+    def functional(Uo, xs, Lo, xa, Wt):
+        return (Uo * Wt[0]).sum() + (xs * Wt[1]).sum() + (Lo * Wt[2]).sum() + (xa * Wt[3]).sum()
+
+    # GPU
+    angs = [to_dev(th[p], torch.float64) for p in parts]
+    Ug, xg, Lg = (to_dev(a).requires_grad_(True) for a in (U, x, L))
+    sg = to_dev(sc).requires_grad_(True)
+    Uo = AG.LocalStep.apply(Ug, xg, Lg, sg, to_dev(Dst), tctx, angs, nb)
+    xs = AG.XSegment.apply(Uo, Lg, xg, sg, to_dev(owner, torch.int32), tctx, eta2, e2)
+    Lo = AG.Dual.apply(Lg, Uo, xs, sg, tctx)
+    xa = AG.XAverage.apply(Uo, Lg, sg, tctx)
+    functional(Uo, xs, Lo, xa, [to_dev(w) for w in W]).backward()
+    got_out = [t.detach().cpu().numpy() for t in (Uo, xs, Lo, xa)]
+    got_grad = [t.grad.cpu().numpy() for t in (Ug, xg, Lg, sg)]
+
+    # float64 reference with dense matrices
+    f64 = lambda a: torch.from_numpy(a.astype(np.float64))
+    Ur, xr, Lr, sr = (f64(a).requires_grad_(True) for a in (U, x, L, sc))
+    rho, eta = sr[0], sr[1]
+    ups = []
+    for m, p in enumerate(parts):
+        A = f64(joseph.dense_matrix(n, nb, th[p]))
+        u = Ur[m].reshape(-1)
+        g = A.T @ (A @ u - f64(D[p]).reshape(-1)) + rho * (u - xr.reshape(-1)) + Lr[m].reshape(-1)
+        ups.append((u - eta * g).reshape(n, n))
+    Uor = torch.stack(ups)
+    own = torch.from_numpy(owner.astype(np.int64))
+    t = (Uor + Lr / rho)[own, torch.arange(n)]
+    xsr = xr
+    for _ in range(e2):
+        xsr = xsr - eta2 * rho * (xsr - t)
+    Lor = Lr + rho * (Uor - xsr)
+    xar = (Uor + Lr / rho).mean(dim=0)
+    functional(Uor, xsr, Lor, xar, [f64(w) for w in W]).backward()
+    ref_out = [t.detach().numpy() for t in (Uor, xsr, Lor, xar)]
+    ref_grad = [t.grad.numpy() for t in (Ur, xr, Lr, sr)]
+    for name, a, b in zip(("U'", "x seg", "L'", "x avg"), got_out, ref_out):
+        log(f"  forward {name}: rel {rel_l2(a, b):.2e}")
+        assert rel_l2(a, b) <= 1e-5
+    for name, a, b in zip(("dU", "dx", "dL", "d(rho, eta)"), got_grad, ref_grad):
+        log(f"  gradient {name}: rel {rel_l2(a, b):.2e}")
+        assert rel_l2(a, b) <= 1e-4
