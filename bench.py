@@ -277,20 +277,35 @@ def bench_diff(args, steps, ctx, log):
                             eta0=0.1 / (L + 1.0), ckpt=2).cuda()
     opt = torch.optim.Adam(model.parameters(), lr=0.05)
 
+    from concurrent.futures import ThreadPoolExecutor
+
+    n_pairs = args.pairs if args.pairs else steps + 1
+    # phantoms are drawn on host threads ahead of the steps that use them
+    gen = ThreadPoolExecutor(max_workers=8)
+    phantoms = [gen.submit(synthdata.phantom, w, i) for i in range(n_pairs)]
+
     def pair(i):
-        truth = synthdata.phantom(w, i)
+        truth = phantoms[i].result()
         t = torch.from_numpy(truth.astype(np.float32)).cuda()
         clean = T.tomo_project(ctx, ang_all, t, nb).cpu().numpy()
         d = synthdata.add_gaussian_noise(clean, w.noise_level, synthdata.sinogram_seed(w, i))
         dd = torch.from_numpy(np.ascontiguousarray(d, dtype=np.float32)).cuda()
         return t, [dd[torch.from_numpy(p).cuda()].contiguous() for p in parts]
 
-    data = [pair(i) for i in range(steps + 1)]
+    data = {}
+
+    def get(i):
+        k = i % n_pairs
+        if k not in data:
+            data[k] = pair(k)
+        return data[k]
+
+    get(0)
     setup_s = time.perf_counter() - t_setup
     log(f"setup: {n}^2, {w.n_angles} angles, {w.n_nodes} nodes, {iters} unrolled iterations, {setup_s:.1f} s")
 
     def train_step(i):
-        tgt, ds = data[i]
+        tgt, ds = get(i)
         opt.zero_grad()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -312,11 +327,14 @@ def bench_diff(args, steps, ctx, log):
         losses.append(lv)
         fw.append(f)
         bw.append(b)
-        log(f"step {i}: loss {lv:.6g}, forward {f * 1e3:.0f} ms, backward + Adam {b * 1e3:.0f} ms")
+        if steps <= 20 or i % 32 == 0 or i == steps:
+            log(f"step {i}: loss {lv:.6g}, forward {f * 1e3:.0f} ms, backward + Adam {b * 1e3:.0f} ms")
     wall = time.perf_counter() - t0
     fwd_updates = iters * e1 * 2 * w.n_angles * n * n       # P and P^T in the forward unroll
     upd_step = 3 * fwd_updates                               # forward, recomputation, backward
-    ms = wall * 1e3 / steps
+    # the training steps themselves (forward, backward, Adam), without the data
+    # synthesis of pairs first used in this run
+    ms = float(np.sum(fw) + np.sum(bw)) * 1e3 / steps
     out = {
         "metric": "proj+backproj ray-voxel updates/s; ADMM iter/s batched vs plain @ equal RMSE",
         "value": upd_step / (ms * 1e-3), "unit": "updates/s", "n_gpus": 1, "steps": steps, "warmup": 1,
@@ -327,7 +345,8 @@ def bench_diff(args, steps, ctx, log):
                                "no quantizer), E1=5, E2=10, learnable rho_k and eta_k (20 scalars), Adam lr 0.05, "
                                "checkpoint every 2 iterations", "n": n, "angles": w.n_angles, "bins": nb,
                    "nodes": w.n_nodes, "unrolled_iterations": iters},
-        "training": {"losses": losses, "forward_ms": float(np.mean(fw)) * 1e3,
+        "training": {"pairs": n_pairs, "losses": losses, "forward_ms": float(np.mean(fw)) * 1e3,
+                     "step_ms_median": float(np.median(np.array(fw) + np.array(bw))) * 1e3,
                      "backward_adam_ms": float(np.mean(bw)) * 1e3,
                      "backward_over_forward": float(np.mean(bw) / np.mean(fw)),
                      "updates_per_step": upd_step, "forward_updates": fwd_updates,
@@ -360,6 +379,9 @@ def main():
     ap.add_argument("--reg-mu", type=float, default=0.02)
     ap.add_argument("--reg-iters", type=int, default=10, help="Chambolle iterations per z-update (TV)")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--pairs", type=int, default=None,
+                    help="differentiation workload: seeded phantom/sinogram pairs the steps cycle through "
+                         "(default: one per step)")
     ap.add_argument("--no-batch-line", action="store_true",
                     help="skip the batching workload's batched-vs-plain comparison of the default run")
     ap.add_argument("--profile-kernels", action="store_true",

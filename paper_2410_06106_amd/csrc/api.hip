@@ -22,8 +22,8 @@ template <class Src> __global__ void k_project_res_reduce(Src);
 template <class Src, bool CHORD> __global__ void k_backproject(Src);
 __global__ void k_seg_none(const SegJob*, int, int);
 template <bool REG, bool TZ> __global__ void k_kmeans(const KMJob*, KMJob, int, int, int, const KMBlock*);
-__global__ void k_dct_range(const SegJob*, int, SegJob, int, int);
-__global__ void k_dct_code(const SegJob*, int, SegJob, int);
+__global__ void k_dct_range(const SegJob*, int, int, SegJob, int, int);
+__global__ void k_dct_code(const SegJob*, int, int, SegJob, int);
 __global__ void k_avg(Many<AvgJob>, const NodeRef*);
 __global__ void k_dual(Many<NodeRef>);
 __global__ void k_reg_step(Many<RegJob>, int);
@@ -343,6 +343,7 @@ struct ConsPlan {
   std::vector<tomo_reg> reg_key;
   DevBuf seg, avg, noderefs, labels, kmjobs, kmwork, kmblocks, dctpart;
   int dct_range_wgs = 0, dct_code_wgs = 0;   // DCT codec launches
+  int dct_range_uni = 0, dct_code_uni = 0;   // workgroups of every job, when all jobs have the same (else 0)
   int n_seg = 0, n_avg = 0, avg_wgs = 0, dual_wgs = 0;
   bool any_xt = false;   // some message asks for the segment before Q
   int n_refs = 0;                 // dual-update entries: the nodes, then the regularization blocks
@@ -1051,6 +1052,12 @@ ConsPlan* get_cons_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, cons
       work_elems += (size_t)(segn + 63) / 64 * 64;
     }
   }
+  plan->dct_range_uni = seg.empty() ? 0 : seg[0].n_chunks;
+  plan->dct_code_uni = seg.empty() ? 0 : dct_code_wgs(seg[0].rows, seg[0].n);
+  for (const auto& j : seg) {
+    if (j.n_chunks != plan->dct_range_uni) plan->dct_range_uni = 0;
+    if (dct_code_wgs(j.rows, j.n) != plan->dct_code_uni) plan->dct_code_uni = 0;
+  }
   if (!plan->dctpart.ensure((size_t)plan->dct_range_wgs * sizeof(float4))) {
     rc = ctx->fail(TOMO_ENOMEM, "consensus plan allocation failed");
     return nullptr;
@@ -1399,10 +1406,10 @@ int admm_consensus_reg(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, i
                          dim3(kKmThreads), 0, s, kj + plan->km_small, KMJob{}, q->levels, q->max_iter, ex,
                          kb ? kb + plan->km_small : nullptr);
   } else if (kind == TOMO_QUANT_DCT) {
-    hipLaunchKernelGGL(k_dct_range, dim3(plan->dct_range_wgs), dim3(DCT_THREADS), 0, s, seg, plan->n_seg, SegJob{},
-                       do_x, e2);
-    hipLaunchKernelGGL(k_dct_code, dim3(plan->dct_code_wgs), dim3(DCT_THREADS), 0, s, seg, plan->n_seg, SegJob{},
-                       q->quality);
+    hipLaunchKernelGGL(k_dct_range, dim3(plan->dct_range_wgs), dim3(DCT_THREADS), 0, s, seg, plan->n_seg,
+                       plan->dct_range_uni, SegJob{}, do_x, e2);
+    hipLaunchKernelGGL(k_dct_code, dim3(plan->dct_code_wgs), dim3(DCT_THREADS), 0, s, seg, plan->n_seg,
+                       plan->dct_code_uni, SegJob{}, q->quality);
   } else if (do_x || plan->any_xt) {
     hipLaunchKernelGGL(k_seg_none, dim3(plan->n_seg), dim3(256), 0, s, seg, do_x, e2);
   }
@@ -1489,8 +1496,8 @@ static int dct_codec(tomo_ctx* ctx, const float* a, int32_t rows, int32_t cols, 
   }
   j.part = part;
   hipStream_t s = (hipStream_t)stream;
-  hipLaunchKernelGGL(k_dct_range, dim3(j.n_chunks), dim3(DCT_THREADS), 0, s, nullptr, 1, j, 0, 0);
-  hipLaunchKernelGGL(k_dct_code, dim3(dct_code_wgs(rows, cols)), dim3(DCT_THREADS), 0, s, nullptr, 1, j, quality);
+  hipLaunchKernelGGL(k_dct_range, dim3(j.n_chunks), dim3(DCT_THREADS), 0, s, nullptr, 1, 0, j, 0, 0);
+  hipLaunchKernelGGL(k_dct_code, dim3(dct_code_wgs(rows, cols)), dim3(DCT_THREADS), 0, s, nullptr, 1, 0, j, quality);
   return launch_status(ctx, what);
 }
 

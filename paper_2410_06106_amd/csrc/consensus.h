@@ -42,7 +42,7 @@ struct SegJob {
 // workgroups; the coding launch gives each workgroup a strip of 16 rows x
 // DCT_STRIP columns (a 16 x 64 sub-strip per wave).
 constexpr int DCT_THREADS = 256;
-constexpr int DCT_CHUNK = 2048;
+constexpr int DCT_CHUNK = 4096;
 constexpr int DCT_MAX_CHUNKS = 64;
 constexpr int DCT_STRIP = 256;
 __host__ __device__ inline int dct_chunk_rows(int rows, int cols) {

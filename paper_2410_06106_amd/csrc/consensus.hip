@@ -1,11 +1,11 @@
 // Consensus, exchange and dual steps of decentralized ADMM (gfx950):
 //   Alg. 3   segment x-update, E2 gradient steps on rho/2 ||u - x + lambda/rho||^2
 //   Eq. 9    averaging x-update x = mean_m (u_m + lambda_m / rho)
-//   JPEG-style quantizer: 8x8 DCT-II on MFMA, table quantization, inverse DCT
+//   Sec. 2.7 JPEG-style quantizer: 8x8 DCT-II on MFMA, table quantization, inverse DCT
 //   Eq. 24   dual update lambda_m += rho (u_m - x)
-// One workgroup owns one segment for the x-update and the DCT quantizer, so a
-// segment's level-map range never leaves the workgroup.  (The K-means quantizer
-// lives in kmeans.hip.)
+// The x-update without a quantizer runs one workgroup per segment; with the DCT
+// quantizer it is fused into the first of the codec's two many-workgroup
+// launches.  (The K-means quantizer lives in kmeans.hip.)
 #include "consensus.h"
 
 namespace tomo {
@@ -68,10 +68,10 @@ __device__ void segment_xupdate(const SegJob& S, int e2, float* xt) {
 // k_dct_code: each workgroup reduces its segment's partials (at most 64, one
 // per lane, so every wave does it without a barrier) and codes a strip of 16
 // rows.  A wave transforms one 16x16 tile = 2x2 blocks at a time with the
-// block-diagonal matrix C2 = diag(C, C): with the tile X held in the
+// block-diagonal matrix C2 = diag(C, C): with a matrix Y held in the
 // accumulator layout of v_mfma_f32_16x16x4_f32 (lane j + 16 g, register r holds
-// X[4g + r][j]) and passed as the A operand, one 4-instruction chain computes
-// X^T B; two chains give C2 V C2^T forward and C2^T F C2 inverse.
+// Y[4g + r][j]) and passed as the A operand, one 4-instruction chain computes
+// Y^T B; two chains transform a tile forward, two more back.
 //
 // Rounding ties: a code is round-half-even(F / step) of the float64 DCT
 // coefficient.  The float32 MFMA coefficient is within about 5e-4 of it (level
@@ -106,63 +106,185 @@ __device__ __forceinline__ f4 mfma_chain(const f4& X, const float* B) {
   return acc;
 }
 
-// the job owning workgroup bid of a launch, by the first-workgroup field F
-// (jobs == null: the launch has the one job `single`)
+// A copy of the job owning workgroup bid of a launch (jobs == null: the
+// launch has the one job `single`).  With uni > 0 every job spans uni
+// workgroups and the index is bid / uni; otherwise it is found by the
+// first-workgroup field F.  The table is read through the constant address
+// space (scalar loads), and a copy cannot alias the arrays the kernel writes.
 template <int SegJob::*F>
-__device__ __forceinline__ const SegJob* job_of(const SegJob* jobs, int n_jobs, const SegJob* single, int bid) {
+__device__ __forceinline__ SegJob job_of(const SegJob* jobs, int n_jobs, int uni, const SegJob& single, int bid) {
   if (!jobs) return single;
+  const auto J = (const __attribute__((address_space(4))) SegJob*)jobs;
   int lo = 0, hi = n_jobs - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (jobs[mid].*F <= bid) lo = mid; else hi = mid - 1;
+  if (uni > 0) {
+    lo = bid / uni;
+  } else {
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (J[mid].*F <= bid) lo = mid; else hi = mid - 1;
+    }
   }
-  return jobs + lo;
+  static_assert(sizeof(SegJob) % 4 == 0, "descriptor copied in 32-bit words");
+  SegJob r;
+  const auto w = (const __attribute__((address_space(4))) int*)(J + lo);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(SegJob) / 4); ++i) reinterpret_cast<int*>(&r)[i] = w[i];
+  return r;
 }
 
-__global__ __launch_bounds__(DCT_THREADS) void k_dct_range(const SegJob* jobs, int n_jobs, SegJob single, int do_x,
-                                                           int e2) {
+// global-address-space views (global loads and stores instead of flat ones)
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gas(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
+__global__ __launch_bounds__(DCT_THREADS) void k_dct_range(const SegJob* jobs, int n_jobs, int uni, SegJob single,
+                                                           int do_x, int e2) {
   __shared__ float red[2 * (DCT_THREADS / 64)];
   __shared__ int redb[DCT_THREADS / 64];
-  const SegJob& S = *job_of<&SegJob::range_wg>(jobs, n_jobs, &single, blockIdx.x);
+  const SegJob S = job_of<&SegJob::range_wg>(jobs, n_jobs, uni, single, blockIdx.x);
   const int chunk = blockIdx.x - S.range_wg;
   const int r0 = chunk * S.chunk_rows, r1 = min(S.rows, r0 + S.chunk_rows);
   const int tid = threadIdx.x;
   const float irho = 1.f / S.rho;
+  // row pieces of four values move as float4 when every array allows it
+  auto al16 = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15) == 0; };
+  const bool vec = (S.cols & 3) == 0 && (S.ld & 3) == 0 && al16(S.src) && (!S.xt || al16(S.xt)) &&
+                   (!do_x || (al16(S.x) && al16(S.u) && al16(S.lam) && (!S.tz || al16(S.tz)) && (S.n & 3) == 0));
   float lo = INFINITY, hi = -INFINITY;
   int bad = 0;
-  for (int r = r0; r < r1; ++r) {
-    for (int c = tid; c < S.cols; c += DCT_THREADS) {
-      float v;
-      if (do_x) {            // consensus: the segment of x, ld = cols = n
-        const size_t i = (size_t)(S.row0 + r) * S.n + c;
-        v = S.x[i];
-        const float tm = reg_target(S.u[i], S.lam[i], irho);
-        if (S.tz) {
-          const float tv = S.tz[i];
-          for (int e = 0; e < e2; ++e) v = xstep_reg(v, tm, tv, S.rho, S.rho_z, S.eta2);
+  auto update = [&](float v, size_t i) {   // Alg. 3 on value v of x at index i of the slice
+    const float tm = reg_target(S.u[i], S.lam[i], irho);
+    if (S.tz) {
+      const float tv = S.tz[i];
+      for (int e = 0; e < e2; ++e) v = xstep_reg(v, tm, tv, S.rho, S.rho_z, S.eta2);
+    } else {
+      for (int e = 0; e < e2; ++e) v = xstep(v, tm, S.rho, S.eta2);
+    }
+    return v;
+  };
+  auto fold = [&](float v) {
+    bad |= !isfinite(v);
+    lo = fminf(lo, v);
+    hi = fmaxf(hi, v);
+  };
+  if (vec) {
+    // the chunk's float4s, DCT_VEC per thread and pass, every load of a pass
+    // issued before any is used
+    constexpr int DCT_VEC = 4;
+    const int per_row = S.cols >> 2;
+    const int total = (r1 - r0) * per_row;
+    for (int base = 0; base < total; base += DCT_THREADS * DCT_VEC) {
+      f4 a[DCT_VEC], uu[DCT_VEC], ll[DCT_VEC], tt[DCT_VEC];
+      size_t ix[DCT_VEC];
+      bool ok[DCT_VEC];
+#pragma unroll
+      for (int q = 0; q < DCT_VEC; ++q) {
+        const int f = base + q * DCT_THREADS + tid;
+        ok[q] = f < total;
+        const int ff = ok[q] ? f : total - 1;
+        const int r = r0 + ff / per_row, c = 4 * (ff - (ff / per_row) * per_row);
+        if (do_x) {       // consensus: the segment of x, ld = cols = n
+          ix[q] = (size_t)(S.row0 + r) * S.n + c;
+          a[q] = *(const __attribute__((address_space(1))) f4*)gas(S.x + ix[q]);
+          uu[q] = *(const __attribute__((address_space(1))) f4*)gas(S.u + ix[q]);
+          ll[q] = *(const __attribute__((address_space(1))) f4*)gas(S.lam + ix[q]);
+          if (S.tz) tt[q] = *(const __attribute__((address_space(1))) f4*)gas(S.tz + ix[q]);
         } else {
-          for (int e = 0; e < e2; ++e) v = xstep(v, tm, S.rho, S.eta2);
+          ix[q] = (size_t)r * S.ld + c;
+          a[q] = *(const __attribute__((address_space(1))) f4*)gas(S.src + ix[q]);
         }
-        S.x[i] = v;
-      } else {
-        v = S.src[(size_t)r * S.ld + c];
       }
-      if (S.xt) S.xt[(size_t)r * S.cols + c] = v;
-      bad |= !isfinite(v);
-      lo = fminf(lo, v);
-      hi = fmaxf(hi, v);
+#pragma unroll
+      for (int q = 0; q < DCT_VEC; ++q) {
+        if (do_x) {
+          float* v = reinterpret_cast<float*>(&a[q]);
+          const float* uv = reinterpret_cast<const float*>(&uu[q]);
+          const float* lv = reinterpret_cast<const float*>(&ll[q]);
+          const float* tv = reinterpret_cast<const float*>(&tt[q]);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const float tm = reg_target(uv[c], lv[c], irho);
+            if (S.tz) {
+              for (int e = 0; e < e2; ++e) v[c] = xstep_reg(v[c], tm, tv[c], S.rho, S.rho_z, S.eta2);
+            } else {
+              for (int e = 0; e < e2; ++e) v[c] = xstep(v[c], tm, S.rho, S.eta2);
+            }
+          }
+          if (ok[q]) *(__attribute__((address_space(1))) f4*)gas(S.x + ix[q]) = a[q];
+        }
+        if (ok[q]) {
+          if (S.xt) {
+            const int f = base + q * DCT_THREADS + tid;
+            *(__attribute__((address_space(1))) f4*)gas(S.xt + (size_t)(r0 + f / per_row) * S.cols +
+                                                      4 * (f - (f / per_row) * per_row)) = a[q];
+          }
+          fold(a[q][0]);
+          fold(a[q][1]);
+          fold(a[q][2]);
+          fold(a[q][3]);
+        }
+      }
+    }
+  } else {
+    for (int r = r0; r < r1; ++r) {
+      for (int c = tid; c < S.cols; c += DCT_THREADS) {
+        float v;
+        if (do_x) {
+          const size_t i = (size_t)(S.row0 + r) * S.n + c;
+          v = update(S.x[i], i);
+          S.x[i] = v;
+        } else {
+          v = S.src[(size_t)r * S.ld + c];
+        }
+        if (S.xt) S.xt[(size_t)r * S.cols + c] = v;
+        fold(v);
+      }
     }
   }
   wg_minmax<DCT_THREADS>(lo, hi, bad, red, redb);
   if (tid == 0) S.part[chunk] = make_float4(lo, hi, bad ? 1.f : 0.f, 0.f);
 }
 
-__global__ __launch_bounds__(DCT_THREADS) void k_dct_code(const SegJob* jobs, int n_jobs, SegJob single,
-                                                          int quality) {
+// Coding.  The wave holds each 16x16 tile transposed: lane j + 16 g, register r
+// holds X[j][4g + r] (one row piece of four values, a float4 when aligned), i.e.
+// Y = X^T in the accumulator layout; the forward chains then give F^T, so the
+// lane's register r holds the coefficient of tile row j, tile column 4g + r
+// (block row j / 8, vertical frequency j % 8; block column (4g + r) / 8,
+// horizontal frequency (4g + r) % 8), and the inverse chains give the decoded
+// tile in the same layout: codes and decoded values are stored as row pieces too.
+// (at most 128 VGPRs: four waves per SIMD, so a launch of four workgroups per
+// CU runs in one round)
+__global__ __launch_bounds__(DCT_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
+void k_dct_code(const SegJob* jobs, int n_jobs, int uni, SegJob single, int quality) {
   __shared__ double c64[64];
-  const SegJob& S = *job_of<&SegJob::code_wg>(jobs, n_jobs, &single, blockIdx.x);
+  const SegJob S = job_of<&SegJob::code_wg>(jobs, n_jobs, uni, single, blockIdx.x);
   const int lid = blockIdx.x - S.code_wg;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int j = lane & 15, g = lane >> 4;
+  const int strips_x = (S.cols + DCT_STRIP - 1) / DCT_STRIP;
+  const int R0 = (lid / strips_x) * 16;
+  const int CW = (lid % strips_x) * DCT_STRIP + wave * 64;   // this wave's 16 x 64 sub-strip
+  const int row = R0 + j;
+  const bool vec = (S.cols & 3) == 0 && (S.ld & 3) == 0 && ((reinterpret_cast<uintptr_t>(S.src) |
+                   reinterpret_cast<uintptr_t>(S.dst)) & 15) == 0;
+  const bool vcode = S.coeffs && (reinterpret_cast<uintptr_t>(S.coeffs) & 7) == 0;
+  // the wave's four tiles, loaded first (in flight while the tables are set up)
+  f4 X[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int col = CW + 16 * t + 4 * g;             // col..col+3 lie in range together (cols % 8 == 0)
+    if (row < S.rows && col < S.cols) {
+      const auto q = gas(S.src + (size_t)row * S.ld + col);
+      if (vec) {
+        X[t] = *(const __attribute__((address_space(1))) f4*)q;
+      } else {
+        X[t][0] = q[0]; X[t][1] = q[1]; X[t][2] = q[2]; X[t][3] = q[3];
+      }
+    } else {
+      X[t][0] = X[t][1] = X[t][2] = X[t][3] = 0.f;
+    }
+  }
   if (tid < 64) c64[tid] = dct_coef64(tid >> 3, tid & 7);
   // the segment's range from its partials (lane l holds chunk l)
   float lo = INFINITY, hi = -INFINITY, badf = 0.f;
@@ -176,17 +298,16 @@ __global__ __launch_bounds__(DCT_THREADS) void k_dct_code(const SegJob* jobs, in
     badf = fmaxf(badf, __shfl_xor(badf, o, 64));
   }
   __syncthreads();                                  // c64 ready
-  const int strips_x = (S.cols + DCT_STRIP - 1) / DCT_STRIP;
-  const int R0 = (lid / strips_x) * 16;
-  const int CW = (lid % strips_x) * DCT_STRIP + wave * 64;   // this wave's 16 x 64 sub-strip
   if (lid == 0 && tid == 0 && S.lohi) { S.lohi[0] = lo; S.lohi[1] = hi; }
-  const int j = lane & 15, g = lane >> 4;
   if (badf != 0.f || hi == lo) {     // constant or non-finite segment: sent as is, codes 0
-    for (int r = 0; r < 16; ++r) {
-      const int row = R0 + r, col = CW + lane;
-      if (row < S.rows && col < S.cols && col < CW + 64) {
-        if (S.dst != S.src) S.dst[(size_t)row * S.ld + col] = S.src[(size_t)row * S.ld + col];
-        if (S.coeffs) S.coeffs[(size_t)row * S.cols + col] = 0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int col = CW + 16 * t + 4 * g;
+      if (row < S.rows && col < S.cols) {
+        for (int c = 0; c < 4; ++c) {
+          if (S.dst != S.src) S.dst[(size_t)row * S.ld + col + c] = X[t][c];
+          if (S.coeffs) S.coeffs[(size_t)row * S.cols + col + c] = 0;
+        }
       }
     }
     return;
@@ -200,45 +321,35 @@ __global__ __launch_bounds__(DCT_THREADS) void k_dct_code(const SegJob* jobs, in
     const bool same = (k >> 3) == (j >> 3);
     Bf[s] = same ? (float)c64[(j & 7) * 8 + (k & 7)] : 0.f;    // C2^T[k][j] = C2[j][k]
     Bi[s] = same ? (float)c64[(k & 7) * 8 + (j & 7)] : 0.f;    // C2[k][j]
-    const int t = (int)kLumaTable[(k & 7) * 8 + (j & 7)];     // block position (row k%8, col j%8)
-    qs[s] = (float)min(255, max(1, (t * scale + 50) / 100));
+    // the step of this lane's coefficient r = s: vertical frequency j % 8,
+    // horizontal frequency (4g + s) % 8
+    const int tq = (int)kLumaTable[(j & 7) * 8 + (k & 7)];
+    qs[s] = (float)min(255, max(1, (tq * scale + 50) / 100));
   }
   const float mapm = 255.f / (hi - lo);
   const float unm = (hi - lo) / 255.f;
   const double lo64 = lo, span64 = (double)hi - (double)lo;
-  const float* src = S.src;
-  // the wave's four tiles: all loads issued first
-  f4 X[4];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int col = CW + 16 * t + j;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = R0 + 4 * g + r;
-      X[t][r] = (row < S.rows && col < S.cols) ? src[(size_t)row * S.ld + col] : lo;
-    }
-  }
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     const int C0 = CW + 16 * t;
     if (C0 >= S.cols) break;                        // uniform across the wave
-    const int col = C0 + j;
+    const int col = C0 + 4 * g;
+    const bool in = row < S.rows && col < S.cols;
     f4 V;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) V[r] = (X[t][r] - lo) * mapm - 128.f;
-    const f4 D1 = mfma_chain(V, Bf);      // (C2 V)^T
-    const f4 F = mfma_chain(D1, Bf);      // C2 V C2^T
+    for (int r = 0; r < 4; ++r) V[r] = in ? (X[t][r] - lo) * mapm - 128.f : 0.f;
+    const f4 D1 = mfma_chain(V, Bf);      // X C2^T
+    const f4 F = mfma_chain(D1, Bf);      // (C2 X C2^T)^T
     float qv[4];
     bool tie[4];
     bool any = false;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int row = R0 + 4 * g + r;
       const float step = qs[r];
       const float tq = F[r] / step;
       qv[r] = rintf(tq);
       const float fr = fabsf(tq - truncf(tq));
-      tie[r] = row < S.rows && col < S.cols && fabsf(fr - 0.5f) * step < 2e-3f;
+      tie[r] = in && fabsf(fr - 0.5f) * step < 2e-3f;
       any = any || tie[r];
     }
     if (__ballot(any)) {
@@ -246,13 +357,12 @@ __global__ __launch_bounds__(DCT_THREADS) void k_dct_code(const SegJob* jobs, in
       for (int r = 0; r < 4; ++r) {
         if (!tie[r]) continue;
         // coefficient (u, v) of the block whose top-left pixel is (br, bc)
-        const int tr = 4 * g + r;
-        const int u = tr & 7, v = j & 7;
-        const int br = R0 + (tr & 8), bc = C0 + (j & 8);
+        const int u = j & 7, v = (4 * g + r) & 7;
+        const int br = R0 + (j & 8), bc = C0 + ((4 * g + r) & 8);
         double f = 0.0;
         for (int y = 0; y < 8; ++y) {
           double rowsum = 0.0;
-          const float* line = src + (size_t)(br + y) * S.ld + bc;
+          const float* line = S.src + (size_t)(br + y) * S.ld + bc;
           for (int x = 0; x < 8; ++x) {
             const double lv = ((double)line[x] - lo64) * 255.0 / span64 - 128.0;
             rowsum += c64[v * 8 + x] * lv;
@@ -264,17 +374,31 @@ __global__ __launch_bounds__(DCT_THREADS) void k_dct_code(const SegJob* jobs, in
     }
     f4 Fq;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = R0 + 4 * g + r;
-      if (S.coeffs && row < S.rows && col < S.cols) S.coeffs[(size_t)row * S.cols + col] = (int16_t)qv[r];
-      Fq[r] = qv[r] * qs[r];
+    for (int r = 0; r < 4; ++r) Fq[r] = qv[r] * qs[r];
+    if (S.coeffs && in) {
+      const auto cq = gas(S.coeffs + (size_t)row * S.cols + col);
+      if (vcode) {
+        typedef unsigned u2 __attribute__((ext_vector_type(2)));
+        u2 w;
+        w[0] = (unsigned)(uint16_t)(int16_t)qv[0] | ((unsigned)(uint16_t)(int16_t)qv[1] << 16);
+        w[1] = (unsigned)(uint16_t)(int16_t)qv[2] | ((unsigned)(uint16_t)(int16_t)qv[3] << 16);
+        *(__attribute__((address_space(1))) u2*)cq = w;
+      } else {
+        for (int r = 0; r < 4; ++r) cq[r] = (int16_t)qv[r];
+      }
     }
-    const f4 D3 = mfma_chain(Fq, Bi);     // F^T C2
-    const f4 R = mfma_chain(D3, Bi);      // C2^T F C2
+    const f4 D3 = mfma_chain(Fq, Bi);     // F C2
+    const f4 R = mfma_chain(D3, Bi);      // (C2^T F C2)^T
+    if (in) {
+      f4 o;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = R0 + 4 * g + r;
-      if (row < S.rows && col < S.cols) S.dst[(size_t)row * S.ld + col] = (R[r] + 128.f) * unm + lo;
+      for (int r = 0; r < 4; ++r) o[r] = (R[r] + 128.f) * unm + lo;
+      const auto q = gas(S.dst + (size_t)row * S.ld + col);
+      if (vec) {
+        *(__attribute__((address_space(1))) f4*)q = o;
+      } else {
+        q[0] = o[0]; q[1] = o[1]; q[2] = o[2]; q[3] = o[3];
+      }
     }
   }
 }
