@@ -258,6 +258,7 @@ __global__ __launch_bounds__(DCT_THREADS) void k_dct_range(const SegJob* jobs, i
 __global__ __launch_bounds__(DCT_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
 void k_dct_code(const SegJob* jobs, int n_jobs, int uni, SegJob single, int quality) {
   __shared__ double c64[64];
+  __shared__ double tile_s[DCT_THREADS / 64][16 * 17];  // a wave's level-mapped tile, for ties
   const SegJob S = job_of<&SegJob::code_wg>(jobs, n_jobs, uni, single, blockIdx.x);
   const int lid = blockIdx.x - S.code_wg;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -353,24 +354,34 @@ void k_dct_code(const SegJob* jobs, int n_jobs, int uni, SegJob single, int qual
       any = any || tie[r];
     }
     if (__ballot(any)) {
+      // every lane of the wave is here (the branch is uniform): the tile's
+      // level-mapped values in float64 go to the wave's LDS slot (row j,
+      // columns 4g..4g+3; blocks lie wholly inside the segment), one division
+      // per value, and the lanes at a tie read their block from there
+      double* tl = tile_s[wave];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) tl[j * 17 + 4 * g + r] = ((double)X[t][r] - lo64) * 255.0 / span64 - 128.0;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         if (!tie[r]) continue;
-        // coefficient (u, v) of the block whose top-left pixel is (br, bc)
+        // coefficient (u, v) of the 8x8 block at tile offset (br, bc)
         const int u = j & 7, v = (4 * g + r) & 7;
-        const int br = R0 + (j & 8), bc = C0 + ((4 * g + r) & 8);
+        const double* blk = tl + (j & 8) * 17 + ((4 * g + r) & 8);
         double f = 0.0;
         for (int y = 0; y < 8; ++y) {
           double rowsum = 0.0;
-          const float* line = S.src + (size_t)(br + y) * S.ld + bc;
-          for (int x = 0; x < 8; ++x) {
-            const double lv = ((double)line[x] - lo64) * 255.0 / span64 - 128.0;
-            rowsum += c64[v * 8 + x] * lv;
-          }
+#pragma unroll
+          for (int x = 0; x < 8; ++x) rowsum += c64[v * 8 + x] * blk[y * 17 + x];
           f += c64[u * 8 + y] * rowsum;
         }
         qv[r] = (float)rint(f / (double)qs[r]);
       }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");   // reads done before the slot is reused
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     f4 Fq;
 #pragma unroll
