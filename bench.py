@@ -276,6 +276,13 @@ def bench_diff(args, steps, ctx, log):
     model = AG.UnrolledADMM(ctx, n, nb, angs, segs, iters=iters, e1=e1, e2=w.x_iters, eta2=w.eta2,
                             eta0=0.1 / (L + 1.0), ckpt=2).cuda()
     opt = torch.optim.Adam(model.parameters(), lr=0.05)
+    if args.no_autotune:
+        tiles = {"kernel": 0, "band": 32, "job_wgs": 16}       # the context's defaults
+    else:
+        choice = model.tune_projector()
+        tiles = {k: choice[k] for k in ("kernel", "band", "job_wgs")}
+        log(f"autotune: band {choice['band']}, {choice['job_wgs']} workgroups per node "
+            f"({choice['us']:.0f} us per batched projection)")
 
     from concurrent.futures import ThreadPoolExecutor
 
@@ -345,6 +352,7 @@ def bench_diff(args, steps, ctx, log):
                                "no quantizer), E1=5, E2=10, learnable rho_k and eta_k (20 scalars), Adam lr 0.05, "
                                "checkpoint every 2 iterations", "n": n, "angles": w.n_angles, "bins": nb,
                    "nodes": w.n_nodes, "unrolled_iterations": iters},
+        "projector_tiles": tiles,
         "training": {"pairs": n_pairs, "losses": losses, "forward_ms": float(np.mean(fw)) * 1e3,
                      "step_ms_median": float(np.median(np.array(fw) + np.array(bw))) * 1e3,
                      "backward_adam_ms": float(np.mean(bw)) * 1e3,

@@ -227,6 +227,20 @@ class UnrolledADMM(torch.nn.Module):
             owner[r0:r0 + nr] = m
         self.owner = owner
 
+    def tune_projector(self, reps: int = 5) -> dict:
+        """Pick the projector launch shape for this model's node batch (the
+        autotuner's sweep over tomo_project_many on scratch images) and set it
+        on the context; returns the autotuner's choice."""
+        from . import autotune
+        m, n = len(self.angles), self.n
+        sizes = [int(a.numel()) for a in self.angles]
+        dev = self.angles[0].device
+        U = torch.rand((m, n, n), device=dev, generator=torch.Generator(device=dev).manual_seed(0))
+        R = torch.empty((sum(sizes), self.n_bins), device=dev)
+        choice = autotune.tune_items(self.tctx, _items(self.angles, U, R, sizes), reps=reps)
+        del U, R
+        return choice
+
     def _iteration(self, k, D, x, U, L):
         """One iteration for all nodes: U, L [M][n][n], D the stacked data."""
         scal = torch.stack([torch.exp(self.log_rho[k]), torch.exp(self.log_eta[k])])   # (rho_k, eta_k)

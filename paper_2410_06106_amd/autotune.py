@@ -91,3 +91,36 @@ def tune(ctx, nodes, cache_path: str | None = None, reps: int = 5, bands=BANDS, 
         with open(cache_path, "w") as fh:
             json.dump(cache, fh, indent=1)
     return dict(choice, cached=False)
+
+
+def _time_items(ctx, items, reps: int) -> float:
+    T.tomo_project_many(ctx, items)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        T.tomo_project_many(ctx, items)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps * 1e3      # microseconds
+
+
+def tune_items(ctx, items, reps: int = 5, bands=BANDS, job_wgs=JOB_WGS, resident: bool = True) -> dict:
+    """The same sweep for a ``tomo_project_many`` item list (``make_items``; the
+    items' images and sinograms are read and overwritten by the trial
+    launches): every (band, job_wgs) pair, and the region-resident kernel when
+    ``resident`` and every image fits it, timed on the batch; the fastest is
+    set on the context.  Returns {"kernel", "band", "job_wgs", "us", "tried"}."""
+    tried = {}
+    for band in bands:
+        for jw in job_wgs:
+            apply(ctx, {"kernel": 0, "band": band, "job_wgs": jw})
+            tried[f"0/{band}/{jw}"] = _time_items(ctx, items, reps)
+    if resident and all(int(it.g.n) <= MAX_RESIDENT_N for it in items):
+        apply(ctx, {"kernel": 1, "band": bands[-1], "job_wgs": job_wgs[0]})
+        tried[f"1/{bands[-1]}/{job_wgs[0]}"] = _time_items(ctx, items, reps)
+    best = min(tried, key=tried.get)
+    kernel, band, jw = (int(v) for v in best.split("/"))
+    choice = {"kernel": kernel, "band": band, "job_wgs": jw, "us": tried[best], "tried": tried}
+    apply(ctx, choice)
+    return choice

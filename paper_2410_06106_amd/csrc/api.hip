@@ -1658,7 +1658,7 @@ int tomo_unroll_ustep_grad(tomo_ctx* ctx, int32_t m, int64_t npix, const float* 
                      scal, dU, dL, dx, part);
   hipLaunchKernelGGL(k_unroll_dot, dim3(nb), dim3(kUnrollThreads), 0, s, (long long)nsino, PG, R,
                      part + 3 * kUnrollMaxWgs);
-  hipLaunchKernelGGL(k_unroll_finish, dim3(1), dim3(64), 0, s, 0, part, na, part + 3 * kUnrollMaxWgs, nb, scal, dscal);
+  hipLaunchKernelGGL(k_unroll_finish, dim3(1), dim3(256), 0, s, 0, part, na, part + 3 * kUnrollMaxWgs, nb, scal, dscal);
   return launch_status(ctx, "tomo_unroll_ustep_grad");
 }
 
@@ -1682,7 +1682,7 @@ int tomo_unroll_xseg_grad(tomo_ctx* ctx, int32_t m, int32_t n, const int32_t* ow
   const int na = unroll_wgs((long long)n * n);
   hipLaunchKernelGGL(k_unroll_xseg_grad, dim3(na), dim3(kUnrollThreads), 0, s, m, n, owner, G, U, L, x, scal, eta2, e2,
                      dU, dL, dx, part);
-  hipLaunchKernelGGL(k_unroll_finish, dim3(1), dim3(64), 0, s, 1, part, na, part, 0, scal, dscal);
+  hipLaunchKernelGGL(k_unroll_finish, dim3(1), dim3(256), 0, s, 1, part, na, part, 0, scal, dscal);
   return launch_status(ctx, "tomo_unroll_xseg_grad");
 }
 
@@ -1703,7 +1703,7 @@ int tomo_unroll_xavg_grad(tomo_ctx* ctx, int32_t m, int64_t npix, const float* G
   const int na = unroll_wgs(npix);
   hipLaunchKernelGGL(k_unroll_xavg_grad, dim3(na), dim3(kUnrollThreads), 0, s, m, (long long)npix, G, L, scal, dU, dL,
                      part);
-  hipLaunchKernelGGL(k_unroll_finish, dim3(1), dim3(64), 0, s, 1, part, na, part, 0, scal, dscal);
+  hipLaunchKernelGGL(k_unroll_finish, dim3(1), dim3(256), 0, s, 1, part, na, part, 0, scal, dscal);
   return launch_status(ctx, "tomo_unroll_xavg_grad");
 }
 
@@ -1724,7 +1724,7 @@ int tomo_unroll_dual_grad(tomo_ctx* ctx, int32_t m, int64_t npix, const float* G
   const int na = unroll_wgs(npix);
   hipLaunchKernelGGL(k_unroll_dual_grad, dim3(na), dim3(kUnrollThreads), 0, s, m, (long long)npix, G, U, xn, scal, dL,
                      dU, dxn, part);
-  hipLaunchKernelGGL(k_unroll_finish, dim3(1), dim3(64), 0, s, 1, part, na, part, 0, scal, dscal);
+  hipLaunchKernelGGL(k_unroll_finish, dim3(1), dim3(256), 0, s, 1, part, na, part, 0, scal, dscal);
   return launch_status(ctx, "tomo_unroll_dual_grad");
 }
 

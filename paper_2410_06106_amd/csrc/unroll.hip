@@ -212,17 +212,31 @@ __global__ __launch_bounds__(UT) void k_axpby(long long n, float alpha, const fl
 }
 
 // ---------------------------------------------------------------------------
-// finish: adds the partials in workgroup order and forms the scalar gradients
+// finish: adds the partials in a fixed order (thread t takes partials t, t +
+// UT, ...; then a fixed tree over the threads) and forms the scalar gradients
 //   kind 0 (u-step):  parts A (<G, U - x>, <G, L>) over na workgroups, parts B
 //                     (<P G, R>) over nb: d rho = -eta sux, d eta = -(sr + rho sux + sl)
 //   kind 1 (one sum): d rho = sum of parts A, d eta = 0
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_unroll_finish(int kind, const double* pa, int na, const double* pb, int nb,
+__global__ __launch_bounds__(UT) void k_unroll_finish(int kind, const double* pa, int na, const double* pb, int nb,
                                                       const float* scal, float* dscal) {
-  if (threadIdx.x != 0) return;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  for (int i = 0; i < na; ++i) { s0 += pa[3 * i]; s1 += pa[3 * i + 1]; }
-  for (int i = 0; i < nb; ++i) s2 += pb[3 * i];
+  __shared__ double red[3][UT];
+  const int t = threadIdx.x;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  for (int i = t; i < na; i += UT) { a0 += pa[3 * i]; a1 += pa[3 * i + 1]; }
+  for (int i = t; i < nb; i += UT) a2 += pb[3 * i];
+  red[0][t] = a0; red[1][t] = a1; red[2][t] = a2;
+  __syncthreads();
+  for (int o = UT / 2; o > 0; o >>= 1) {
+    if (t < o) {
+      red[0][t] += red[0][t + o];
+      red[1][t] += red[1][t + o];
+      red[2][t] += red[2][t + o];
+    }
+    __syncthreads();
+  }
+  if (t != 0) return;
+  const double s0 = red[0][0], s1 = red[1][0], s2 = red[2][0];
   if (kind == 0) {
     const double rho = scal[0], eta = scal[1];
     dscal[0] = (float)(-eta * s0);
