@@ -464,7 +464,24 @@ int quantize_dct_noalloc(tomo_ctx* ctx, const float* a, int32_t rows, int32_t co
  *   tomo_unroll_dual_grad   dL = G, dU = rho G, dxn = -rho sum_m G_m,
  *                           d rho = <G, U - xn>.
  *   tomo_axpby              out = alpha a + beta b over n values (out may be a or b).
+ *
+ * The forward of one unrolled Alg. 2 step, fused into the batched projector
+ * pair (two launches, the u-step in the backprojector's epilogue):
+ *   tomo_unroll_local_step  items[i].sino = R_i = P_i U_i - D_i, then
+ *                           Uo_i = U_i - eta (P_i^T R_i + rho (U_i - x) + L_i)
+ *                           for the nodes of `items` (U_i = items[i].image, read
+ *                           only; all items share n and n_bins).  D: float32
+ *                           [sum n_ang][n_bins], the items' data rows in item
+ *                           order; x float32 [n][n]; L, Uo float32
+ *                           [n_items][n][n]; scal as above.  The job tables are
+ *                           staged like tomo_project_many's (do not capture).
+ *                           Errors: TOMO_EINVAL for an invalid item list,
+ *                           items of different n or n_bins, a null pointer, or
+ *                           an output (the R_i rows, Uo) overlapping an input
+ *                           or the other output.
  */
+int tomo_unroll_local_step(tomo_ctx* ctx, const tomo_proj_item* items, int32_t n_items, const float* D,
+                           const float* x, const float* L, const float* scal, float* Uo, void* stream);
 int tomo_axpby(tomo_ctx* ctx, int64_t n, float alpha, const float* a, float beta, const float* b, float* out,
                void* stream);
 int tomo_unroll_ustep(tomo_ctx* ctx, int32_t m, int64_t npix, const float* U, const float* B, const float* x,

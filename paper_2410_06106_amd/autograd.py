@@ -121,11 +121,9 @@ class LocalStep(torch.autograd.Function):
         U = U.contiguous()
         sizes = [int(a.numel()) for a in angles]
         R = torch.empty((sum(sizes), n_bins), dtype=torch.float32, device=U.device)
-        T.tomo_project_many(tctx, _items(angles, U, R, sizes))
-        T.tomo_axpby(tctx, 1.0, R, -1.0, D, out=R)                       # R = P U - D
-        B = torch.empty_like(U)
-        T.tomo_backproject_many(tctx, _items(angles, B, R, sizes), 1.0, 0.0)
-        Uo = T.tomo_unroll_ustep(tctx, U, B, x.contiguous(), L.contiguous(), scal.contiguous())
+        # R = P U - D, then the u-step in the backprojector's epilogue
+        Uo = T.tomo_unroll_local_step(tctx, _items(angles, U, R, sizes), U, D.contiguous(), x.contiguous(),
+                                      L.contiguous(), scal.contiguous())
         fctx.save_for_backward(U, x, L, scal, R)
         fctx.tctx, fctx.angles, fctx.sizes, fctx.n_bins = tctx, angles, sizes, n_bins
         return Uo

@@ -752,8 +752,18 @@ int project_one(tomo_ctx* ctx, tomo_geom g, const double* angles, int n_ang, con
 // the host for this call, staged through pinned memory and copied to the
 // device on `stream`; the projector's workspace is the context's.  No cache:
 // the item pointers may differ on every call.
+// The unrolled u-step's extra operands (tomo_unroll_local_step): the
+// projector subtracts D's rows, the backprojector forms Uo_i in its epilogue.
+struct UnrollArgs {
+  const float* D;
+  const float* x;
+  const float* L;
+  const float* scal;
+  float* Uo;
+};
+
 int stage_batch(tomo_ctx* ctx, const tomo_proj_item* items, int n_items, int kind, float alpha, float beta,
-                void* stream, ProjLaunch& plan, int& bp_wgs) {
+                void* stream, ProjLaunch& plan, int& bp_wgs, const UnrollArgs* ua = nullptr) {
   std::vector<ProjJob> pj, rj;
   std::vector<BPJob> bj;
   if (kind == 0) {
@@ -782,9 +792,12 @@ int stage_batch(tomo_ctx* ctx, const tomo_proj_item* items, int n_items, int kin
         !ctx->bbbase.ensure(std::max<size_t>(bb_elems, 1) * 4))
       return ctx->fail(TOMO_ENOMEM, "batch workspace allocation failed");
     int pw = 0, rw = 0;
+    size_t drow = 0;
     for (int i = 0; i < n_items; ++i) {
       const tomo_proj_item& I = items[i];
-      ProjJob j = make_proj_job(I.image, I.angles, nullptr, I.sino, I.g.n, I.g.n_bins, I.n_ang, shapes[i]);
+      const float* d = ua ? ua->D + drow * I.g.n_bins : nullptr;
+      drow += I.n_ang;
+      ProjJob j = make_proj_job(I.image, I.angles, d, I.sino, I.g.n, I.g.n_bins, I.n_ang, shapes[i]);
       j.partial = static_cast<float*>(ctx->bpartial.p) + poff[i];
       j.bbase = static_cast<int*>(ctx->bbbase.p) + boff[i];
       j.chord = ctx->model;
@@ -811,6 +824,15 @@ int stage_batch(tomo_ctx* ctx, const tomo_proj_item* items, int n_items, int kin
       b.mode = BP_PLAIN;
       b.alpha = alpha;
       b.beta = beta;
+      if (ua) {
+        const size_t npix = (size_t)I.g.n * I.g.n;
+        b.mode = BP_UNROLL;
+        b.u_in = I.image;
+        b.img = ua->Uo + i * npix;
+        b.x = ua->x;
+        b.lam = ua->L + i * npix;
+        b.scal = ua->scal;
+      }
       b.chord = ctx->model;
       b.wg_begin = bw;
       bw += b.tiles_x * b.tiles_x;
@@ -1288,6 +1310,42 @@ int tomo_backproject_many(tomo_ctx* ctx, const tomo_proj_item* items, int32_t n_
   if (int rc = stage_batch(ctx, items, n_items, 1, alpha, beta, stream, L, wgs)) return rc;
   launch_backproject(Many<BPJob>{static_cast<const BPJob*>(ctx->btable.p), n_items}, wgs, ctx->model, stream);
   return launch_status(ctx, "tomo_backproject_many");
+}
+
+int tomo_unroll_local_step(tomo_ctx* ctx, const tomo_proj_item* items, int32_t n_items, const float* D,
+                           const float* x, const float* L, const float* scal, float* Uo, void* stream) {
+  if (!ctx) return TOMO_EINVAL;
+  if (int rc = check_items(ctx, items, n_items, 0)) return rc;
+  if (!D || !x || !L || !scal || !Uo) return ctx->fail(TOMO_EINVAL, "null pointer");
+  const int n = items[0].g.n, nb = items[0].g.n_bins;
+  size_t rows = 0;
+  for (int i = 0; i < n_items; ++i) {
+    if (items[i].g.n != n || items[i].g.n_bins != nb) return ctx->fail(TOMO_EINVAL, "items must share n and n_bins");
+    rows += items[i].n_ang;
+  }
+  const size_t img = (size_t)n * n * 4, stack = img * n_items, dbytes = rows * nb * 4;
+  // R_i rows (first launch) and Uo (second) against every operand
+  for (int i = 0; i < n_items; ++i) {
+    const size_t sb = (size_t)items[i].n_ang * nb * 4;
+    if (overlaps(items[i].sino, sb, D, dbytes) || overlaps(items[i].sino, sb, x, img) ||
+        overlaps(items[i].sino, sb, L, stack) || overlaps(items[i].sino, sb, scal, 8) ||
+        overlaps(Uo, stack, items[i].image, img) || overlaps(Uo, stack, items[i].sino, sb))
+      return ctx->fail(TOMO_EINVAL, "an output overlaps an input or the other output");
+  }
+  if (overlaps(Uo, stack, D, dbytes) || overlaps(Uo, stack, x, img) || overlaps(Uo, stack, L, stack) ||
+      overlaps(Uo, stack, scal, 8))
+    return ctx->fail(TOMO_EINVAL, "Uo overlaps an input");
+  if (int rc = set_device(ctx)) return rc;
+  const UnrollArgs ua{D, x, L, scal, Uo};
+  ProjLaunch P;
+  int unused = 0;
+  if (int rc = stage_batch(ctx, items, n_items, 0, 0.f, 0.f, stream, P, unused, &ua)) return rc;
+  launch_projection(P, stream);
+  ProjLaunch B;
+  int wgs = 0;
+  if (int rc = stage_batch(ctx, items, n_items, 1, 1.f, 0.f, stream, B, wgs, &ua)) return rc;
+  launch_backproject(Many<BPJob>{static_cast<const BPJob*>(ctx->btable.p), n_items}, wgs, ctx->model, stream);
+  return launch_status(ctx, "tomo_unroll_local_step");
 }
 
 int tomo_ctr_gd(tomo_ctx* ctx, tomo_geom g, const double* angles, int32_t n_ang, const float* d, float* u,

@@ -128,15 +128,19 @@ __global__ __launch_bounds__(BTHREADS) void k_backproject(Src src) {
       if (c < J.n) out[c] = J.beta != 0.f ? fmaf(J.alpha, accv[q], J.beta * out[c]) : J.alpha * accv[q];
     }
   } else {
+    // ADMM u-step, in place (BP_ADMM) or from u_in with (rho, eta1) read
+    // from device memory (BP_UNROLL)
     const float* xr = J.x + (size_t)r * J.n;
     const float* lr = J.lam + (size_t)r * J.n;
+    const float* ur = J.u_in ? J.u_in + (size_t)r * J.n : out;
+    const float rho = J.scal ? J.scal[0] : J.rho, eta = J.scal ? J.scal[1] : J.eta1;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       int c = cb + q;
       if (c < J.n) {
-        float u = out[c];
-        float g = accv[q] + fmaf(J.rho, u - xr[c], lr[c]);
-        out[c] = fmaf(-J.eta1, g, u);
+        float u = ur[c];
+        float g = accv[q] + fmaf(rho, u - xr[c], lr[c]);
+        out[c] = fmaf(-eta, g, u);
       }
     }
   }

@@ -93,7 +93,7 @@ constexpr int BW = 48;          // staged bins per (tile, angle)
 constexpr int BAC = 64;         // angles per staged chunk
 constexpr int BTHREADS = 256;   // 4 pixels per thread
 
-enum { BP_PLAIN = 0, BP_ADMM = 1 };
+enum { BP_PLAIN = 0, BP_ADMM = 1, BP_UNROLL = 2 };
 
 struct BPJob {
   const float* sino;    // [n_ang][nb]
@@ -108,6 +108,8 @@ struct BPJob {
   float alpha, beta;    // plain: img = alpha * P^T sino + beta * img
   float rho, eta1;      // ADMM:  u -= eta1 * (P^T sino + rho (u - x) + lam)
   int chord;            // 0: Joseph weights; 1: chord lengths
+  const float* u_in;    // unrolled step: u read from here (img = the new u), or null (u = img)
+  const float* scal;    // unrolled step: (rho, eta1) in device memory, or null (the fields above)
 };
 
 // cos and sin of a projection angle.  The chord-length model takes a cosine

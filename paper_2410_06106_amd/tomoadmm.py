@@ -32,7 +32,7 @@ EXPORTED = ("tomo_create", "tomo_destroy", "tomo_status_string", "tomo_last_erro
             "admm_reg_update", "admm_consensus_reg",
             "quantize_kmeans", "quantize_dct", "quantize_dct_noalloc", "tomo_pack_labels", "tomo_unpack_labels",
             "tomo_dct_encode_words", "tomo_dct_encode", "tomo_dct_decode", "tomo_sqdiff",
-            "tomo_axpby", "tomo_unroll_ustep", "tomo_unroll_ustep_grad", "tomo_unroll_xseg", "tomo_unroll_xseg_grad",
+            "tomo_axpby", "tomo_unroll_local_step", "tomo_unroll_ustep", "tomo_unroll_ustep_grad", "tomo_unroll_xseg", "tomo_unroll_xseg_grad",
             "tomo_unroll_xavg", "tomo_unroll_xavg_grad", "tomo_unroll_dual", "tomo_unroll_dual_grad")
 
 
@@ -116,6 +116,7 @@ _lib.tomo_dct_decode.argtypes = [_P, _P, ctypes.c_int64, _P, _P, ctypes.c_int32,
 _lib.tomo_unpack_labels.argtypes = [_P, _P, ctypes.c_int64, ctypes.c_int32, _P, ctypes.c_int32, _P, _P, _P]
 _I32, _I64, _F32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float
 _lib.tomo_axpby.argtypes = [_P, _I64, _F32, _P, _F32, _P, _P, _P]
+_lib.tomo_unroll_local_step.argtypes = [_P, ctypes.POINTER(tomo_proj_item), _I32, _P, _P, _P, _P, _P, _P]
 _lib.tomo_unroll_ustep.argtypes = [_P, _I32, _I64, _P, _P, _P, _P, _P, _P, _P]
 _lib.tomo_unroll_ustep_grad.argtypes = [_P, _I32, _I64, _P, _P, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P]
 _lib.tomo_unroll_xseg.argtypes = [_P, _I32, _I32, _P, _P, _P, _P, _P, _F32, _I32, _P, _P]
@@ -473,6 +474,20 @@ def tomo_axpby(ctx: Context, alpha: float, a, beta: float, b, out=None, stream=N
                          _f32(out, "out", a.shape), _stream(stream))
     ctx.check(rc, "tomo_axpby")
     return out
+
+
+def tomo_unroll_local_step(ctx: Context, items, U, D, x, L, scal, stream=None):
+    """Fused forward of one unrolled Alg. 2 step for the nodes of ``items``
+    (``make_items``: image = U_m, sino = the rows of R that receive P_m U_m - D_m);
+    U, L [M][n][n] (items' images are U's slices), D the stacked data rows,
+    x [n][n], scal (rho, eta).  Returns the new U."""
+    m, n = _stack_dims(U)
+    Uo = torch.empty_like(U)
+    rc = _lib.tomo_unroll_local_step(ctx.handle, items, len(items), _f32(D, "D"), _f32(x, "x", (n, n)),
+                                     _f32(L, "L", U.shape), _f32(scal, "scal", (2,)), _f32(Uo, "Uo"),
+                                     _stream(stream))
+    ctx.check(rc, "tomo_unroll_local_step")
+    return Uo
 
 
 def tomo_unroll_ustep(ctx: Context, U, B, x, L, scal, stream=None):

@@ -307,3 +307,42 @@ def test_unrolled_step_functions_match_float64_autograd(mods, tctx):
     for name, a, b in zip(("dU", "dx", "dL", "d(rho, eta)"), got_grad, ref_grad):
         log(f"  gradient {name}: rel {rel_l2(a, b):.2e}")
         assert rel_l2(a, b) <= 1e-4
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_fused_local_step_equals_unfused_sequence(mods, model):
+    """tomo_unroll_local_step (P U - D in the projector's epilogue, the u-step in
+    the backprojector's) against the unfused calls (tomo_project_many,
+    tomo_axpby, tomo_backproject_many, tomo_unroll_ustep) on a ragged batch of
+    100^2 nodes with several projector regions: the residual R bit for bit, the
+    new U to 1e-6 (the epilogue groups the u-step's terms differently)."""
+    T, AG = mods
+    ctx = T.Context(0)
+    T.tomo_set_option(ctx, T.TOMO_OPT_PROJ_MODEL, model)
+    T.tomo_set_option(ctx, T.TOMO_OPT_PROJ_JOB_WGS, 64)
+    rng = np.random.default_rng(5)
+    M, n, nb, K = 4, 100, 143, 53
+    th = synthdata.angles(K)
+    parts = synthdata.partition_angles(K, M, "interleaved")
+    angs = [to_dev(th[p], torch.float64) for p in parts]
+    sizes = [len(p) for p in parts]
+    U = to_dev(rng.standard_normal((M, n, n)))
+    L = to_dev(0.3 * rng.standard_normal((M, n, n)))
+    x = to_dev(rng.standard_normal((n, n)))
+    D = to_dev(rng.standard_normal((K, nb)))
+    scal = to_dev(np.array([1.3, 0.004], np.float32))
+    R1 = torch.empty((K, nb), device="cuda")
+    Uo1 = T.tomo_unroll_local_step(ctx, AG._items(angs, U, R1, sizes), U, D, x, L, scal)
+    R2 = torch.empty((K, nb), device="cuda")
+    T.tomo_project_many(ctx, AG._items(angs, U, R2, sizes))
+    T.tomo_axpby(ctx, 1.0, R2, -1.0, D, out=R2)
+    B = torch.empty_like(U)
+    T.tomo_backproject_many(ctx, AG._items(angs, B, R2, sizes), 1.0, 0.0)
+    Uo2 = T.tomo_unroll_ustep(ctx, U, B, x, L, scal)
+    torch.cuda.synchronize()
+    assert torch.equal(R1, R2)
+    assert rel_l2(Uo1.cpu().numpy(), Uo2.cpu().numpy()) < 1e-6
+    with pytest.raises(T.TomoError):          # Uo overlapping L
+        rc = T._lib.tomo_unroll_local_step(ctx.handle, AG._items(angs, U, R1, sizes), M, D.data_ptr(),
+                                           x.data_ptr(), L.data_ptr(), scal.data_ptr(), L.data_ptr(), None)
+        ctx.check(rc, "tomo_unroll_local_step")
