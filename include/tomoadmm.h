@@ -449,7 +449,9 @@ int quantize_dct_noalloc(tomo_ctx* ctx, const float* a, int32_t rows, int32_t co
  *                           forward residual R = P U - D (nsino values, stacked
  *                           like PG): dU = G - eta (PtPG + rho G), dL = -eta G,
  *                           dx = eta rho sum_m G_m, d rho = -eta <G, U - x>,
- *                           d eta = -(<PG, R> + rho <G, U - x> + <G, L>).
+ *                           d eta = -(<PG, R> + rho <G, U - x> + <G, L>);
+ *                           with accumulate != 0, dL, dx and dscal are added
+ *                           to (the sums over several steps, in place).
  *   tomo_unroll_xseg        Alg. 3 on every row r from x: E2 steps
  *                           x <- x - eta2 rho (x - t), t = U_o + L_o / rho,
  *                           o = owner[r] (int32 [n], the node owning row r).
@@ -488,7 +490,8 @@ int tomo_unroll_ustep(tomo_ctx* ctx, int32_t m, int64_t npix, const float* U, co
                       const float* L, const float* scal, float* Uo, void* stream);
 int tomo_unroll_ustep_grad(tomo_ctx* ctx, int32_t m, int64_t npix, const float* G, const float* PtPG, const float* PG,
                            const float* R, int64_t nsino, const float* U, const float* x, const float* L,
-                           const float* scal, float* dU, float* dL, float* dx, float* dscal, void* stream);
+                           const float* scal, float* dU, float* dL, float* dx, float* dscal, int32_t accumulate,
+                           void* stream);
 int tomo_unroll_xseg(tomo_ctx* ctx, int32_t m, int32_t n, const int32_t* owner, const float* U, const float* L,
                      const float* x, const float* scal, float eta2, int32_t e2, float* xo, void* stream);
 int tomo_unroll_xseg_grad(tomo_ctx* ctx, int32_t m, int32_t n, const int32_t* owner, const float* G, const float* U,

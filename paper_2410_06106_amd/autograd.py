@@ -18,7 +18,9 @@ step of an iteration is one launch for all nodes.  Every step of an iteration
 is a Function whose forward and backward are HIP kernels (the tomo_unroll_*
 calls): ``LocalStep`` (Alg. 2: P, the residual, P^T and the u-step; its
 backward applies P^T P to the incoming gradient and forms the gradients of u,
-x, lambda, rho and eta, the scalar ones as float64 sums), ``XSegment`` (Alg. 3),
+x, lambda, rho and eta, the scalar ones as float64 sums; ``LocalSteps`` runs
+E1 of them as one Function whose backward sums the gradients of x, lambda, rho
+and eta over the steps in place), ``XSegment`` (Alg. 3),
 ``XAverage`` (Eq. 9) and ``Dual`` (Eq. 24).  (rho_k, eta_k) enter the kernels
 as a two-element device tensor, so learned values never go through the host.
 """
@@ -141,6 +143,46 @@ class LocalStep(torch.autograd.Function):
         return dU, dx, dL, ds, None, None, None, None
 
 
+class LocalSteps(torch.autograd.Function):
+    """E1 Alg. 2 steps for all nodes in one Function, U -> U after ``e1`` steps.
+    It keeps every step's input and residual, and its backward runs the steps'
+    backward passes in reverse order with the gradients of x, L and (rho, eta)
+    summed in place over the steps (one gradient tensor each instead of one per
+    step for autograd to add up)."""
+
+    @staticmethod
+    def forward(fctx, U, x, L, scal, D, tctx, angles, n_bins, e1):
+        U, x, L, scal, D = U.contiguous(), x.contiguous(), L.contiguous(), scal.contiguous(), D.contiguous()
+        sizes = [int(a.numel()) for a in angles]
+        us, rs = [], []
+        for _ in range(e1):
+            R = torch.empty((sum(sizes), n_bins), dtype=torch.float32, device=U.device)
+            Un = T.tomo_unroll_local_step(tctx, _items(angles, U, R, sizes), U, D, x, L, scal)
+            us.append(U)
+            rs.append(R)
+            U = Un
+        fctx.save_for_backward(x, L, scal, *us, *rs)
+        fctx.tctx, fctx.angles, fctx.sizes, fctx.e1 = tctx, angles, sizes, e1
+        return U
+
+    @staticmethod
+    def backward(fctx, G):
+        saved = fctx.saved_tensors
+        e1 = fctx.e1
+        x, L, scal = saved[:3]
+        us, rs = saved[3:3 + e1], saved[3 + e1:]
+        G = G.contiguous()
+        dL = dx = ds = None
+        for k in reversed(range(e1)):
+            PG = torch.empty_like(rs[k])
+            T.tomo_project_many(fctx.tctx, _items(fctx.angles, G, PG, fctx.sizes))
+            PtPG = torch.empty_like(G)
+            T.tomo_backproject_many(fctx.tctx, _items(fctx.angles, PtPG, PG, fctx.sizes), 1.0, 0.0)
+            G, dL, dx, ds = T.tomo_unroll_ustep_grad(fctx.tctx, G, PtPG, PG, rs[k], us[k], x, L, scal, dL=dL, dx=dx,
+                                                     ds=ds, accumulate=k != e1 - 1)
+        return G, dx, dL, ds, None, None, None, None, None
+
+
 class XSegment(torch.autograd.Function):
     """Alg. 3 on every node's own rows: E2 steps x <- x - eta2 rho (x - t), t = U_o + L_o / rho."""
 
@@ -242,8 +284,8 @@ class UnrolledADMM(torch.nn.Module):
     def _iteration(self, k, D, x, U, L):
         """One iteration for all nodes: U, L [M][n][n], D the stacked data."""
         scal = torch.stack([torch.exp(self.log_rho[k]), torch.exp(self.log_eta[k])])   # (rho_k, eta_k)
-        for _ in range(self.e1):                                                # Alg. 2
-            U = LocalStep.apply(U, x, L, scal, D, self.tctx, self.angles, self.n_bins)
+        if self.e1 > 0:                                                         # Alg. 2, E1 steps
+            U = LocalSteps.apply(U, x, L, scal, D, self.tctx, self.angles, self.n_bins, self.e1)
         if self.mode == "seg":                                                  # Alg. 3 (Eq. 17)
             x_new = XSegment.apply(U, L, x, scal, self.owner, self.tctx, self.eta2, self.e2)
         else:                                                                   # Eq. 9

@@ -39,7 +39,7 @@ __global__ void k_unpack_labels(const unsigned*, int, int, const float*, int, ui
 __global__ void k_unroll_ustep(int, long long, const float*, const float*, const float*, const float*, const float*,
                                float*);
 __global__ void k_unroll_ustep_grad(int, long long, const float*, const float*, const float*, const float*,
-                                    const float*, const float*, float*, float*, float*, double*);
+                                    const float*, const float*, float*, float*, float*, int, double*);
 __global__ void k_unroll_dot(long long, const float*, const float*, double*);
 __global__ void k_unroll_xseg(int, const int*, const float*, const float*, const float*, const float*, float, int,
                               float*);
@@ -51,7 +51,7 @@ __global__ void k_unroll_xavg_grad(int, long long, const float*, const float*, c
 __global__ void k_unroll_dual(int, long long, const float*, const float*, const float*, const float*, float*);
 __global__ void k_unroll_dual_grad(int, long long, const float*, const float*, const float*, const float*, float*,
                                    float*, float*, double*);
-__global__ void k_unroll_finish(int, const double*, int, const double*, int, const float*, float*);
+__global__ void k_unroll_finish(int, const double*, int, const double*, int, const float*, float*, int);
 __global__ void k_axpby(long long, float, const float*, float, const float*, float*);
 }  // namespace tomo
 
@@ -1705,18 +1705,21 @@ int tomo_unroll_ustep(tomo_ctx* ctx, int32_t m, int64_t npix, const float* U, co
 
 int tomo_unroll_ustep_grad(tomo_ctx* ctx, int32_t m, int64_t npix, const float* G, const float* PtPG, const float* PG,
                            const float* R, int64_t nsino, const float* U, const float* x, const float* L,
-                           const float* scal, float* dU, float* dL, float* dx, float* dscal, void* stream) {
+                           const float* scal, float* dU, float* dL, float* dx, float* dscal, int32_t accumulate,
+                           void* stream) {
   if (int rc = unroll_check(ctx, m, npix, {G, PtPG, PG, R, U, x, L, scal, dU, dL, dx, dscal})) return rc;
   if (nsino < 1) return ctx->fail(TOMO_EINVAL, "bad sinogram size");
   double* part = unroll_parts(ctx);
   if (!part) return ctx->fail(TOMO_ENOMEM, "workspace");
   hipStream_t s = (hipStream_t)stream;
   const int na = unroll_wgs(npix), nb = unroll_wgs(nsino);
+  const int acc = accumulate != 0;
   hipLaunchKernelGGL(k_unroll_ustep_grad, dim3(na), dim3(kUnrollThreads), 0, s, m, (long long)npix, G, PtPG, U, x, L,
-                     scal, dU, dL, dx, part);
+                     scal, dU, dL, dx, acc, part);
   hipLaunchKernelGGL(k_unroll_dot, dim3(nb), dim3(kUnrollThreads), 0, s, (long long)nsino, PG, R,
                      part + 3 * kUnrollMaxWgs);
-  hipLaunchKernelGGL(k_unroll_finish, dim3(1), dim3(256), 0, s, 0, part, na, part + 3 * kUnrollMaxWgs, nb, scal, dscal);
+  hipLaunchKernelGGL(k_unroll_finish, dim3(1), dim3(256), 0, s, 0, part, na, part + 3 * kUnrollMaxWgs, nb, scal, dscal,
+                     acc);
   return launch_status(ctx, "tomo_unroll_ustep_grad");
 }
 
@@ -1740,7 +1743,7 @@ int tomo_unroll_xseg_grad(tomo_ctx* ctx, int32_t m, int32_t n, const int32_t* ow
   const int na = unroll_wgs((long long)n * n);
   hipLaunchKernelGGL(k_unroll_xseg_grad, dim3(na), dim3(kUnrollThreads), 0, s, m, n, owner, G, U, L, x, scal, eta2, e2,
                      dU, dL, dx, part);
-  hipLaunchKernelGGL(k_unroll_finish, dim3(1), dim3(256), 0, s, 1, part, na, part, 0, scal, dscal);
+  hipLaunchKernelGGL(k_unroll_finish, dim3(1), dim3(256), 0, s, 1, part, na, part, 0, scal, dscal, 0);
   return launch_status(ctx, "tomo_unroll_xseg_grad");
 }
 
@@ -1761,7 +1764,7 @@ int tomo_unroll_xavg_grad(tomo_ctx* ctx, int32_t m, int64_t npix, const float* G
   const int na = unroll_wgs(npix);
   hipLaunchKernelGGL(k_unroll_xavg_grad, dim3(na), dim3(kUnrollThreads), 0, s, m, (long long)npix, G, L, scal, dU, dL,
                      part);
-  hipLaunchKernelGGL(k_unroll_finish, dim3(1), dim3(256), 0, s, 1, part, na, part, 0, scal, dscal);
+  hipLaunchKernelGGL(k_unroll_finish, dim3(1), dim3(256), 0, s, 1, part, na, part, 0, scal, dscal, 0);
   return launch_status(ctx, "tomo_unroll_xavg_grad");
 }
 
@@ -1782,7 +1785,7 @@ int tomo_unroll_dual_grad(tomo_ctx* ctx, int32_t m, int64_t npix, const float* G
   const int na = unroll_wgs(npix);
   hipLaunchKernelGGL(k_unroll_dual_grad, dim3(na), dim3(kUnrollThreads), 0, s, m, (long long)npix, G, U, xn, scal, dL,
                      dU, dxn, part);
-  hipLaunchKernelGGL(k_unroll_finish, dim3(1), dim3(256), 0, s, 1, part, na, part, 0, scal, dscal);
+  hipLaunchKernelGGL(k_unroll_finish, dim3(1), dim3(256), 0, s, 1, part, na, part, 0, scal, dscal, 0);
   return launch_status(ctx, "tomo_unroll_dual_grad");
 }
 

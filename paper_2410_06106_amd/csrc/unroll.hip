@@ -60,11 +60,12 @@ __global__ __launch_bounds__(UT) void k_unroll_ustep(int m, long long npix, cons
 //   dU = G - eta (P^T P G + rho G),  dL = -eta G,  dx = eta rho sum_m G_m,
 //   d eta = -(<P G, R> + rho <G, U - x> + <G, L>),  d rho = -eta <G, U - x>,
 // R = P U - D the forward residual.  One thread per pixel handles it for all
-// nodes (so dx needs no atomics); part[wg] = (<G, U - x>, <G, L>, 0).
+// nodes (so dx needs no atomics); part[wg] = (<G, U - x>, <G, L>, 0).  With
+// acc, dL and dx are added to instead of written.
 __global__ __launch_bounds__(UT) void k_unroll_ustep_grad(int m, long long npix, const float* G, const float* PtPG,
                                                           const float* U, const float* x, const float* L,
                                                           const float* scal, float* dU, float* dL, float* dx,
-                                                          double* part) {
+                                                          int acc, double* part) {
   const float rho = scal[0], eta = scal[1];
   double sux = 0.0, sl = 0.0;
   for (long long p = (long long)blockIdx.x * UT + threadIdx.x; p < npix; p += (long long)gridDim.x * UT) {
@@ -74,12 +75,12 @@ __global__ __launch_bounds__(UT) void k_unroll_ustep_grad(int m, long long npix,
       const long long i = (long long)k * npix + p;
       const float g = G[i];
       dU[i] = g - eta * (PtPG[i] + rho * g);
-      dL[i] = -eta * g;
+      dL[i] = acc ? fmaf(-eta, g, dL[i]) : -eta * g;
       gs += g;
       sux += (double)g * ((double)U[i] - (double)xp);
       sl += (double)g * (double)L[i];
     }
-    dx[p] = eta * rho * gs;
+    dx[p] = acc ? fmaf(eta * rho, gs, dx[p]) : eta * rho * gs;
   }
   wg_sum3(sux, sl, 0.0, part);
 }
@@ -217,9 +218,10 @@ __global__ __launch_bounds__(UT) void k_axpby(long long n, float alpha, const fl
 //   kind 0 (u-step):  parts A (<G, U - x>, <G, L>) over na workgroups, parts B
 //                     (<P G, R>) over nb: d rho = -eta sux, d eta = -(sr + rho sux + sl)
 //   kind 1 (one sum): d rho = sum of parts A, d eta = 0
+// With acc the two values are added to dscal instead of written.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(UT) void k_unroll_finish(int kind, const double* pa, int na, const double* pb, int nb,
-                                                      const float* scal, float* dscal) {
+                                                      const float* scal, float* dscal, int acc) {
   __shared__ double red[3][UT];
   const int t = threadIdx.x;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
@@ -237,14 +239,17 @@ __global__ __launch_bounds__(UT) void k_unroll_finish(int kind, const double* pa
   }
   if (t != 0) return;
   const double s0 = red[0][0], s1 = red[1][0], s2 = red[2][0];
+  float r0, r1;
   if (kind == 0) {
     const double rho = scal[0], eta = scal[1];
-    dscal[0] = (float)(-eta * s0);
-    dscal[1] = (float)(-(s2 + rho * s0 + s1));
+    r0 = (float)(-eta * s0);
+    r1 = (float)(-(s2 + rho * s0 + s1));
   } else {
-    dscal[0] = (float)s0;
-    dscal[1] = 0.f;
+    r0 = (float)s0;
+    r1 = 0.f;
   }
+  dscal[0] = acc ? dscal[0] + r0 : r0;
+  dscal[1] = acc ? dscal[1] + r1 : r1;
 }
 
 }  // namespace tomo

@@ -118,7 +118,8 @@ _I32, _I64, _F32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float
 _lib.tomo_axpby.argtypes = [_P, _I64, _F32, _P, _F32, _P, _P, _P]
 _lib.tomo_unroll_local_step.argtypes = [_P, ctypes.POINTER(tomo_proj_item), _I32, _P, _P, _P, _P, _P, _P]
 _lib.tomo_unroll_ustep.argtypes = [_P, _I32, _I64, _P, _P, _P, _P, _P, _P, _P]
-_lib.tomo_unroll_ustep_grad.argtypes = [_P, _I32, _I64, _P, _P, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P]
+_lib.tomo_unroll_ustep_grad.argtypes = [_P, _I32, _I64, _P, _P, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _I32,
+                                         _P]
 _lib.tomo_unroll_xseg.argtypes = [_P, _I32, _I32, _P, _P, _P, _P, _P, _F32, _I32, _P, _P]
 _lib.tomo_unroll_xseg_grad.argtypes = [_P, _I32, _I32, _P, _P, _P, _P, _P, _P, _F32, _I32, _P, _P, _P, _P, _P]
 _lib.tomo_unroll_xavg.argtypes = [_P, _I32, _I64, _P, _P, _P, _P, _P]
@@ -499,15 +500,22 @@ def tomo_unroll_ustep(ctx: Context, U, B, x, L, scal, stream=None):
     return Uo
 
 
-def tomo_unroll_ustep_grad(ctx: Context, G, PtPG, PG, R, U, x, L, scal, stream=None):
+def tomo_unroll_ustep_grad(ctx: Context, G, PtPG, PG, R, U, x, L, scal, stream=None, dL=None, dx=None, ds=None,
+                           accumulate: bool = False):
+    """Gradients of one u-step; returns (dU, dL, dx, dscal).  With ``accumulate``
+    the given dL, dx, ds are added to in place (and returned)."""
     m, n = _stack_dims(U)
-    dU, dL = torch.empty_like(U), torch.empty_like(U)
-    dx = torch.empty_like(x)
-    ds = torch.empty(2, dtype=torch.float32, device=U.device)
+    dU = torch.empty_like(U)
+    if accumulate and (dL is None or dx is None or ds is None):
+        raise ValueError("accumulate needs dL, dx and ds")
+    dL = torch.empty_like(U) if dL is None else dL
+    dx = torch.empty_like(x) if dx is None else dx
+    ds = torch.empty(2, dtype=torch.float32, device=U.device) if ds is None else ds
     rc = _lib.tomo_unroll_ustep_grad(ctx.handle, m, n * n, _f32(G, "G", U.shape), _f32(PtPG, "PtPG", U.shape),
                                      _f32(PG, "PG"), _f32(R, "R", PG.shape), PG.numel(), _f32(U, "U"),
                                      _f32(x, "x", (n, n)), _f32(L, "L", U.shape), _f32(scal, "scal", (2,)),
-                                     _f32(dU, "dU"), _f32(dL, "dL"), _f32(dx, "dx"), _f32(ds, "dscal"), _stream(stream))
+                                     _f32(dU, "dU"), _f32(dL, "dL", U.shape), _f32(dx, "dx", (n, n)),
+                                     _f32(ds, "dscal", (2,)), int(bool(accumulate)), _stream(stream))
     ctx.check(rc, "tomo_unroll_ustep_grad")
     return dU, dL, dx, ds
 

@@ -346,3 +346,34 @@ def test_fused_local_step_equals_unfused_sequence(mods, model):
         rc = T._lib.tomo_unroll_local_step(ctx.handle, AG._items(angs, U, R1, sizes), M, D.data_ptr(),
                                            x.data_ptr(), L.data_ptr(), scal.data_ptr(), L.data_ptr(), None)
         ctx.check(rc, "tomo_unroll_local_step")
+
+
+def test_local_steps_equal_chained_local_step(mods, tctx):
+    """LocalSteps (E1 = 3 steps in one Function, gradients of x, L and
+    (rho, eta) summed in place) against three chained LocalStep calls: the same
+    output bit for bit, and the same gradients of U, x, L and (rho, eta) to 1e-6."""
+    T, AG = mods
+    rng = np.random.default_rng(8)
+    M, n, nb, K = 3, 40, 59, 33
+    th = synthdata.angles(K)
+    parts = synthdata.partition_angles(K, M, "interleaved")
+    angs = [to_dev(th[p], torch.float64) for p in parts]
+    D = to_dev(np.concatenate([rng.standard_normal((len(p), nb)) for p in parts]))
+    base = [to_dev(a) for a in (rng.standard_normal((M, n, n)), rng.standard_normal((n, n)),
+                                0.3 * rng.standard_normal((M, n, n)), np.array([1.1, 0.003]))]
+    W = to_dev(rng.standard_normal((M, n, n)))
+    outs, grads = [], []
+    for fused in (True, False):
+        U, x, L, sc = (t.clone().requires_grad_(True) for t in base)
+        if fused:
+            out = AG.LocalSteps.apply(U, x, L, sc, D, tctx, angs, nb, 3)
+        else:
+            out = U
+            for _ in range(3):
+                out = AG.LocalStep.apply(out, x, L, sc, D, tctx, angs, nb)
+        (out * W).sum().backward()
+        outs.append(out.detach().cpu())
+        grads.append([t.grad.cpu().numpy() for t in (U, x, L, sc)])
+    assert torch.equal(outs[0], outs[1])
+    for a, b in zip(*grads):
+        assert rel_l2(a, b) < 1e-6
