@@ -44,7 +44,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 ALGO_FLOPS_PER_UPDATE = 4.0        # the two multiply-adds of the 2-tap interpolation
-PEAK_FP32_TFLOPS = 157.3           # MI355X vector FP32 (published)
+PEAK_FP32_TFLOPS = 157.3           # MI355X vector FP32 (published, with packed FP32 instructions)
+# without packed FP32 (the library is built with it off): 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz
+PEAK_FP32_SINGLE_ISSUE_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 PEAK_HBM_GBS = 8000.0
 PHASE_KERNELS = {"project": "projection phase: k_project + k_project_reduce",
                  "backproject": "backprojection phase: k_backproject"}
@@ -671,6 +673,8 @@ def main():
         "phases_us": dict({k: v * 1e3 for k, v in kern.items()}, consensus=consensus_us),
         "roofline": {"bound": "alu", "kernel": PHASE_KERNELS[dom], "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
+                     "peak_single_issue": PEAK_FP32_SINGLE_ISSUE_TFLOPS,
+                     "frac_single_issue": achieved / PEAK_FP32_SINGLE_ISSUE_TFLOPS,
                      "algorithmic": f"{ALGO_FLOPS_PER_UPDATE:g} flop per ray-voxel update x "
                                     f"{upd_per_launch} updates per launch"},
         "hbm": ({"achieved": traffic / dur_s / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
