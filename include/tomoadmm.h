@@ -47,7 +47,7 @@ enum {
   TOMO_EINVAL = 1,        /* bad argument, checked on the host                 */
   TOMO_ENOMEM = 2,        /* device workspace could not be allocated            */
   TOMO_EDEVICE = 3,       /* HIP runtime or kernel launch failure               */
-  TOMO_EUNSUPPORTED = 4   /* valid request this build does not handle           */
+  TOMO_EUNSUPPORTED = 4   /* valid request the library does not handle         */
 };
 
 /* Create a context bound to HIP device `device`.  *ctx receives the handle. */

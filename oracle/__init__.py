@@ -14,7 +14,7 @@ chord     Eq. 2 with intersection lengths: the chord of each ray through each
           pixel square (a trapezoid in the ray offset), its transpose, dense form.
 admm      Alg. 1 (centralized GD), Alg. 2 (local u-update), Alg. 3 (segment
           x-update), Eq. 9 (averaging x-update), Eq. 23-24 (exchange, dual),
-          Alg. 4 (driver).
+          Alg. 4 (the outer iteration).
 kmeans    Alg. 5: scalar K-means quantizer with a fully specified, bit-exact
           fixed-point centroid update.
 dct       "standard JPEG" quantizer: 8x8 orthonormal DCT-II with the luminance
@@ -27,6 +27,6 @@ stepsize  power iteration for the step size of Alg. 2.
 
 Parity status: every function is pinned by a ``-m "not gpu"`` test in
 ``tests/test_oracle_*.py`` except the long-horizon trajectory of the segment
-x-update driver (its iteration map is not contractive), which is parity
+x-update iteration (its iteration map is not contractive), which is parity
 unpinned beyond single-iteration checks.
 """

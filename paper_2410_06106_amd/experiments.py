@@ -14,7 +14,7 @@
             quantizer) next to the formula.
 
 Every iteration runs in the library's kernels (projector pair, consensus,
-quantizers, the centralized step) through the same batched driver as the
+quantizers, the centralized step) through the same batched ADMM loop as the
 benchmark; the host only builds the inputs, applies the stopping rule of
 Section 3.2 (relative change of x below 1e-6) and reports.  Inputs are
 synthetic (``synthdata``): a piecewise-constant phantom with three gray levels

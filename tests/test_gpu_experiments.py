@@ -1,4 +1,4 @@
-"""The quality-study driver (paper_2410_06106_amd.experiments) against the
+"""The quality studies (paper_2410_06106_amd.experiments) against the
 oracle at a small size: with the same inputs and step sizes, CTR, unquantized
 dADMM, dADMM-K and dADMM-J give the oracle's RMSE trajectories, and the
 stopping rule measures the relative change of x."""
