@@ -230,3 +230,79 @@ def test_large_workload_dct_consensus_teacher_forced(T, ctx, quality):
     total = M * rows * n
     log(f"  x~ worst rel-L2 {worst_xt:.2e}; DCT codes at ties {n_ties} of {total} ({n_ties / total:.2e})")
     assert n_ties <= DCT_TIE_BUDGET * total
+
+
+def test_single_workload_teacher_forced_sampled(T, ctx):
+    """The 512^2, 720-angle, 16-node workload (contiguous angle blocks, Poisson
+    data, SEG, K-means 8 levels, E1 = 5, E2 = 10) in the launch shape the
+    benchmark times (all nodes in one batched local update and one consensus
+    call, projector tiles 32/48): 12 iterations on the GPU, and at iterations 0,
+    5 and 11 nodes 0, 7 and 15 checked against one oracle iteration from the
+    GPU's own state (local update and dual to 1e-5; x~ to 1e-5; K-means labels,
+    centroids, iteration count and exchanged segment bit-exact on the GPU's x~)."""
+    w = synthdata.WORKLOADS["single"]
+    n, nb, M = w.n, w.n_bins, w.n_nodes
+    truth = synthdata.phantom(w)
+    th = synthdata.angles(w.n_angles)
+    d = synthdata.poisson_noisy(joseph.project(truth, th, nb), w.noise_level, n, synthdata.sinogram_seed(w))
+    parts = synthdata.partition_angles(w.n_angles, M, w.split)
+    segs = synthdata.segment_rows(n, M)
+    v0 = np.random.default_rng(0).standard_normal((n, n))
+    L = stepsize.normal_operator_norm(th[parts[0]], n, nb, v0, iters=5)
+    rho = 1.0
+    eta1 = float(np.float32(0.5 / (L + rho)))
+    c = T.Context(0)
+    T.tomo_set_option(c, T.TOMO_OPT_PROJ_BAND, 32)
+    T.tomo_set_option(c, T.TOMO_OPT_PROJ_JOB_WGS, 48)
+    x = torch.zeros((n, n), dtype=torch.float32, device="cuda")
+    us = [torch.zeros_like(x) for _ in parts]
+    lams = [torch.zeros_like(x) for _ in parts]
+    ents = [dict(n=n, n_bins=nb, angles=to_dev(th[p], torch.float64), slice=0, d=to_dev(d[p]), u=us[m],
+                 lam=lams[m], x=x, seg_row0=segs[m][0], seg_rows=segs[m][1], rho=rho, eta1=eta1, eta2=w.eta2)
+            for m, p in enumerate(parts)]
+    nodes = T.make_nodes(ents)
+    k = w.levels
+    labels = [torch.empty(r * n, dtype=torch.uint8, device="cuda") for _, r in segs]
+    cents = [torch.empty(k, dtype=torch.float32, device="cuda") for _ in segs]
+    iters = [torch.empty(1, dtype=torch.int32, device="cuda") for _ in segs]
+    xts = [torch.empty((r, n), dtype=torch.float32, device="cuda") for _, r in segs]
+    msgs = T.make_msgs([dict(labels=labels[m], centroids=cents[m], iters=iters[m], x_tilde=xts[m])
+                        for m in range(M)])
+    q = T.tomo_quant(T.TOMO_QUANT_KMEANS, k, 30, 50)
+    sample = (0, 7, 15)
+    worst = dict(u=0.0, xt=0.0, lam=0.0)
+    for it in range(12):
+        check = it in (0, 5, 11)
+        if check:
+            log(f"case single 512^2 iteration {it}: nodes {sample}")
+            x0, u0, l0 = _np(x), {m: _np(us[m]) for m in sample}, {m: _np(lams[m]) for m in sample}
+        T.admm_local_update(c, nodes, w.inner_iters)
+        if check:
+            u1 = {m: _np(us[m]) for m in sample}
+        T.admm_consensus(c, nodes, T.TOMO_XUPDATE_SEGMENT, w.x_iters, q, msgs)
+        if not check:
+            continue
+        x1 = _np(x)
+        for m in sample:
+            p = parts[m]
+            ref = oadmm.local_update(u0[m], x0, l0[m], d[p].astype(np.float64), th[p], rho, eta1, w.inner_iters)
+            err = rel_l2(u1[m], ref)
+            worst["u"] = max(worst["u"], err)
+            assert err <= 1e-5, (it, m, err)
+            r0, nr = segs[m]
+            sl = slice(r0, r0 + nr)
+            ref_xt = oadmm.x_update_segment(x0[sl], u1[m][sl], l0[m][sl], rho, w.eta2, w.x_iters)
+            xt = xts[m].cpu().numpy()
+            err = rel_l2(xt, ref_xt)
+            worst["xt"] = max(worst["xt"], err)
+            assert err <= 1e-5, (it, m, err)
+            kq = kmeans_quantize(xt.reshape(-1), k, 30)
+            np.testing.assert_array_equal(labels[m].cpu().numpy(), kq.labels)
+            np.testing.assert_array_equal(cents[m].cpu().numpy(), kq.centroids)
+            assert int(iters[m].item()) == kq.iters
+            np.testing.assert_array_equal(x1[sl].astype(np.float32).reshape(-1), kq.a_hat)
+            ref = oadmm.dual_update(l0[m], u1[m], x1, rho)
+            err = rel_l2(_np(lams[m]), ref)
+            worst["lam"] = max(worst["lam"], err)
+            assert err <= 1e-5, (it, m, err)
+    log(f"  worst rel-L2 at the checked iterations: {worst}")
