@@ -155,6 +155,72 @@ def test_batched_mixed_segment_sizes_equals_plain_loop(mods, ctx):
     assert all(np.isfinite(p).all() and np.abs(p).max() > 0 for p in plain)
 
 
+def test_batched_mixed_sizes_against_oracle(mods, ctx):
+    """One batched iteration (every node of every slice in one local-update call
+    and one consensus call, K-means 16) over slices of uneven image sizes and
+    node counts (40^2 to 128^2, 2 to 8 nodes, data from the oracle's projector),
+    from a state two batched iterations in: the first and last node of each
+    slice against one oracle iteration from the GPU's state (local update and
+    dual to 1e-5, x~ to 1e-5, K-means labels, centroids, iteration count and the
+    exchanged segment bit-exact on the GPU's x~)."""
+    T, A = mods
+    from oracle.kmeans import kmeans_quantize
+    spec = [(48, 60, 69, 2), (64, 90, 91, 4), (40, 50, 57, 5), (128, 192, 182, 8)]
+    slices, data = [], []
+    for i, (n, k, b, m) in enumerate(spec):
+        w = synthdata.Workload(f"mix{i}", 0, n, k, b, m, "interleaved", 6, "gaussian", 0.01, 5)
+        truth = synthdata.phantom(w, i)
+        th = synthdata.angles(k)
+        d = synthdata.add_gaussian_noise(joseph.project(truth, th, b), w.noise_level, synthdata.sinogram_seed(w, i))
+        parts = synthdata.partition_angles(k, m, "interleaved")
+        v0 = np.random.default_rng(i).standard_normal((n, n))
+        L = max(stepsize.normal_operator_norm(th[p], n, b, v0, iters=10) for p in parts)
+        s = A.make_slice(ctx, w, slice_idx=i, d_host=d, truth_host=truth)
+        s.eta1 = float(np.float32(0.5 / (L + 1.0)))
+        slices.append(s)
+        data.append((th, d, parts, synthdata.segment_rows(n, m)))
+    M = sum(len(s.d) for s in slices)
+    labels, cents, iters, xts = [], [], [], []
+    for s in slices:
+        for r0, nr in s.segments:
+            labels.append(torch.empty(nr * s.n, dtype=torch.uint8, device="cuda"))
+            cents.append(torch.empty(16, dtype=torch.float32, device="cuda"))
+            iters.append(torch.empty(1, dtype=torch.int32, device="cuda"))
+            xts.append(torch.empty((nr, s.n), dtype=torch.float32, device="cuda"))
+    msgs = T.make_msgs([dict(labels=labels[j], centroids=cents[j], iters=iters[j], x_tilde=xts[j]) for j in range(M)])
+    run = A.DADMM(ctx, slices, quant=T.tomo_quant(T.TOMO_QUANT_KMEANS, 16, 30, 50), msgs=msgs)
+    for _ in range(2):
+        run.step()
+    snap = [(s.x.cpu().numpy().astype(np.float64), [u.cpu().numpy().astype(np.float64) for u in s.u],
+             [l.cpu().numpy().astype(np.float64) for l in s.lam]) for s in slices]
+    T.admm_local_update(ctx, run.nodes, run.e1)
+    u1 = [[u.cpu().numpy().astype(np.float64) for u in s.u] for s in slices]
+    T.admm_consensus(ctx, run.nodes, run.mode, run.e2, run.quant, msgs)
+    j0 = 0
+    for si, s in enumerate(slices):
+        th, d, parts, segs = data[si]
+        x0, u0, l0 = snap[si]
+        x1 = s.x.cpu().numpy().astype(np.float64)
+        for m in sorted({0, len(parts) - 1}):
+            log(f"  slice {si} ({s.n}^2, {len(parts)} nodes): node {m}")
+            p = parts[m]
+            ref = oadmm.local_update(u0[m], x0, l0[m], d[p].astype(np.float64), th[p], 1.0, s.eta1, run.e1)
+            assert rel_l2(u1[si][m], ref) <= 1e-5, (si, m)
+            r0, nr = segs[m]
+            sl = slice(r0, r0 + nr)
+            ref_xt = oadmm.x_update_segment(x0[sl], u1[si][m][sl], l0[m][sl], 1.0, run.eta2, run.e2)
+            xt = xts[j0 + m].cpu().numpy()
+            assert rel_l2(xt, ref_xt) <= 1e-5, (si, m)
+            kq = kmeans_quantize(xt.reshape(-1), 16, 30)
+            np.testing.assert_array_equal(labels[j0 + m].cpu().numpy(), kq.labels)
+            np.testing.assert_array_equal(cents[j0 + m].cpu().numpy(), kq.centroids)
+            assert int(iters[j0 + m].item()) == kq.iters
+            np.testing.assert_array_equal(x1[sl].astype(np.float32).reshape(-1), kq.a_hat)
+            lam_ref = oadmm.dual_update(l0[m], u1[si][m], x1, 1.0)
+            assert rel_l2(s.lam[m].cpu().numpy(), lam_ref) <= 1e-5, (si, m)
+        j0 += len(parts)
+
+
 def test_graph_replay_matches_eager(mods, ctx):
     T, A = mods
     slices = _slices(T, A, ctx)
