@@ -363,7 +363,6 @@ __global__ __launch_bounds__(PTHREADS) void k_project(Src src) {
 // spans n_achunk * ceil(nb / PTHREADS) workgroups of this launch.
 template <class Src>
 __global__ __launch_bounds__(PTHREADS) void k_project_reduce(Src src) {
-  __shared__ int fin_bbase[PMAXREG * PA];
   int lid;
   const ProjJob J = src.get(blockIdx.x, lid);
   const int G = J.n_rr * J.n_rc;
@@ -372,10 +371,10 @@ __global__ __launch_bounds__(PTHREADS) void k_project_reduce(Src src) {
   const int b = (lid - achunk * nbb) * PTHREADS + threadIdx.x;
   const int a0 = achunk * PA;
   const int na = min(PA, J.n_ang - a0);
-  // first bins of the regions' partials, as the projector computed them
-  const int* bb = J.bbase + (size_t)achunk * G * PA;
-  for (int i = threadIdx.x; i < G * PA; i += PTHREADS) fin_bbase[i] = bb[i];
-  __syncthreads();
+  // first bins of the regions' partials, as the projector computed them: the
+  // same for every thread of the workgroup, so read through the constant
+  // address space (scalar loads, no LDS staging or barrier)
+  const auto fin_bbase = (const __attribute__((address_space(4))) int*)(J.bbase + (size_t)achunk * G * PA);
   if (b >= J.nb) return;
   const float* pbase = J.partial + (size_t)achunk * G * (PA * PACC);
   // every region wrote all PA * PACC of its partials (zeros past its rays), so
