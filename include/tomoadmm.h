@@ -459,6 +459,13 @@ int quantize_dct_noalloc(tomo_ctx* ctx, const float* a, int32_t rows, int32_t co
  *                           dL_o = (1 - a^E2) G / rho (zero on rows a node does
  *                           not own), d rho = sum G ((1 - a^E2)(-L_o / rho^2)
  *                           - E2 eta2 a^(E2-1) (x - t)).
+ *   tomo_unroll_seg_dual_grad  the two above chained, x' = xseg(U, L, x) and
+ *                           L' = L + rho (U - x'), in one pass: given Gx =
+ *                           dLoss/dx' (from its other uses) and GL = dLoss/dL',
+ *                           with gx = Gx - rho sum_m GL_m: dL = GL + the xseg
+ *                           term of gx, dU = rho GL + the xseg term of gx,
+ *                           dx = a^E2 gx, d rho = sum_m <GL_m, U_m - x'> + the
+ *                           xseg term; xs = x' (float32 [n][n]).
  *   tomo_unroll_xavg        Eq. 9: xo = (1/M) sum_m (U_m + L_m / rho).
  *   tomo_unroll_xavg_grad   dU_m = G / M, dL_m = G / (M rho),
  *                           d rho = -sum_m <G, L_m> / (M rho^2).
@@ -497,6 +504,10 @@ int tomo_unroll_xseg(tomo_ctx* ctx, int32_t m, int32_t n, const int32_t* owner, 
 int tomo_unroll_xseg_grad(tomo_ctx* ctx, int32_t m, int32_t n, const int32_t* owner, const float* G, const float* U,
                           const float* L, const float* x, const float* scal, float eta2, int32_t e2, float* dU,
                           float* dL, float* dx, float* dscal, void* stream);
+int tomo_unroll_seg_dual_grad(tomo_ctx* ctx, int32_t m, int32_t n, const int32_t* owner, const float* Gx,
+                              const float* GL, const float* U, const float* L, const float* x, const float* xs,
+                              const float* scal, float eta2, int32_t e2, float* dU, float* dL, float* dx, float* dscal,
+                              void* stream);
 int tomo_unroll_xavg(tomo_ctx* ctx, int32_t m, int64_t npix, const float* U, const float* L, const float* scal,
                      float* xo, void* stream);
 int tomo_unroll_xavg_grad(tomo_ctx* ctx, int32_t m, int64_t npix, const float* G, const float* L, const float* scal,

@@ -201,6 +201,28 @@ class XSegment(torch.autograd.Function):
         return dU, dL, dx, ds, None, None, None, None
 
 
+class SegConsensus(torch.autograd.Function):
+    """Alg. 3 on every node's own rows followed by the dual update (Eq. 24), as
+    one Function returning (x', L'): its backward forms the gradients of U, L,
+    x and (rho, eta) of both steps in one pass (tomo_unroll_seg_dual_grad)."""
+
+    @staticmethod
+    def forward(fctx, U, L, x, scal, owner, tctx, eta2, e2):
+        U, L, x, scal = U.contiguous(), L.contiguous(), x.contiguous(), scal.contiguous()
+        xs = T.tomo_unroll_xseg(tctx, owner, U, L, x, scal, eta2, e2)
+        Lo = T.tomo_unroll_dual(tctx, L, U, xs, scal)
+        fctx.save_for_backward(U, L, x, xs, scal, owner)
+        fctx.tctx, fctx.eta2, fctx.e2 = tctx, eta2, e2
+        return xs, Lo
+
+    @staticmethod
+    def backward(fctx, Gx, GL):
+        U, L, x, xs, scal, owner = fctx.saved_tensors
+        dU, dL, dx, ds = T.tomo_unroll_seg_dual_grad(fctx.tctx, owner, Gx.contiguous(), GL.contiguous(), U, L, x, xs,
+                                                     scal, fctx.eta2, fctx.e2)
+        return dU, dL, dx, ds, None, None, None, None
+
+
 class XAverage(torch.autograd.Function):
     """Eq. 9: x = mean_m (U_m + L_m / rho)."""
 
@@ -286,11 +308,11 @@ class UnrolledADMM(torch.nn.Module):
         scal = torch.stack([torch.exp(self.log_rho[k]), torch.exp(self.log_eta[k])])   # (rho_k, eta_k)
         if self.e1 > 0:                                                         # Alg. 2, E1 steps
             U = LocalSteps.apply(U, x, L, scal, D, self.tctx, self.angles, self.n_bins, self.e1)
-        if self.mode == "seg":                                                  # Alg. 3 (Eq. 17)
-            x_new = XSegment.apply(U, L, x, scal, self.owner, self.tctx, self.eta2, self.e2)
+        if self.mode == "seg":                                                  # Alg. 3 (Eq. 17), Eq. 24
+            x_new, L = SegConsensus.apply(U, L, x, scal, self.owner, self.tctx, self.eta2, self.e2)
         else:                                                                   # Eq. 9
             x_new = XAverage.apply(U, L, scal, self.tctx)
-        L = Dual.apply(L, U, x_new, scal, self.tctx)                            # Eq. 18 / 24
+            L = Dual.apply(L, U, x_new, scal, self.tctx)                        # Eq. 18 / 24
         return x_new, U, L
 
     def _segment(self, k0, k1, D, x, U, L):

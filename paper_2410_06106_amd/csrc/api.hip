@@ -45,6 +45,9 @@ __global__ void k_unroll_xseg(int, const int*, const float*, const float*, const
                               float*);
 __global__ void k_unroll_xseg_grad(int, int, const int*, const float*, const float*, const float*, const float*,
                                    const float*, float, int, float*, float*, float*, double*);
+__global__ void k_unroll_segdual_grad(int, int, const int*, const float*, const float*, const float*, const float*,
+                                      const float*, const float*, const float*, float, int, float*, float*, float*,
+                                      double*);
 __global__ void k_unroll_xavg(int, long long, const float*, const float*, const float*, float*);
 __global__ void k_unroll_xavg_grad(int, long long, const float*, const float*, const float*, float*, float*,
                                    double*);
@@ -1745,6 +1748,22 @@ int tomo_unroll_xseg_grad(tomo_ctx* ctx, int32_t m, int32_t n, const int32_t* ow
                      dU, dL, dx, part);
   hipLaunchKernelGGL(k_unroll_finish, dim3(1), dim3(256), 0, s, 1, part, na, part, 0, scal, dscal, 0);
   return launch_status(ctx, "tomo_unroll_xseg_grad");
+}
+
+int tomo_unroll_seg_dual_grad(tomo_ctx* ctx, int32_t m, int32_t n, const int32_t* owner, const float* Gx,
+                              const float* GL, const float* U, const float* L, const float* x, const float* xs,
+                              const float* scal, float eta2, int32_t e2, float* dU, float* dL, float* dx, float* dscal,
+                              void* stream) {
+  if (int rc = unroll_check(ctx, m, (int64_t)n * n, {owner, Gx, GL, U, L, x, xs, scal, dU, dL, dx, dscal})) return rc;
+  if (e2 < 0) return ctx->fail(TOMO_EINVAL, "E2 < 0");
+  double* part = unroll_parts(ctx);
+  if (!part) return ctx->fail(TOMO_ENOMEM, "workspace");
+  hipStream_t s = (hipStream_t)stream;
+  const int na = unroll_wgs((long long)n * n);
+  hipLaunchKernelGGL(k_unroll_segdual_grad, dim3(na), dim3(kUnrollThreads), 0, s, m, n, owner, Gx, GL, U, L, x, xs,
+                     scal, eta2, e2, dU, dL, dx, part);
+  hipLaunchKernelGGL(k_unroll_finish, dim3(1), dim3(256), 0, s, 1, part, na, part, 0, scal, dscal, 0);
+  return launch_status(ctx, "tomo_unroll_seg_dual_grad");
 }
 
 int tomo_unroll_xavg(tomo_ctx* ctx, int32_t m, int64_t npix, const float* U, const float* L, const float* scal,

@@ -140,6 +140,47 @@ __global__ __launch_bounds__(UT) void k_unroll_xseg_grad(int m, int n, const int
   wg_sum3(sr, 0.0, 0.0, part);
 }
 
+// Gradients of the SEG x-update followed by the dual update, (xs, Lo) with
+// xs = t + a^E2 (x - t) and Lo = L + rho (U - xs), given Gx = dLoss/dxs (from
+// later uses of xs) and GL = dLoss/dLo, in one pass: gx = Gx - rho sum_m GL_m
+// is the total gradient of xs; dL = GL (+ (1 - a^E2) gx / rho on the owner's
+// rows), dU = rho GL (+ (1 - a^E2) gx on the owner's rows), dx = a^E2 gx,
+// d rho = sum_m <GL_m, U_m - xs> + the Alg. 3 term of gx.  part[wg] = (d rho share, 0, 0).
+__global__ __launch_bounds__(UT) void k_unroll_segdual_grad(int m, int n, const int* owner, const float* Gx,
+                                                            const float* GL, const float* U, const float* L,
+                                                            const float* x, const float* xs, const float* scal,
+                                                            float eta2, int e2, float* dU, float* dL, float* dx,
+                                                            double* part) {
+  const float rho_f = scal[0];
+  const double rho = rho_f;
+  const double a = 1.0 - (double)eta2 * rho;
+  double aE = 1.0, aE1 = 1.0;                      // a^E2, a^(E2-1)
+  for (int e = 0; e < e2; ++e) { aE1 = aE; aE *= a; }
+  const long long npix = (long long)n * n;
+  double sr = 0.0;
+  for (long long p = (long long)blockIdx.x * UT + threadIdx.x; p < npix; p += (long long)gridDim.x * UT) {
+    const int o = owner[p / n];
+    float gs = 0.f;
+    for (int k = 0; k < m; ++k) gs += GL[(long long)k * npix + p];
+    const float gxf = Gx[p] + -rho_f * gs;
+    const double gx = gxf;
+    const long long io = (long long)o * npix + p;
+    const double lo = L[io], t = (double)U[io] + lo / rho;
+    dx[p] = (float)(aE * gx);
+    sr += gx * ((1.0 - aE) * (-lo / (rho * rho)) - (double)e2 * eta2 * aE1 * ((double)x[p] - t));
+    const float xsp = xs[p];
+    const float cl = (float)((1.0 - aE) * gx / rho), cu = (float)((1.0 - aE) * gx);
+    for (int k = 0; k < m; ++k) {
+      const long long i = (long long)k * npix + p;
+      const float g = GL[i];
+      dL[i] = k == o ? g + cl : g;
+      dU[i] = k == o ? rho_f * g + cu : rho_f * g;
+      sr += (double)g * ((double)U[i] - (double)xsp);
+    }
+  }
+  wg_sum3(sr, 0.0, 0.0, part);
+}
+
 // ---------------------------------------------------------------------------
 // x-update, AVG
 // ---------------------------------------------------------------------------

@@ -33,6 +33,7 @@ EXPORTED = ("tomo_create", "tomo_destroy", "tomo_status_string", "tomo_last_erro
             "quantize_kmeans", "quantize_dct", "quantize_dct_noalloc", "tomo_pack_labels", "tomo_unpack_labels",
             "tomo_dct_encode_words", "tomo_dct_encode", "tomo_dct_decode", "tomo_sqdiff",
             "tomo_axpby", "tomo_unroll_local_step", "tomo_unroll_ustep", "tomo_unroll_ustep_grad", "tomo_unroll_xseg", "tomo_unroll_xseg_grad",
+            "tomo_unroll_seg_dual_grad",
             "tomo_unroll_xavg", "tomo_unroll_xavg_grad", "tomo_unroll_dual", "tomo_unroll_dual_grad")
 
 
@@ -122,6 +123,8 @@ _lib.tomo_unroll_ustep_grad.argtypes = [_P, _I32, _I64, _P, _P, _P, _P, _I64, _P
                                          _P]
 _lib.tomo_unroll_xseg.argtypes = [_P, _I32, _I32, _P, _P, _P, _P, _P, _F32, _I32, _P, _P]
 _lib.tomo_unroll_xseg_grad.argtypes = [_P, _I32, _I32, _P, _P, _P, _P, _P, _P, _F32, _I32, _P, _P, _P, _P, _P]
+_lib.tomo_unroll_seg_dual_grad.argtypes = [_P, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _F32, _I32, _P, _P, _P, _P,
+                                            _P]
 _lib.tomo_unroll_xavg.argtypes = [_P, _I32, _I64, _P, _P, _P, _P, _P]
 _lib.tomo_unroll_xavg_grad.argtypes = [_P, _I32, _I64, _P, _P, _P, _P, _P, _P, _P]
 _lib.tomo_unroll_dual.argtypes = [_P, _I32, _I64, _P, _P, _P, _P, _P, _P]
@@ -540,6 +543,22 @@ def tomo_unroll_xseg_grad(ctx: Context, owner, G, U, L, x, scal, eta2: float, e2
                                     _f32(scal, "scal", (2,)), float(eta2), int(e2), _f32(dU, "dU"), _f32(dL, "dL"),
                                     _f32(dx, "dx"), _f32(ds, "dscal"), _stream(stream))
     ctx.check(rc, "tomo_unroll_xseg_grad")
+    return dU, dL, dx, ds
+
+
+def tomo_unroll_seg_dual_grad(ctx: Context, owner, Gx, GL, U, L, x, xs, scal, eta2: float, e2: int, stream=None):
+    """Gradients of (xs, Lo) = (Alg. 3 x-update, Eq. 24 dual) for dLoss/dxs = Gx and
+    dLoss/dLo = GL; returns (dU, dL, dx, dscal)."""
+    m, n = _stack_dims(U)
+    dU, dL = torch.empty_like(U), torch.empty_like(U)
+    dx = torch.empty_like(x)
+    ds = torch.empty(2, dtype=torch.float32, device=U.device)
+    rc = _lib.tomo_unroll_seg_dual_grad(ctx.handle, m, n, _dev(owner, torch.int32, "owner", (n,)),
+                                        _f32(Gx, "Gx", (n, n)), _f32(GL, "GL", U.shape), _f32(U, "U"),
+                                        _f32(L, "L", U.shape), _f32(x, "x", (n, n)), _f32(xs, "xs", (n, n)),
+                                        _f32(scal, "scal", (2,)), float(eta2), int(e2), _f32(dU, "dU"), _f32(dL, "dL"),
+                                        _f32(dx, "dx"), _f32(ds, "dscal"), _stream(stream))
+    ctx.check(rc, "tomo_unroll_seg_dual_grad")
     return dU, dL, dx, ds
 
 

@@ -377,3 +377,32 @@ def test_local_steps_equal_chained_local_step(mods, tctx):
     assert torch.equal(outs[0], outs[1])
     for a, b in zip(*grads):
         assert rel_l2(a, b) < 1e-6
+
+
+def test_seg_consensus_equals_xsegment_then_dual(mods, tctx):
+    """SegConsensus (Alg. 3 and the dual update as one Function, one backward
+    pass) against XSegment followed by Dual: x' and L' bit for bit, and the
+    gradients of a random linear functional of both with respect to U, L, x and
+    (rho, eta) to 1e-6 (the float64 sums are added in another order)."""
+    T, AG = mods
+    rng = np.random.default_rng(13)
+    M, n = 4, 48
+    segs = synthdata.segment_rows(n, M)
+    owner = to_dev(np.concatenate([np.full(r, m) for m, (_, r) in enumerate(segs)]).astype(np.int32), torch.int32)
+    base = [to_dev(a) for a in (rng.standard_normal((M, n, n)), 0.3 * rng.standard_normal((M, n, n)),
+                                rng.standard_normal((n, n)), np.array([1.3, 0.004]))]
+    Wx, WL = to_dev(rng.standard_normal((n, n))), to_dev(rng.standard_normal((M, n, n)))
+    outs, grads = [], []
+    for fused in (True, False):
+        U, L, x, sc = (t.clone().requires_grad_(True) for t in base)
+        if fused:
+            xs, Lo = AG.SegConsensus.apply(U, L, x, sc, owner, tctx, 0.2, 7)
+        else:
+            xs = AG.XSegment.apply(U, L, x, sc, owner, tctx, 0.2, 7)
+            Lo = AG.Dual.apply(L, U, xs, sc, tctx)
+        ((xs * Wx).sum() + (Lo * WL).sum()).backward()
+        outs.append([xs.detach().cpu(), Lo.detach().cpu()])
+        grads.append([t.grad.cpu().numpy() for t in (U, L, x, sc)])
+    assert all(torch.equal(a, b) for a, b in zip(*outs))
+    for a, b in zip(*grads):
+        assert rel_l2(a, b) < 1e-6
