@@ -6,11 +6,13 @@ backprojection, u-step) per node, the segment x-update with the quantized
 exchange, and the dual update.  The iteration is launched in its batched form
 (one launch per kernel for all slices and nodes) and replayed from a HIP graph;
 inputs are resident on the device before timing starts.  Two forms of the
-captured iteration give bit-identical iterates: the sequential one, and the
+captured iteration give bit-identical iterates: the sequential one; the
 pipelined one, whose last part launches the next iteration's first projection
 (which reads only u and d) on a second stream, concurrently with the
-consensus; every step of either runs 5 projections, 5 backprojections and one
-consensus.  A few replays of each pick the faster, which is timed.  Workloads:
+consensus; and the alternating one, a graph of two pipelined iterations whose
+local updates alternate between the two streams.  Every step of each runs 5
+projections, 5 backprojections and one consensus.  A few replays of each pick
+the fastest, which is timed.  Workloads:
 
 * ``single`` (default): 512 x 512, 720 angles, 725 bins, 16 nodes with
   contiguous angle blocks, Poisson data at 1e5 photons, K-means with 8 levels;
@@ -515,36 +517,51 @@ def main():
         run.step()                       # builds the batched plans
     zero_all()
     torch.cuda.synchronize()
-    # the two forms of the captured iteration (bit-identical iterates): the
-    # sequential one, and the pipelined one whose next first projection runs
-    # concurrently with the consensus; a few replays of each pick the faster
-    graphs = {"sequential": run.capture(1), "pipelined": run.capture(1, pipelined=True)}
+    # the forms of the captured iteration (bit-identical iterates): the
+    # sequential one; the pipelined one, whose next first projection runs
+    # concurrently with the consensus on a second stream; and the alternating
+    # one (two iterations per graph, the local updates alternating between the
+    # two streams); a few replays of each pick the fastest
+    graphs = {"sequential": run.capture(1), "pipelined": run.capture(1, pipelined=True),
+              "alternating": run.capture(2, pipelined=True, alternate=True)}
+    per_replay = {"sequential": 1, "pipelined": 1, "alternating": 2}
+
+    def replay_iters(form, k):
+        """k iterations of a form (an odd one of the alternating form by the
+        pipelined graph, which keeps the same state convention)"""
+        if form == "alternating":
+            for _ in range(k // 2):
+                graphs[form].replay()
+            if k % 2:
+                graphs["pipelined"].replay()
+        else:
+            for _ in range(k):
+                graphs[form].replay()
+
     trial_us = {}
     for _ in range(2):                   # alternate the forms; each keeps its best round
         for form, g in graphs.items():
             zero_all()
-            if form == "pipelined":
+            if form != "sequential":
                 run.prime()
             g.replay()
             torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            n_trial = max(2, steps // 5)
+            n_trial = max(2, steps // 5 // per_replay[form])
             e0.record()
             for _ in range(n_trial):
                 g.replay()
             e1.record()
             torch.cuda.synchronize()
-            us = e0.elapsed_time(e1) / n_trial * 1e3
+            us = e0.elapsed_time(e1) / (n_trial * per_replay[form]) * 1e3
             trial_us[form] = min(us, trial_us.get(form, us))
     form = min(trial_us, key=trial_us.get)
-    graph = graphs[form]
     log(f"iteration graph: {form} (trial us per iteration: "
         + ", ".join(f"{k} {v:.1f}" for k, v in trial_us.items()) + ")")
     zero_all()
-    if form == "pipelined":
+    if form != "sequential":
         run.prime()
-    for _ in range(n_eq):
-        graph.replay()
+    replay_iters(form, n_eq)
     torch.cuda.synchronize()
     rmse_batched = [run.rmse(i) for i in range(n_slices)]
     identical = all(bool(torch.equal(xp, s.x)) for xp, s in zip(x_plain, slices))
@@ -552,15 +569,13 @@ def main():
     log(f"plain loop {n_slices / plain_s:.1f} slice-iterations/s, rmse[0] plain {rmse_plain[0]:.6g} "
         f"batched {rmse_batched[0]:.6g} identical={identical}")
 
-    # --- timed region: K replays of the one-iteration graph
-    for _ in range(args.warmup):
-        graph.replay()
+    # --- timed region: K iterations of the graph's form
+    replay_iters(form, args.warmup)
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        graph.replay()
+    replay_iters(form, steps)
     ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0

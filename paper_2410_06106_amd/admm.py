@@ -195,22 +195,64 @@ class DADMM:
             T.admm_local_phase(self.ctx, self.nodes, 0)
         main.wait_stream(side)
 
-    def capture(self, iters_per_graph=1, pipelined=False):
+    def step_pipelined_pair(self, a, b):
+        """Two pipelined iterations whose local updates alternate between streams
+        ``a`` and ``b`` (the first projection of the first was launched on ``a``
+        by prime() or the previous pair; call it with ``a`` current).  Each
+        next first projection runs on the other stream beside the consensus,
+        and that stream then carries the next local update: it waits for the
+        consensus only after its projection, when the consensus has usually
+        finished, so neither stream idles at that wait (the one-stream form
+        joins the side stream back at every iteration).  Bit-identical to
+        step()."""
+        if self.e1 < 1:
+            raise ValueError("the pipelined iteration needs E1 >= 1")
+        done = None
+        for s, other in ((a, b), (b, a)):
+            with torch.cuda.stream(s):
+                if done is not None:
+                    s.wait_event(done)                 # x and lambda of the last consensus
+                if self.regs is not None:
+                    T.admm_reg_update(self.ctx, self.nodes, self.regs)
+                T.admm_local_phase(self.ctx, self.nodes, 1)
+                for _ in range(self.e1 - 1):
+                    T.admm_local_phase(self.ctx, self.nodes, 0)
+                    T.admm_local_phase(self.ctx, self.nodes, 1)
+                ready = torch.cuda.Event()
+                ready.record(s)
+                # consensus first: its few large workgroups reach the CUs
+                # before the projector's fill them
+                self.consensus(self.nodes, self.msgs, self.regs)
+                done = torch.cuda.Event()
+                done.record(s)
+            other.wait_event(ready)
+            with torch.cuda.stream(other):
+                T.admm_local_phase(self.ctx, self.nodes, 0)
+        a.wait_event(done)
+
+    def capture(self, iters_per_graph=1, pipelined=False, alternate=False):
         """Capture ``iters_per_graph`` batched iterations into a HIP graph (after one
         uncaptured call has built the plans).  ``pipelined``: the iterations are
-        step_pipelined ones (fork/join inside the graph); call prime() before the
-        first replay and again whenever the state was reset."""
+        step_pipelined ones (fork/join inside the graph), or with ``alternate``
+        step_pipelined_pair ones (``iters_per_graph`` even); call prime() before
+        the first replay and again whenever the state was reset."""
+        if alternate and (not pipelined or iters_per_graph % 2):
+            raise ValueError("the alternating form is pipelined, two iterations at a time")
         g = torch.cuda.CUDAGraph()
         s = torch.cuda.Stream()
         side = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s):
             with torch.cuda.graph(g, stream=s):
-                for _ in range(iters_per_graph):
-                    if pipelined:
-                        self.step_pipelined(side)
-                    else:
-                        self.step()
+                if alternate:
+                    for _ in range(iters_per_graph // 2):
+                        self.step_pipelined_pair(s, side)
+                else:
+                    for _ in range(iters_per_graph):
+                        if pipelined:
+                            self.step_pipelined(side)
+                        else:
+                            self.step()
         torch.cuda.current_stream().wait_stream(s)
         self.graph = g
         return g

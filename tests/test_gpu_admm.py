@@ -279,6 +279,18 @@ def test_pipelined_iteration_matches_step(mods, ctx):
         got = [t.cpu() for s in slices for t in s.u + s.lam + [s.x]]
         assert all(torch.equal(a, b) for a, b in zip(got, eager[k])), f"pipelined replay {k} differs"
         log(f"  replay {k}: identical to step()")
+    # two iterations per graph, the local updates alternating between the streams
+    g2 = run.capture(2, pipelined=True, alternate=True)
+    _restore(slices, s0)
+    torch.cuda.synchronize()
+    run.prime()
+    for k in range(2):
+        g2.replay()
+        torch.cuda.synchronize()
+        _ = torch.ones(8, device="cuda").sum().item()
+        got = [t.cpu() for s in slices for t in s.u + s.lam + [s.x]]
+        assert all(torch.equal(a, b) for a, b in zip(got, eager[2 * k + 1])), f"alternating replay {k} differs"
+        log(f"  alternating replay {k}: identical to two step() calls")
 
 
 def test_dispatch_order_on_a_one_workgroup_plan(mods):

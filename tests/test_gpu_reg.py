@@ -241,8 +241,9 @@ def test_blocks_on_many_slices_batched_pipelined_and_plain_agree(mods, ctx):
     """Three slices of different sizes, each with a TV block (different
     iteration counts per z-update would not be expressible per slice here, so
     the blocks share them), K-means exchange: the plain per-slice loop, the
-    batched step and the pipelined graph (z-update beside the local update,
-    next projection beside the consensus) give the same iterates bit for bit."""
+    batched step, the pipelined graph (z-update beside the local update, next
+    projection beside the consensus) and the alternating two-iteration graph
+    give the same iterates bit for bit."""
     T, A = mods
     slices = []
     for i, (n, k, b, m) in enumerate([(96, 90, 136, 3), (64, 70, 91, 2), (128, 120, 182, 4)]):
@@ -252,12 +253,12 @@ def test_blocks_on_many_slices_batched_pipelined_and_plain_agree(mods, ctx):
         slices.append(s)
     run = A.DADMM(ctx, slices, quant=T.tomo_quant(T.TOMO_QUANT_KMEANS, 8, 30, 50),
                   reg=dict(kind=T.TOMO_REG_TV, mu=0.05, tv_iters=6))
-    for _ in range(3):
+    for _ in range(4):
         run.step_plain()
     plain = [t.cpu().clone() for s in slices for t in [s.x, s.reg["z"], s.reg["nu"]]]
     for s in slices:
         s.zero()
-    for _ in range(3):
+    for _ in range(4):
         run.step()
     got = [t.cpu() for s in slices for t in [s.x, s.reg["z"], s.reg["nu"]]]
     assert all(torch.equal(a, b) for a, b in zip(got, plain)), "batched step differs from the plain loop"
@@ -266,11 +267,21 @@ def test_blocks_on_many_slices_batched_pipelined_and_plain_agree(mods, ctx):
         s.zero()
     torch.cuda.synchronize()
     run.prime()
-    for _ in range(3):
+    for _ in range(4):
         g.replay()
     torch.cuda.synchronize()
     got = [t.cpu() for s in slices for t in [s.x, s.reg["z"], s.reg["nu"]]]
     assert all(torch.equal(a, b) for a, b in zip(got, plain)), "pipelined graph differs from the plain loop"
+    g2 = run.capture(2, pipelined=True, alternate=True)
+    for s in slices:
+        s.zero()
+    torch.cuda.synchronize()
+    run.prime()
+    for _ in range(2):
+        g2.replay()
+    torch.cuda.synchronize()
+    got = [t.cpu() for s in slices for t in [s.x, s.reg["z"], s.reg["nu"]]]
+    assert all(torch.equal(a, b) for a, b in zip(got, plain)), "alternating graph differs from the plain loop"
 
 
 def test_block_lowers_error_on_noisy_data(mods, ctx):
