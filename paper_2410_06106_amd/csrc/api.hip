@@ -344,7 +344,7 @@ struct ConsPlan {
   std::vector<tomo_node> key;
   std::vector<tomo_msg> msg_key;
   std::vector<tomo_reg> reg_key;
-  DevBuf seg, avg, noderefs, labels, kmjobs, kmwork, kmblocks, dctpart;
+  DevBuf seg, avg, noderefs, kmjobs, kmwork, kmblocks, dctpart;
   int dct_range_wgs = 0, dct_code_wgs = 0;   // DCT codec launches
   int dct_range_uni = 0, dct_code_uni = 0;   // workgroups of every job, when all jobs have the same (else 0)
   int n_seg = 0, n_avg = 0, avg_wgs = 0, dual_wgs = 0;
@@ -1063,15 +1063,14 @@ ConsPlan* get_cons_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, cons
     refs.push_back(ref);
   }
   // K-means jobs: segments that fit the registers first, then the longer ones,
-  // each with its own slice of the label scratch and of the workspace
+  // each with its own slice of the workspace (labels are written only where the
+  // caller asks for them)
   std::vector<KMJob> km_small, km_big;
   std::vector<KMBlock> kb_small, kb_big;
-  std::vector<size_t> label_off(n_nodes), work_off(n_nodes, 0);
-  size_t label_elems = 0, work_elems = 0;
+  std::vector<size_t> work_off(n_nodes, 0);
+  size_t work_elems = 0;
   for (int i = 0; i < n_nodes; ++i) {
     const long long segn = (long long)nodes[i].seg_rows * nodes[i].g.n;
-    label_off[i] = label_elems;
-    if (!(msg && msg[i].labels)) label_elems += (size_t)(segn + 255) / 256 * 256;
     if (segn > KM_LDS_VALUES) {
       work_off[i] = work_elems;
       work_elems += (size_t)(segn + 63) / 64 * 64;
@@ -1093,7 +1092,6 @@ ConsPlan* get_cons_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, cons
   }
   if (!plan->seg.ensure(seg.size() * sizeof(SegJob)) || !plan->avg.ensure(avg.size() * sizeof(AvgJob)) ||
       !plan->noderefs.ensure(refs.size() * sizeof(NodeRef)) ||
-      !plan->labels.ensure(std::max<size_t>(label_elems, 1)) ||
       !plan->kmjobs.ensure((size_t)n_nodes * sizeof(KMJob)) ||
       !plan->kmwork.ensure(work_elems * sizeof(float))) {
     rc = ctx->fail(TOMO_ENOMEM, "consensus plan allocation failed");
@@ -1116,7 +1114,7 @@ ConsPlan* get_cons_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, cons
     j.n = (long long)N.seg_rows * N.g.n;
     j.rho = N.rho;
     j.eta2 = N.eta2;
-    j.labels = (msg && msg[i].labels) ? msg[i].labels : static_cast<uint8_t*>(plan->labels.p) + label_off[i];
+    j.labels = msg ? msg[i].labels : nullptr;
     j.cent = msg ? msg[i].centroids : nullptr;
     j.iters = msg ? msg[i].iters : nullptr;
     j.xt = msg ? msg[i].x_tilde : nullptr;

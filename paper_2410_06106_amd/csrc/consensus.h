@@ -124,17 +124,33 @@ __host__ __device__ inline int tv_launch_iters(int T, int L, int l) {
   return T / L + (l < T % L ? 1 : 0);
 }
 
-// One Alg. 3 step x - eta2 rho (x - t_m), t_m = u + lambda/rho formed once per
-// value (reg_target); with a block's term x - eta2 (rho (x - t_m) + rho_z (x - t_z)).
-// Every fused multiply-add is explicit so that each kernel running a step
-// rounds the same way.
+// Alg. 3 on one value: E2 gradient steps x <- x - eta2 rho (x - t_m), t_m = u +
+// lambda/rho formed once per value (reg_target); with a block's term
+// x <- x - eta2 (rho (x - t_m) + rho_z (x - t_z)).  The objective is quadratic in
+// x, so the steps are a linear recurrence with factor a = 1 - eta2 s, s = rho
+// (+ rho_z), and E2 of them equal x + (1 - a^E2) (t - x) for the fixed point t
+// = (rho t_m + rho_z t_z) / s.  The kernels apply that closed form: without a
+// block x + q (t_m - x) with q = 1 - a^E2, with one x + c (rho (t_m - x) + rho_z
+// (t_z - x)) with c = q / s; the coefficients are formed once in float64 and
+// rounded to float32, and every kernel running the update rounds the same way.
+// E2 = 0 leaves x as it is (callers skip the update).
 __device__ __forceinline__ float reg_target(float uv, float lv, float irho) { return fmaf(lv, irho, uv); }
-__device__ __forceinline__ float xstep(float xv, float tm, float rho, float eta2) {
-  return fmaf(-eta2, rho * (xv - tm), xv);
+__device__ __forceinline__ double xseg_decay(double s, float eta2, int e2) {   // a^E2
+  const double a = 1.0 - (double)eta2 * s;
+  double p = 1.0;
+  for (int e = 0; e < e2; ++e) p *= a;
+  return p;
 }
-__device__ __forceinline__ float xstep_reg(float xv, float tm, float tv, float rho, float rho_z, float eta2) {
-  const float delta = fmaf(rho, xv - tm, rho_z * (xv - tv));
-  return fmaf(-eta2, delta, xv);
+__device__ __forceinline__ float xseg_q(float rho, float eta2, int e2) {
+  return (float)(1.0 - xseg_decay((double)rho, eta2, e2));
+}
+__device__ __forceinline__ float xseg_c(float rho, float rho_z, float eta2, int e2) {
+  const double s = (double)rho + (double)rho_z;
+  return (float)((1.0 - xseg_decay(s, eta2, e2)) / s);
+}
+__device__ __forceinline__ float xseg(float xv, float tm, float q) { return fmaf(q, tm - xv, xv); }
+__device__ __forceinline__ float xseg_reg(float xv, float tm, float tv, float rho, float rho_z, float c) {
+  return fmaf(c, fmaf(rho, tm - xv, rho_z * (tv - xv)), xv);
 }
 
 struct RegJob {

@@ -42,15 +42,11 @@ __device__ void segment_xupdate(const SegJob& S, int e2, float* xt) {
   const size_t base = (size_t)S.row0 * S.n;
   const size_t cnt = (size_t)S.rows * S.n;
   const float irho = 1.f / S.rho;
+  const float q = S.tz ? xseg_c(S.rho, S.rho_z, S.eta2, e2) : xseg_q(S.rho, S.eta2, e2);
   for (size_t i = threadIdx.x; i < cnt; i += NT) {
     float xv = S.x[base + i];
     const float tm = reg_target(S.u[base + i], S.lam[base + i], irho);
-    if (S.tz) {
-      const float tv = S.tz[base + i];
-      for (int e = 0; e < e2; ++e) xv = xstep_reg(xv, tm, tv, S.rho, S.rho_z, S.eta2);
-    } else {
-      for (int e = 0; e < e2; ++e) xv = xstep(xv, tm, S.rho, S.eta2);
-    }
+    if (e2 > 0) xv = S.tz ? xseg_reg(xv, tm, S.tz[base + i], S.rho, S.rho_z, q) : xseg(xv, tm, q);
     S.x[base + i] = xv;
     if (xt) xt[i] = xv;
   }
@@ -153,14 +149,10 @@ __global__ __launch_bounds__(DCT_THREADS) void k_dct_range(const SegJob* jobs, i
                    (!do_x || (al16(S.x) && al16(S.u) && al16(S.lam) && (!S.tz || al16(S.tz)) && (S.n & 3) == 0));
   float lo = INFINITY, hi = -INFINITY;
   int bad = 0;
+  const float xq = S.tz ? xseg_c(S.rho, S.rho_z, S.eta2, e2) : xseg_q(S.rho, S.eta2, e2);
   auto update = [&](float v, size_t i) {   // Alg. 3 on value v of x at index i of the slice
     const float tm = reg_target(S.u[i], S.lam[i], irho);
-    if (S.tz) {
-      const float tv = S.tz[i];
-      for (int e = 0; e < e2; ++e) v = xstep_reg(v, tm, tv, S.rho, S.rho_z, S.eta2);
-    } else {
-      for (int e = 0; e < e2; ++e) v = xstep(v, tm, S.rho, S.eta2);
-    }
+    if (e2 > 0) v = S.tz ? xseg_reg(v, tm, S.tz[i], S.rho, S.rho_z, xq) : xseg(v, tm, xq);
     return v;
   };
   auto fold = [&](float v) {
@@ -205,11 +197,7 @@ __global__ __launch_bounds__(DCT_THREADS) void k_dct_range(const SegJob* jobs, i
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
             const float tm = reg_target(uv[c], lv[c], irho);
-            if (S.tz) {
-              for (int e = 0; e < e2; ++e) v[c] = xstep_reg(v[c], tm, tv[c], S.rho, S.rho_z, S.eta2);
-            } else {
-              for (int e = 0; e < e2; ++e) v[c] = xstep(v[c], tm, S.rho, S.eta2);
-            }
+            if (e2 > 0) v[c] = S.tz ? xseg_reg(v[c], tm, tv[c], S.rho, S.rho_z, xq) : xseg(v[c], tm, xq);
           }
           if (ok[q]) *(__attribute__((address_space(1))) f4*)gas(S.x + ix[q]) = a[q];
         }

@@ -62,18 +62,15 @@ __device__ __forceinline__ int km_fixed(float v, int S) {
   return (int)rintf(ldexpf(v, S));     // exact scaling, round half to even
 }
 
-__device__ __forceinline__ float km_xupdate(float xv, float uv, float lv, float rho, float irho, float eta2,
-                                            int e2) {
-  const float tm = reg_target(uv, lv, irho);
-  for (int e = 0; e < e2; ++e) xv = xstep(xv, tm, rho, eta2);
-  return xv;
+// Alg. 3 on one value (closed form, coefficient q; E2 = 0 leaves it as it is)
+__device__ __forceinline__ float km_xupdate(float xv, float uv, float lv, float irho, float q, int e2) {
+  return e2 > 0 ? xseg(xv, reg_target(uv, lv, irho), q) : xv;
 }
 
 // the same with a regularization block's target t_z and penalty rho_z
-__device__ __forceinline__ float km_xupdate_reg(float xv, float tm, float tv, float rho, float rho_z, float eta2,
+__device__ __forceinline__ float km_xupdate_reg(float xv, float tm, float tv, float rho, float rho_z, float c,
                                                 int e2) {
-  for (int e = 0; e < e2; ++e) xv = xstep_reg(xv, tm, tv, rho, rho_z, eta2);
-  return xv;
+  return e2 > 0 ? xseg_reg(xv, tm, tv, rho, rho_z, c) : xv;
 }
 
 // Largest float32 below a finite x.
@@ -200,8 +197,9 @@ __device__ __forceinline__ int group_sum(int v, int G) {
 // Count and code sum of the values a <= x for the threshold x of a group of G
 // lanes (every lane of the wave active; the G lanes of a group hold the same
 // x): the buckets left of x's bucket from the prefix tables, plus the values of
-// that bucket at or below x, which the group's lanes read G apart and add up
-// with butterflies.  Every lane of the group gets the totals.
+// that bucket at or below x, which the group's lanes read G apart (four reads
+// in flight per trip) and add up with butterflies.  Every lane of the group
+// gets the totals.
 template <class VP>
 __device__ __forceinline__ void group_at_or_below(const KMShared& sh, VP V, float x, const Buckets& bk, float lo,
                                                   float hi, int n, long long tot, int S, int G, int& cnt,
@@ -221,17 +219,16 @@ __device__ __forceinline__ void group_at_or_below(const KMShared& sh, VP V, floa
   }
   int c = 0;
   long long s = 0;
-  for (int p = p0 + sub; p < p1; p += 2 * G) {   // two reads per trip, both in flight
-    const float a0 = V[p];
-    const float a1 = V[min(p + G, p1 - 1)];
-    if (a0 <= x) {
-      ++c;
-      s += km_fixed(a0, S);
-    }
-    if (p + G < p1 && a1 <= x) {
-      ++c;
-      s += km_fixed(a1, S);
-    }
+  for (int p = p0 + sub; p < p1; p += 4 * G) {   // four reads per trip, all in flight
+    float a[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) a[r] = V[min(p + r * G, p1 - 1)];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (p + r * G < p1 && a[r] <= x) {
+        ++c;
+        s += km_fixed(a[r], S);
+      }
   }
   cnt = c0 + group_sum(c, G);
   sum = s0 + group_sum(s, G);
@@ -282,6 +279,7 @@ __global__ __launch_bounds__(KT) void k_kmeans(const KMJob* jobs, KMJob single, 
   const int n = (int)J.n;
   const bool do_x = J.u != nullptr;
   const float irho = 1.f / J.rho;
+  const float xq = do_x ? xseg_q(J.rho, J.eta2, e2) : 0.f;
   const auto src = gptr(J.src);
   const auto xo = gptr(J.x);
   const auto ahat = gptr(J.a_hat);
@@ -345,6 +343,7 @@ __global__ __launch_bounds__(KT) void k_kmeans(const KMJob* jobs, KMJob single, 
       const KMBlock RB = (TZ && blocks) ? blocks[seg] : KMBlock{nullptr, 0.f};
       if (TZ && RB.tz) {
         const auto tzz = gptr(RB.tz);
+        const float xc = xseg_c(J.rho, RB.rho_z, J.eta2, e2);
         // t_m = u + lambda/rho into the u registers, then t_z into the lambda
         // registers (no more values in flight than without the block)
 #pragma unroll
@@ -356,14 +355,14 @@ __global__ __launch_bounds__(KT) void k_kmeans(const KMJob* jobs, KMJob single, 
 #pragma unroll
         for (int e = 0; e < KVPT; ++e) {
           const long long i = base + tid + (long long)e * KT;
-          a[e] = km_xupdate_reg(a[e], uv[e], lv[e], J.rho, RB.rho_z, J.eta2, e2);
+          a[e] = km_xupdate_reg(a[e], uv[e], lv[e], J.rho, RB.rho_z, xc, e2);
           if (!REG && i < n) xo[i] = a[e];   // re-read by the later passes
         }
       } else {
 #pragma unroll
         for (int e = 0; e < KVPT; ++e) {
           const long long i = base + tid + (long long)e * KT;
-          a[e] = km_xupdate(a[e], uv[e], lv[e], J.rho, irho, J.eta2, e2);
+          a[e] = km_xupdate(a[e], uv[e], lv[e], irho, xq, e2);
           if (!REG && i < n) xo[i] = a[e];   // re-read by the later passes
         }
       }

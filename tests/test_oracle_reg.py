@@ -110,6 +110,18 @@ def test_segment_update_with_block_tends_to_weighted_target():
     np.testing.assert_allclose(out, ref, atol=1e-7)
 
 
+def test_segment_update_with_block_closed_form():
+    """E2 steps on the block's quadratic: a linear recurrence with factor
+    1 - eta2 (rho + rho_z) towards the rho-weighted mean of the two targets."""
+    rng = np.random.default_rng(6)
+    x, u, lam, tz = (rng.standard_normal((3, 7)) for _ in range(4))
+    rho, rho_z, eta2 = 0.8, 0.3, 0.25
+    t = (rho * (u + lam / rho) + rho_z * tz) / (rho + rho_z)
+    for e2 in (0, 1, 3, 10):
+        ref = t + (1 - eta2 * (rho + rho_z)) ** e2 * (x - t)
+        np.testing.assert_allclose(reg.x_update_segment(x, u, lam, rho, tz, rho_z, eta2, e2), ref, atol=1e-14)
+
+
 def _tiny_problem(n=6, n_ang=8, nodes=2, seed=5):
     rng = np.random.default_rng(seed)
     th = np.sort(rng.uniform(0, np.pi, n_ang))
