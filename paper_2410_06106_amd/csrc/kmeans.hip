@@ -154,14 +154,6 @@ __device__ __forceinline__ long long dpp_add_i64(long long v) {
   return v + (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
-__device__ __forceinline__ long long group_sum(long long v, int G) {
-  if (G >= 2) v = dpp_add_i64<0xB1>(v);
-  if (G >= 4) v = dpp_add_i64<0x4E>(v);
-  if (G >= 8) v = dpp_add_i64<0x141>(v);
-  if (G >= 16) v = dpp_add_i64<0x140>(v);
-  return v;
-}
-
 __device__ __forceinline__ long long wave_sum_i64(long long v) {
   v = dpp_add_i64<0xB1>(v);    // quad_perm [1, 0, 3, 2]: pairs
   v = dpp_add_i64<0x4E>(v);    // quad_perm [2, 3, 0, 1]: quads
@@ -175,36 +167,64 @@ __device__ __forceinline__ long long wave_sum_i64(long long v) {
   return lane(0) + lane(16) + lane(32) + lane(48);
 }
 
-// Value of lane `src` (an explicit cross-lane permute, ds_bpermute); every
-// lane of the wave must be active, since a permute reads zero from an inactive
-// lane.
-__device__ __forceinline__ int lane_from(int v, int src) { return __builtin_amdgcn_ds_bpermute(src << 2, v); }
-__device__ __forceinline__ float lane_from(float v, int src) { return __int_as_float(lane_from(__float_as_int(v), src)); }
-__device__ __forceinline__ long long lane_from(long long v, int src) {
-  const unsigned lo = (unsigned)lane_from((int)v, src), hi = (unsigned)lane_from((int)(v >> 32), src);
+// Cross-lane moves of the Lloyd loop (every lane of the wave active).  Lane
+// l of the wave holds group l % KP (KP a power of two): the previous group's
+// lane is l - 1 and the next group's l + 1, one DPP wave shift away; the
+// lanes of one group are KP apart, and their sum reaches every one of them by
+// rotations within rows of 16 lanes (distances below 16), then the swaps of
+// row pairs and of wave halves (v_permlane16_swap / v_permlane32_swap, whose
+// two results add up to the lane's own value plus its partner's).  Integer
+// adds, so exact in any order.
+template <int CTRL>
+__device__ __forceinline__ int dpp_mov(int v) { return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false); }
+template <int CTRL>
+__device__ __forceinline__ long long dpp_mov(long long v) {
+  const unsigned lo = (unsigned)dpp_mov<CTRL>((int)v), hi = (unsigned)dpp_mov<CTRL>((int)(v >> 32));
   return (long long)(((unsigned long long)hi << 32) | lo);
 }
+__device__ __forceinline__ int from_prev(int v) { return dpp_mov<0x138>(v); }        // wave_shr:1
+__device__ __forceinline__ long long from_prev(long long v) { return dpp_mov<0x138>(v); }
+__device__ __forceinline__ float from_next(float v) { return __int_as_float(dpp_mov<0x130>(__float_as_int(v))); }   // wave_shl:1
 
-// Sums over aligned groups of G lanes (G = 1, 2, 4, 8 or 16; all lanes active),
-// returned to every lane of the group: butterflies within rows of 16 lanes.
-__device__ __forceinline__ int group_sum(int v, int G) {
-  if (G >= 2) v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);    // quad_perm [1, 0, 3, 2]
-  if (G >= 4) v += __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);    // quad_perm [2, 3, 0, 1]
-  if (G >= 8) v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);   // row_half_mirror
-  if (G >= 16) v += __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false);  // row_mirror
+__device__ __forceinline__ int pair_sum16(int v) {
+  const auto p = __builtin_amdgcn_permlane16_swap((unsigned)v, (unsigned)v, false, false);
+  return (int)(p[0] + p[1]);
+}
+__device__ __forceinline__ int pair_sum32(int v) {
+  const auto p = __builtin_amdgcn_permlane32_swap((unsigned)v, (unsigned)v, false, false);
+  return (int)(p[0] + p[1]);
+}
+__device__ __forceinline__ long long pair_sum16(long long v) {
+  const auto a = __builtin_amdgcn_permlane16_swap((unsigned)v, (unsigned)v, false, false);
+  const auto b = __builtin_amdgcn_permlane16_swap((unsigned)(v >> 32), (unsigned)(v >> 32), false, false);
+  return (long long)((((unsigned long long)b[0] << 32) | a[0]) + (((unsigned long long)b[1] << 32) | a[1]));
+}
+__device__ __forceinline__ long long pair_sum32(long long v) {
+  const auto a = __builtin_amdgcn_permlane32_swap((unsigned)v, (unsigned)v, false, false);
+  const auto b = __builtin_amdgcn_permlane32_swap((unsigned)(v >> 32), (unsigned)(v >> 32), false, false);
+  return (long long)((((unsigned long long)b[0] << 32) | a[0]) + (((unsigned long long)b[1] << 32) | a[1]));
+}
+template <int KP, typename T>
+__device__ __forceinline__ T strided_sum(T v) {
+  if constexpr (KP <= 1) v += dpp_mov<0x121>(v);   // row_ror:1
+  if constexpr (KP <= 2) v += dpp_mov<0x122>(v);   // row_ror:2
+  if constexpr (KP <= 4) v += dpp_mov<0x124>(v);   // row_ror:4
+  if constexpr (KP <= 8) v += dpp_mov<0x128>(v);   // row_ror:8
+  if constexpr (KP <= 16) v = pair_sum16(v);
+  if constexpr (KP <= 32) v = pair_sum32(v);
   return v;
 }
-// Count and code sum of the values a <= x for the threshold x of a group of G
-// lanes (every lane of the wave active; the G lanes of a group hold the same
-// x): the buckets left of x's bucket from the prefix tables, plus the values of
-// that bucket at or below x, which the group's lanes read G apart (four reads
-// in flight per trip) and add up with butterflies.  Every lane of the group
-// gets the totals.
-template <class VP>
+
+// Count and code sum of the values a <= x for the threshold x of a group (its
+// 64 / KP lanes hold the same x; `sub` is the lane's index in the group): the
+// buckets left of x's bucket from the prefix tables, plus the values of that
+// bucket at or below x, which the group's lanes read 64 / KP apart (four reads
+// in flight per trip).  Every lane of the group gets the totals.
+template <int KP, class VP>
 __device__ __forceinline__ void group_at_or_below(const KMShared& sh, VP V, float x, const Buckets& bk, float lo,
-                                                  float hi, int n, long long tot, int S, int G, int& cnt,
+                                                  float hi, int n, long long tot, int S, int sub, int& cnt,
                                                   long long& sum) {
-  const int sub = (threadIdx.x & 63) & (G - 1);
+  constexpr int G = 64 / KP;
   int c0 = 0, p0 = 0, p1 = 0;
   long long s0 = 0;
   if (x >= hi) {
@@ -230,8 +250,71 @@ __device__ __forceinline__ void group_at_or_below(const KMShared& sh, VP V, floa
         s += km_fixed(a[r], S);
       }
   }
-  cnt = c0 + group_sum(c, G);
-  sum = s0 + group_sum(s, G);
+  cnt = c0 + strided_sum<KP>(c);
+  sum = s0 + strided_sum<KP>(s);
+}
+
+// Lloyd iterations for k <= KP <= 64 in one wave (wave 0 of the workgroup),
+// with no barrier inside the loop.  Group j (lanes j, j + KP, ...) holds
+// centre j and, for j < k - 1, the threshold between centres j and j + 1,
+// whose count and code sum at or below it the group's lanes find together.
+// Cluster j is the values between thresholds j - 1 and j: its totals take the
+// previous group's from the lane one below.  Groups from k - 1 up hold no
+// threshold (+inf: all n values, the total code sum).  Every cross-lane
+// operation runs with all 64 lanes active.  Returns the iterations run; the
+// final centres and thresholds go to sh.cent and sh.thr.
+template <int KP, class VP>
+__device__ int lloyd_wave(KMShared& sh, VP V, const Buckets& bk, float lo, float hi, int n, long long tot, int S,
+                          int k, int max_iter) {
+  const int l = threadIdx.x & 63;
+  const int grp = l & (KP - 1), sub = l / KP;
+  const bool has_c = grp < k, has_t = grp < k - 1;
+  float cj = has_c ? sh.cent[grp] : 0.f;
+  const float c1 = from_next(cj);
+  float xt = has_t ? threshold((double)cj + (double)c1) : INFINITY;
+  int prev = 0, it = 0;
+  for (int t = 0;; ++t) {
+    int cb;
+    long long sb;
+    group_at_or_below<KP>(sh, V, xt, bk, lo, hi, n, tot, S, sub, cb, sb);
+    if (t > 0) {
+      it = t;
+      if (__ballot(has_t && cb != prev) == 0) break;   // no label changed
+    }
+    if (t == max_iter) break;
+    prev = cb;
+    // centres of the current labels, then their stable sort: when they are
+    // already non-decreasing the sort is the identity; otherwise every group
+    // finds its stable rank (the groups' first lanes broadcast one at a time)
+    // and picks the centre ranked grp
+    const int cprev = from_prev(cb);
+    const long long sprev = from_prev(sb);
+    const int c = has_c ? cb - (grp > 0 ? cprev : 0) : 0;
+    const long long q = sb - (grp > 0 ? sprev : 0);
+    float u = cj;
+    if (c > 0) u = (float)(ldexp((double)q, -S) / (double)c);
+    float un = from_next(u);
+    if (__ballot(grp + 1 < k && un < u) == 0) {
+      cj = u;
+    } else {
+      int r = 0;
+      for (int i = 0; i < k; ++i) {
+        const float ui = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(u), i));
+        r += (ui < u) || (ui == u && i < grp);
+      }
+      for (int i = 0; i < k; ++i) {
+        const float ui = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(u), i));
+        cj = __builtin_amdgcn_readlane(r, i) == grp ? ui : cj;
+      }
+      un = from_next(cj);
+    }
+    xt = has_t ? threshold((double)cj + (double)un) : INFINITY;
+  }
+  if (sub == 0) {
+    if (has_c) sh.cent[grp] = cj;
+    if (has_t) sh.thr[grp] = xt;
+  }
+  return it;
 }
 
 // Count and code sum of the values a <= x, by one wave (every lane active and
@@ -458,65 +541,19 @@ __global__ __launch_bounds__(KT) void k_kmeans(const KMJob* jobs, KMJob single, 
 
   int it = 0;
   if (k <= 64) {
-    // Lloyd iterations in wave 0 alone, with no barrier inside the loop.  The
-    // wave is cut into k groups of G lanes (G <= 16, G k <= 64): group j holds
-    // centre j and, for j < k - 1, the threshold between centres j and j + 1,
-    // whose count and code sum at or below it the group's lanes find together.
-    // Cluster j is the values between thresholds j - 1 and j; its totals take
-    // the previous group's by a permute.  Groups from k - 1 up hold no
-    // threshold (+inf: all n values, the total code sum).  Every cross-lane
-    // operation runs with all 64 lanes active.
+    // Lloyd iterations in wave 0 alone (lloyd_wave), groups of 64 / KP lanes
     if (w == 0) {
-      int G = 16;
-      while (G > 1 && G * k > 64) G >>= 1;
-      const int grp = l / G;
-      const bool has_c = grp < k, has_t = grp < k - 1;
-      float cj = has_c ? sh.cent[grp] : 0.f;
-      const float c1 = lane_from(cj, min(l + G, 63));
-      float xt = has_t ? threshold((double)cj + (double)c1) : INFINITY;
-      int prev = 0;
-      for (int t = 0;; ++t) {
-        int cb;
-        long long sb;
-        if constexpr (REG) group_at_or_below(sh, vlds, xt, bk, lo, hi, n, tot, S, G, cb, sb);
-        else group_at_or_below(sh, gptr((const float*)wv), xt, bk, lo, hi, n, tot, S, G, cb, sb);
-        if (t > 0) {
-          it = t;
-          if (__ballot(has_t && cb != prev) == 0) break;   // no label changed
-        }
-        if (t == max_iter) break;
-        prev = cb;
-        // centres of the current labels, then their stable sort: when they are
-        // already non-decreasing the sort is the identity; otherwise every group
-        // finds its stable rank (the groups' first lanes broadcast one at a
-        // time) and picks the centre ranked grp
-        const int cprev = lane_from(cb, max(l - G, 0));
-        const long long sprev = lane_from(sb, max(l - G, 0));
-        const int c = has_c ? cb - (grp > 0 ? cprev : 0) : 0;
-        const long long q = sb - (grp > 0 ? sprev : 0);
-        float u = cj;
-        if (c > 0) u = (float)(ldexp((double)q, -S) / (double)c);
-        float un = lane_from(u, min(l + G, 63));
-        if (__ballot(grp + 1 < k && un < u) == 0) {
-          cj = u;
-        } else {
-          int r = 0;
-          for (int i = 0; i < k; ++i) {
-            const float ui = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(u), i * G));
-            r += (ui < u) || (ui == u && i < grp);
-          }
-          for (int i = 0; i < k; ++i) {
-            const float ui = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(u), i * G));
-            cj = __builtin_amdgcn_readlane(r, i * G) == grp ? ui : cj;
-          }
-          un = lane_from(cj, min(l + G, 63));
-        }
-        xt = has_t ? threshold((double)cj + (double)un) : INFINITY;
-      }
-      if ((l & (G - 1)) == 0) {
-        if (has_c) sh.cent[grp] = cj;
-        if (has_t) sh.thr[grp] = xt;
-      }
+      auto run = [&](auto V) {
+        if (k <= 1) return lloyd_wave<1>(sh, V, bk, lo, hi, n, tot, S, k, max_iter);
+        if (k <= 2) return lloyd_wave<2>(sh, V, bk, lo, hi, n, tot, S, k, max_iter);
+        if (k <= 4) return lloyd_wave<4>(sh, V, bk, lo, hi, n, tot, S, k, max_iter);
+        if (k <= 8) return lloyd_wave<8>(sh, V, bk, lo, hi, n, tot, S, k, max_iter);
+        if (k <= 16) return lloyd_wave<16>(sh, V, bk, lo, hi, n, tot, S, k, max_iter);
+        if (k <= 32) return lloyd_wave<32>(sh, V, bk, lo, hi, n, tot, S, k, max_iter);
+        return lloyd_wave<64>(sh, V, bk, lo, hi, n, tot, S, k, max_iter);
+      };
+      if constexpr (REG) it = run(static_cast<const float*>(vlds));
+      else it = run(gptr((const float*)wv));
     }
     __syncthreads();
   } else {
