@@ -5,14 +5,15 @@ workload: E1 = 5 local steps (Joseph projection, residual, matched
 backprojection, u-step) per node, the segment x-update with the quantized
 exchange, and the dual update.  The iteration is launched in its batched form
 (one launch per kernel for all slices and nodes) and replayed from a HIP graph;
-inputs are resident on the device before timing starts.  Two forms of the
+inputs are resident on the device before timing starts.  Three forms of the
 captured iteration give bit-identical iterates: the sequential one; the
 pipelined one, whose last part launches the next iteration's first projection
 (which reads only u and d) on a second stream, concurrently with the
-consensus; and the alternating one, a graph of two pipelined iterations whose
-local updates alternate between the two streams.  Every step of each runs 5
-projections, 5 backprojections and one consensus.  A few replays of each pick
-the fastest, which is timed.  Workloads:
+consensus; and the alternating one, pipelined iterations whose local updates
+alternate between the two streams.  Every step of each runs 5 projections, 5
+backprojections and one consensus.  A graph holds several iterations (10 for
+the single workload: each replay costs a few microseconds of launch overhead).
+A few replays of each form pick the fastest, which is timed.  Workloads:
 
 * ``single`` (default): 512 x 512, 720 angles, 725 bins, 16 nodes with
   contiguous angle blocks, Poisson data at 1e5 photons, K-means with 8 levels;
@@ -54,8 +55,11 @@ PHASE_KERNELS = {"project": "projection phase: k_project + k_project_reduce",
                  "backproject": "backprojection phase: k_backproject"}
 KERNEL_SOURCES = ("paper_2410_06106_amd/csrc/project.hip", "paper_2410_06106_amd/csrc/project_res.hip",
                   "paper_2410_06106_amd/csrc/backproject.hip", "paper_2410_06106_amd/csrc/common.h")
-DEFAULT_STEPS = {"single": 100, "batch": 5, "large": 10, "diff": 4}
+DEFAULT_STEPS = {"single": 500, "batch": 5, "large": 10, "diff": 4}
 EQUAL_RMSE_STEPS = {"single": 5, "batch": 2, "large": 2, "diff": 0}
+# ADMM iterations captured per graph replay (a replay costs a few us of launch
+# overhead, which matters at the 0.6 ms iteration of the single workload only)
+ITERS_PER_GRAPH = {"single": 10, "batch": 1, "large": 2, "diff": 1}
 
 
 def _source_sha(paths):
@@ -520,23 +524,23 @@ def main():
     # the forms of the captured iteration (bit-identical iterates): the
     # sequential one; the pipelined one, whose next first projection runs
     # concurrently with the consensus on a second stream; and the alternating
-    # one (two iterations per graph, the local updates alternating between the
-    # two streams); a few replays of each pick the fastest
-    graphs = {"sequential": run.capture(1), "pipelined": run.capture(1, pipelined=True),
-              "alternating": run.capture(2, pipelined=True, alternate=True)}
-    per_replay = {"sequential": 1, "pipelined": 1, "alternating": 2}
+    # one (the local updates alternating between the two streams).  Each graph
+    # holds ITERS_PER_GRAPH iterations (a replay costs a few us of launch
+    # overhead); one-iteration graphs of the sequential and pipelined forms
+    # cover a remainder.  A few replays of each form pick the fastest.
+    G = ITERS_PER_GRAPH[args.workload]
+    graphs = {"sequential": run.capture(G), "pipelined": run.capture(G, pipelined=True)}
+    if G % 2 == 0:
+        graphs["alternating"] = run.capture(G, pipelined=True, alternate=True)
+    single = {"sequential": run.capture(1), "pipelined": run.capture(1, pipelined=True)}
 
     def replay_iters(form, k):
-        """k iterations of a form (an odd one of the alternating form by the
-        pipelined graph, which keeps the same state convention)"""
-        if form == "alternating":
-            for _ in range(k // 2):
-                graphs[form].replay()
-            if k % 2:
-                graphs["pipelined"].replay()
-        else:
-            for _ in range(k):
-                graphs[form].replay()
+        """k iterations of a form: whole graphs, then one-iteration graphs (the
+        pipelined one for both pipelined forms, which share its state convention)"""
+        for _ in range(k // G):
+            graphs[form].replay()
+        for _ in range(k % G):
+            single["sequential" if form == "sequential" else "pipelined"].replay()
 
     trial_us = {}
     for _ in range(2):                   # alternate the forms; each keeps its best round
@@ -547,13 +551,13 @@ def main():
             g.replay()
             torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            n_trial = max(2, steps // 5 // per_replay[form])
+            n_trial = max(2, steps // 5 // G)
             e0.record()
             for _ in range(n_trial):
                 g.replay()
             e1.record()
             torch.cuda.synchronize()
-            us = e0.elapsed_time(e1) / (n_trial * per_replay[form]) * 1e3
+            us = e0.elapsed_time(e1) / (n_trial * G) * 1e3
             trial_us[form] = min(us, trial_us.get(form, us))
     form = min(trial_us, key=trial_us.get)
     log(f"iteration graph: {form} (trial us per iteration: "
@@ -683,7 +687,7 @@ def main():
         "batching": batching,
         "kmeans_lloyd_iters_last_step": lloyd,
         "projector_tiles": tiles,
-        "iteration_graph": {"form": form, "trial_us": trial_us},
+        "iteration_graph": {"form": form, "iterations_per_graph": G, "trial_us": trial_us},
         "regularization": zinfo,
         "phases_us": dict({k: v * 1e3 for k, v in kern.items()}, consensus=consensus_us),
         "roofline": {"bound": "alu", "kernel": PHASE_KERNELS[dom], "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
