@@ -55,7 +55,9 @@ PHASE_KERNELS = {"project": "projection phase: k_project + k_project_reduce",
                  "backproject": "backprojection phase: k_backproject"}
 KERNEL_SOURCES = ("paper_2410_06106_amd/csrc/project.hip", "paper_2410_06106_amd/csrc/project_res.hip",
                   "paper_2410_06106_amd/csrc/backproject.hip", "paper_2410_06106_amd/csrc/common.h")
-DEFAULT_STEPS = {"single": 500, "batch": 5, "large": 10, "diff": 4}
+DEFAULT_STEPS = {"single": 2000, "batch": 5, "large": 10, "diff": 4}
+# untimed warm-up steps; for the single workload one whole graph (see below)
+DEFAULT_WARMUP = {"single": 10, "batch": 3, "large": 3, "diff": 3}
 EQUAL_RMSE_STEPS = {"single": 5, "batch": 2, "large": 2, "diff": 0}
 # ADMM iterations captured per graph replay (a replay costs a few us of launch
 # overhead, which matters at the 0.6 ms iteration of the single workload only)
@@ -378,7 +380,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="single", choices=("single", "batch", "large", "diff"))
     ap.add_argument("--plain-steps", type=int, default=None)
     ap.add_argument("--kernel-reps", type=int, default=20)
@@ -409,6 +411,8 @@ def main():
               "(no multi-GPU path is built); run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
     steps = args.steps if args.steps is not None else DEFAULT_STEPS[args.workload]
+    if args.warmup is None:
+        args.warmup = DEFAULT_WARMUP[args.workload]
     n_eq = args.plain_steps if args.plain_steps is not None else EQUAL_RMSE_STEPS[args.workload]
 
     import numpy as np
