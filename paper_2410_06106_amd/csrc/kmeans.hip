@@ -104,6 +104,68 @@ __device__ __forceinline__ __attribute__((address_space(1))) T* gptr(T* p) {
   return (__attribute__((address_space(1))) T*)p;
 }
 
+// Cross-lane moves by DPP (every lane of the wave active): lane l reads the
+// value of another lane of the wave, 0 where the pattern has no source lane.
+template <int CTRL>
+__device__ __forceinline__ int dpp_mov(int v) { return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false); }
+template <int CTRL>
+__device__ __forceinline__ long long dpp_mov(long long v) {
+  const unsigned lo = (unsigned)dpp_mov<CTRL>((int)v), hi = (unsigned)dpp_mov<CTRL>((int)(v >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) { return __int_as_float(dpp_mov<CTRL>(__float_as_int(v))); }
+__device__ __forceinline__ long long lane_value(long long v, int i) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)v, i);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(v >> 32), i);
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ int lane_value(int v, int i) { return __builtin_amdgcn_readlane(v, i); }
+
+// Inclusive prefix sum over the 64 lanes of a wave (every lane active):
+// shifted adds within rows of 16 lanes (row_shr 1, 2, 4, 8), then each row
+// adds the totals of the rows below it (their last lanes, read as scalars).
+// Integer adds, so exact in any order.
+template <typename T>
+__device__ __forceinline__ T wave_scan(T v) {
+  v += dpp_mov<0x111>(v);   // row_shr:1
+  v += dpp_mov<0x112>(v);   // row_shr:2
+  v += dpp_mov<0x114>(v);   // row_shr:4
+  v += dpp_mov<0x118>(v);   // row_shr:8
+  const T r0 = lane_value(v, 15), r1 = lane_value(v, 31), r2 = lane_value(v, 47);
+  const int l = threadIdx.x & 63;
+  if (l >= 16) v += r0;
+  if (l >= 32) v += r1;
+  if (l >= 48) v += r2;
+  return v;
+}
+
+// Min, max and OR over the 64 lanes of a wave, to every lane: rotations within
+// rows of 16 lanes, then the row pairs and the wave halves (v_permlane16_swap,
+// v_permlane32_swap: the lane's own value and its partner's).
+__device__ __forceinline__ float swap16(float v, bool mx) {
+  const auto p = __builtin_amdgcn_permlane16_swap((unsigned)__float_as_int(v), (unsigned)__float_as_int(v), false, false);
+  const float a = __int_as_float((int)p[0]), b = __int_as_float((int)p[1]);
+  return mx ? fmaxf(a, b) : fminf(a, b);
+}
+__device__ __forceinline__ float swap32(float v, bool mx) {
+  const auto p = __builtin_amdgcn_permlane32_swap((unsigned)__float_as_int(v), (unsigned)__float_as_int(v), false, false);
+  const float a = __int_as_float((int)p[0]), b = __int_as_float((int)p[1]);
+  return mx ? fmaxf(a, b) : fminf(a, b);
+}
+__device__ __forceinline__ void wave_range(float& lo, float& hi, int& bad) {
+  lo = fminf(lo, dpp_mov<0x121>(lo)); hi = fmaxf(hi, dpp_mov<0x121>(hi)); bad |= dpp_mov<0x121>(bad);   // row_ror:1
+  lo = fminf(lo, dpp_mov<0x122>(lo)); hi = fmaxf(hi, dpp_mov<0x122>(hi)); bad |= dpp_mov<0x122>(bad);   // row_ror:2
+  lo = fminf(lo, dpp_mov<0x124>(lo)); hi = fmaxf(hi, dpp_mov<0x124>(hi)); bad |= dpp_mov<0x124>(bad);   // row_ror:4
+  lo = fminf(lo, dpp_mov<0x128>(lo)); hi = fmaxf(hi, dpp_mov<0x128>(hi)); bad |= dpp_mov<0x128>(bad);   // row_ror:8
+  lo = swap16(lo, false); hi = swap16(hi, true);
+  lo = swap32(lo, false); hi = swap32(hi, true);
+  const auto b16 = __builtin_amdgcn_permlane16_swap((unsigned)bad, (unsigned)bad, false, false);
+  bad = (int)(b16[0] | b16[1]);
+  const auto b32 = __builtin_amdgcn_permlane32_swap((unsigned)bad, (unsigned)bad, false, false);
+  bad = (int)(b32[0] | b32[1]);
+}
+
 // Exclusive prefix of the B bucket counts and code sums, in place; entry B
 // receives the totals.
 __device__ void bucket_scan(KMShared& sh, int B) {
@@ -120,13 +182,8 @@ __device__ void bucket_scan(KMShared& sh, int B) {
     ct += c[r];
     st += s[r];
   }
-  int ic = ct;
-  long long is = st;
-  for (int o = 1; o < 64; o <<= 1) {
-    const int oc = __shfl_up(ic, o, 64);
-    const long long os = __shfl_up(is, o, 64);
-    if (l >= o) { ic += oc; is += os; }
-  }
+  const int ic = wave_scan(ct);
+  const long long is = wave_scan(st);
   if (l == 63) { sh.wcnt[w] = ic; sh.wsum[w] = is; }
   __syncthreads();
   int ec = ic - ct;
@@ -175,13 +232,6 @@ __device__ __forceinline__ long long wave_sum_i64(long long v) {
 // row pairs and of wave halves (v_permlane16_swap / v_permlane32_swap, whose
 // two results add up to the lane's own value plus its partner's).  Integer
 // adds, so exact in any order.
-template <int CTRL>
-__device__ __forceinline__ int dpp_mov(int v) { return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false); }
-template <int CTRL>
-__device__ __forceinline__ long long dpp_mov(long long v) {
-  const unsigned lo = (unsigned)dpp_mov<CTRL>((int)v), hi = (unsigned)dpp_mov<CTRL>((int)(v >> 32));
-  return (long long)(((unsigned long long)hi << 32) | lo);
-}
 __device__ __forceinline__ int from_prev(int v) { return dpp_mov<0x138>(v); }        // wave_shr:1
 __device__ __forceinline__ long long from_prev(long long v) { return dpp_mov<0x138>(v); }
 __device__ __forceinline__ float from_next(float v) { return __int_as_float(dpp_mov<0x130>(__float_as_int(v))); }   // wave_shl:1
@@ -375,6 +425,10 @@ __global__ __launch_bounds__(KT) void k_kmeans(const KMJob* jobs, KMJob single, 
     if (J.iters && tid == 0) *J.iters = 0;
     return;
   }
+  // the bucket tables are cleared first, while the first pass's loads are in
+  // flight (the barrier after the range reduction orders them before use)
+  const int B = min(KBUCKETS, max(1, n / 4));
+  for (int b = tid; b < B; b += KT) { sh.start[b] = 0; sh.fill[b] = 0; sh.psum[b] = 0; }
 
   // every value once, KVPT per thread at a time: from registers (REG) or
   // loaded from the segment after the x-update
@@ -466,11 +520,7 @@ __global__ __launch_bounds__(KT) void k_kmeans(const KMJob* jobs, KMJob single, 
     }
     if constexpr (REG) break;   // n <= KT * KVPT: one chunk
   }
-  for (int o = 32; o > 0; o >>= 1) {
-    lo = fminf(lo, __shfl_xor(lo, o, 64));
-    hi = fmaxf(hi, __shfl_xor(hi, o, 64));
-    bad |= __shfl_xor(bad, o, 64);
-  }
+  wave_range(lo, hi, bad);
   if (l == 0) { sh.red[2 * w] = lo; sh.red[2 * w + 1] = hi; sh.redb[w] = bad; }
   __syncthreads();
   lo = sh.red[0];
@@ -496,11 +546,9 @@ __global__ __launch_bounds__(KT) void k_kmeans(const KMJob* jobs, KMJob single, 
   int e;
   frexp(fmax(fabs((double)lo), fabs((double)hi)), &e);
   const int S = 30 - e;
-  const int B = min(KBUCKETS, max(1, n / 4));
   const Buckets bk{lo, (float)B / (hi - lo), (float)(B - 1)};
 
   // pass 2: bucket counts and code sums
-  for (int b = tid; b < B; b += KT) { sh.start[b] = 0; sh.fill[b] = 0; sh.psum[b] = 0; }
   if (tid < k) {
     double lo64 = lo, hi64 = hi;
     double t = (hi64 - lo64) * (double)(2 * tid + 1);
