@@ -102,14 +102,19 @@ int tomo_release(tomo_ctx* ctx);
  *                           band-streamed projector and computes positions in
  *                           float64 (about twice the cost).
  *   TOMO_OPT_PROJ_ORDER     dispatch order of the band-streamed projector
- *                           of admm_local_update / admm_local_phase: with 1
- *                           (default), a launch of at most 8 workgroups per
- *                           compute unit starts its workgroups in an order
- *                           the plan derives from a cost it estimates from
- *                           the node angles (read back to the host once, when
- *                           the plan is built): per die, largest first;
- *                           larger launches, and 0, keep node order.  Results
- *                           are bit-identical for both values.
+ *                           of admm_local_update / admm_local_phase: with 1,
+ *                           a launch of at most 8 workgroups per compute
+ *                           unit starts its workgroups in an order the plan
+ *                           derives from a cost it estimates from the node
+ *                           angles (read back to the host once, when the
+ *                           plan is built): per die, largest first; with 2
+ *                           (default), the same with all workgroups of a node
+ *                           on one die, and, when every die then receives the
+ *                           same number of them, the node's region-reduction
+ *                           and backprojector workgroups on that die too (its
+ *                           partial sums, residual and image stay in that
+ *                           die's L2 cache); larger launches, and 0, keep node
+ *                           order.  Results are bit-identical for all values.
  */
 enum {
   TOMO_OPT_PROJ_JOB_WGS = 1,

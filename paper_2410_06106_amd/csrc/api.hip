@@ -235,10 +235,14 @@ constexpr int kOrderMaxWgsPerCu = 8;   // largest launch (workgroups per CU) giv
 // table order), so that a compute unit receives a mix of heavy and light
 // workgroups and the longest ones do not trail at the end; (3) the lists are
 // interleaved: blockIdx b takes entry b / n_xcc of the list of die b % n_xcc.
+// With `per_node` the groups are whole jobs (every region and angle chunk of
+// a node), and job_die receives the die each job starts on, so that the
+// region reduction and the backprojection of that node can run there too.
 // Needs the angles on the host; returns false (and the launch keeps table
 // order) when they cannot be read.
 bool band_order(const tomo_node* nodes, int n_nodes, const std::vector<ProjShape>& shapes,
-                const std::vector<ProjJob>& pj, int R, int chord, int n_xcc, std::vector<int2>& order) {
+                const std::vector<ProjJob>& pj, int R, int chord, int n_xcc, bool per_node,
+                std::vector<int2>& order, std::vector<int>& job_die) {
   std::vector<float> cost;
   std::vector<int2> ent;
   std::vector<std::vector<int>> groups;
@@ -255,6 +259,16 @@ bool band_order(const tomo_node* nodes, int n_nodes, const std::vector<ProjShape
     band_costs(ang.data(), nodes[i].n_ang, nodes[i].g.n, nodes[i].g.n_bins, shapes[i], R, chord, cost);
     for (int k = c0; k < (int)cost.size(); ++k) ent.push_back(make_int2(i, k - c0));
     const int G = shapes[i].regions();
+    if (per_node) {
+      groups.emplace_back();
+      double sum = 0.0;
+      for (int k = c0; k < (int)cost.size(); ++k) {
+        groups.back().push_back(k);
+        sum += cost[k];
+      }
+      gcost.push_back(sum);
+      continue;
+    }
     for (int g = 0; g < G; ++g) {
       groups.emplace_back();
       double sum = 0.0;
@@ -273,6 +287,7 @@ bool band_order(const tomo_node* nodes, int n_nodes, const std::vector<ProjShape
   std::vector<double> load(nx, 0.0);
   std::vector<int> room(nx);
   for (int x = 0; x < nx; ++x) room[x] = T / nx + (x < T % nx ? 1 : 0);   // workgroups b with b % nx == x
+  job_die.assign(n_nodes, -1);
   for (int g : gi) {
     size_t k = 0;
     while (k < groups[g].size()) {
@@ -280,6 +295,8 @@ bool band_order(const tomo_node* nodes, int n_nodes, const std::vector<ProjShape
       for (int x = 0; x < nx; ++x)
         if (room[x] > 0 && (best < 0 || load[x] < load[best])) best = x;
       if (best < 0) return false;
+      const int job = ent[groups[g][k]].x;
+      if (job_die[job] < 0) job_die[job] = best;
       for (; k < groups[g].size() && room[best] > 0; ++k) {
         die[best].push_back(groups[g][k]);
         load[best] += cost[groups[g][k]];
@@ -292,6 +309,25 @@ bool band_order(const tomo_node* nodes, int n_nodes, const std::vector<ProjShape
     std::stable_sort(die[x].begin(), die[x].end(), [&](int a, int b) { return cost[a] > cost[b]; });
     for (size_t k = 0; k < die[x].size(); ++k) order[k * nx + x] = ent[die[x][k]];
   }
+  return true;
+}
+
+// Dispatch order that runs the workgroups of job i (wgs[i] of them, in job
+// order) on die job_die[i]: each die's list interleaved as in band_order.
+// Only when every die receives the same number of workgroups (a launch has no
+// holes); returns false otherwise, and the launch keeps table order.
+bool die_order(const std::vector<int>& wgs, const std::vector<int>& job_die, int n_xcc, std::vector<int2>& order) {
+  const int nx = std::max(1, n_xcc);
+  std::vector<std::vector<int2>> die(nx);
+  for (size_t i = 0; i < wgs.size(); ++i) {
+    if (job_die[i] < 0 || job_die[i] >= nx) return false;
+    for (int w = 0; w < wgs[i]; ++w) die[job_die[i]].push_back(make_int2((int)i, w));
+  }
+  for (int x = 1; x < nx; ++x)
+    if (die[x].size() != die[0].size()) return false;
+  order.resize(die[0].size() * nx);
+  for (int x = 0; x < nx; ++x)
+    for (size_t k = 0; k < die[x].size(); ++k) order[k * nx + x] = die[x][k];
   return true;
 }
 
@@ -334,6 +370,8 @@ struct LocalPlan {
   DevBuf pjobs, rjobs, bjobs, resid, partial, bbase;
   DevBuf order;                  // band projector dispatch order (int2 per workgroup), if built
   bool ordered = false;
+  DevBuf rorder, border;         // reduction and backprojector orders (same die per node), if built
+  bool r_ordered = false, b_ordered = false;
   int n_p = 0, p_wgs = 0, n_r = 0, r_wgs = 0, n_b = 0, b_wgs = 0;
   int band = 16;                 // projector band depth (16 or 32)
   bool resident = false;         // region-resident projector (k_project_res)
@@ -387,7 +425,8 @@ struct tomo_ctx {
   int proj_band = 32;         // TOMO_OPT_PROJ_BAND
   int proj_kernel = 0;        // TOMO_OPT_PROJ_KERNEL
   int model = 0;              // TOMO_OPT_PROJ_MODEL (0 Joseph, 1 chord lengths)
-  int proj_order = 1;         // TOMO_OPT_PROJ_ORDER (0 table order, 1 estimated cost, largest first)
+  int proj_order = 2;         // TOMO_OPT_PROJ_ORDER (0 table order, 1 estimated cost, largest first,
+                              // 2 the same with each node's workgroups of every local-update kernel on one die)
   std::string err;
   DevBuf partial;                                // standalone projector workspace
   DevBuf pbbase;                                 // standalone projector: region bin bases
@@ -613,18 +652,50 @@ LocalPlan* get_local_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, in
     return nullptr;
   }
   std::vector<int2> ord;
+  std::vector<int> job_die;
+  auto upload = [&](DevBuf& buf, const std::vector<int2>& o) {
+    return buf.ensure(o.size() * sizeof(int2)) &&
+           hipMemcpy(buf.p, o.data(), o.size() * sizeof(int2), hipMemcpyHostToDevice) == hipSuccess;
+  };
   // with many workgroups per CU the hardware's dynamic dispatch evens out the
   // load and table order keeps the angle chunks of one region together in
   // time (shared reads in L2); the table pays off for launches of a few waves
-  if (!resident && ctx->proj_order == 1 && pw <= kOrderMaxWgsPerCu * ctx->n_cu &&
-      band_order(nodes, n_nodes, shapes, pj, ctx->proj_band, ctx->model, ctx->n_xcc, ord) &&
+  if (!resident && ctx->proj_order >= 1 && pw <= kOrderMaxWgsPerCu * ctx->n_cu &&
+      band_order(nodes, n_nodes, shapes, pj, ctx->proj_band, ctx->model, ctx->n_xcc, ctx->proj_order == 2, ord,
+                 job_die) &&
       (int)ord.size() == pw) {
-    if (!plan->order.ensure(ord.size() * sizeof(int2)) ||
-        hipMemcpy(plan->order.p, ord.data(), ord.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess) {
+    if (!upload(plan->order, ord)) {
       rc = ctx->fail(TOMO_EDEVICE, "dispatch order upload failed");
       return nullptr;
     }
     plan->ordered = true;
+    if (ctx->proj_order == 2) {
+      // the node's partials, residual and image stay in its die's L2: its
+      // reduction and backprojection workgroups run on that die as well
+      std::vector<int> rwgs, rdie, bwgs;
+      for (int i = 0; i < n_nodes; ++i) {
+        if (shapes[i].regions() > 1) {
+          rwgs.push_back(reduce_wgs(shapes[i], nodes[i].g.n_bins));
+          rdie.push_back(job_die[i]);
+        }
+        bwgs.push_back(bj[i].tiles_x * bj[i].tiles_x);
+      }
+      std::vector<int2> ro, bo;
+      if (!rj.empty() && die_order(rwgs, rdie, ctx->n_xcc, ro) && (int)ro.size() == rw) {
+        if (!upload(plan->rorder, ro)) {
+          rc = ctx->fail(TOMO_EDEVICE, "dispatch order upload failed");
+          return nullptr;
+        }
+        plan->r_ordered = true;
+      }
+      if (die_order(bwgs, job_die, ctx->n_xcc, bo) && (int)bo.size() == bw) {
+        if (!upload(plan->border, bo)) {
+          rc = ctx->fail(TOMO_EDEVICE, "dispatch order upload failed");
+          return nullptr;
+        }
+        plan->b_ordered = true;
+      }
+    }
   }
   plan->n_r = (int)rj.size();
   plan->r_wgs = rw;
@@ -648,6 +719,7 @@ struct ProjLaunch {
   const ProjJob* pjobs = nullptr;
   const ProjJob* rjobs = nullptr;
   const int2* order = nullptr;   // band kernel dispatch order or null
+  const int2* rorder = nullptr;  // reduction dispatch order or null
   int n_p = 0, p_wgs = 0, n_r = 0, r_wgs = 0;
   int band = 32;
   bool resident = false, chord = false;
@@ -658,6 +730,7 @@ ProjLaunch launch_of(const LocalPlan* plan) {
   L.pjobs = static_cast<const ProjJob*>(plan->pjobs.p);
   L.rjobs = static_cast<const ProjJob*>(plan->rjobs.p);
   L.order = plan->ordered ? static_cast<const int2*>(plan->order.p) : nullptr;
+  L.rorder = plan->r_ordered ? static_cast<const int2*>(plan->rorder.p) : nullptr;
   L.n_p = plan->n_p;
   L.p_wgs = plan->p_wgs;
   L.n_r = plan->n_r;
@@ -692,6 +765,7 @@ void launch_projection(const ProjLaunch& L, void* stream) {
   }
   if (L.n_r > 0) {
     Many<ProjJob> rs{L.rjobs, L.n_r};
+    rs.order = L.rorder;
     hipLaunchKernelGGL(k_project_reduce<Many<ProjJob>>, dim3(L.r_wgs), dim3(PTHREADS), 0, (hipStream_t)stream, rs);
   }
 }
@@ -1226,7 +1300,7 @@ int tomo_set_option(tomo_ctx* ctx, int32_t option, int64_t value) {
       ctx->model = (int)value;
       break;
     case TOMO_OPT_PROJ_ORDER:
-      if (value != 0 && value != 1) return ctx->fail(TOMO_EINVAL, "projector order must be 0 or 1");
+      if (value < 0 || value > 2) return ctx->fail(TOMO_EINVAL, "projector order must be 0, 1 or 2");
       ctx->proj_order = (int)value;
       break;
     default:
@@ -1388,6 +1462,7 @@ int admm_local_update(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, in
   }
   if (!plan) return rc;
   Many<BPJob> bs{static_cast<const BPJob*>(plan->bjobs.p), plan->n_b};
+  if (plan->b_ordered) bs.order = static_cast<const int2*>(plan->border.p);
   for (int e = 0; e < e1; ++e) {
     launch_projection(launch_of(plan), stream);
     launch_backproject(bs, plan->b_wgs, plan->chord, stream);
@@ -1411,6 +1486,7 @@ int admm_local_phase(tomo_ctx* ctx, const tomo_node* nodes, int32_t n_nodes, int
     launch_projection(launch_of(plan), stream);
   } else {
     Many<BPJob> bs{static_cast<const BPJob*>(plan->bjobs.p), plan->n_b};
+    if (plan->b_ordered) bs.order = static_cast<const int2*>(plan->border.p);
     launch_backproject(bs, plan->b_wgs, plan->chord, stream);
   }
   return launch_status(ctx, "admm_local_phase");

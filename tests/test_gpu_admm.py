@@ -291,14 +291,29 @@ def test_pipelined_iteration_matches_step(mods, ctx):
         got = [t.cpu() for s in slices for t in s.u + s.lam + [s.x]]
         assert all(torch.equal(a, b) for a, b in zip(got, eager[2 * k + 1])), f"alternating replay {k} differs"
         log(f"  alternating replay {k}: identical to two step() calls")
+    # several pipelined iterations per graph (the benchmark's form), then one
+    # one-iteration replay continuing from its state
+    g3 = run.capture(3, pipelined=True)
+    _restore(slices, s0)
+    torch.cuda.synchronize()
+    run.prime()
+    g3.replay()
+    torch.cuda.synchronize()
+    got = [t.cpu() for s in slices for t in s.u + s.lam + [s.x]]
+    assert all(torch.equal(a, b) for a, b in zip(got, eager[2])), "three-iteration pipelined replay differs"
+    g.replay()
+    torch.cuda.synchronize()
+    got = [t.cpu() for s in slices for t in s.u + s.lam + [s.x]]
+    assert all(torch.equal(a, b) for a, b in zip(got, eager[3])), "one-iteration replay after it differs"
+    log("  three-iteration graph, then a one-iteration one: identical to step()")
 
 
 def test_dispatch_order_on_a_one_workgroup_plan(mods):
     """A plan of fewer projector workgroups than dies (one 8 x 8 node, 3
-    angles: one workgroup) in both dispatch orders: the same local update."""
+    angles: one workgroup) in every dispatch order: the same local update."""
     T, A = mods
     out = []
-    for order in (0, 1):
+    for order in (0, 1, 2):
         c = T.Context(0)
         T.tomo_set_option(c, T.TOMO_OPT_PROJ_ORDER, order)
         w = synthdata.Workload("one", 4, 8, 3, 12, 1, "interleaved", 3, "gaussian", 0.01, 2)
@@ -307,18 +322,20 @@ def test_dispatch_order_on_a_one_workgroup_plan(mods):
         T.admm_local_update(c, A.DADMM(c, [s]).nodes, 3)
         torch.cuda.synchronize()
         out.append(s.u[0].cpu().clone())
-    assert torch.equal(out[0], out[1]) and out[0].abs().max() > 0
+    assert torch.equal(out[0], out[1]) and torch.equal(out[0], out[2]) and out[0].abs().max() > 0
 
 
 def test_dispatch_order_does_not_change_results(mods):
     """The batched projector started in estimated-cost order
-    (TOMO_OPT_PROJ_ORDER = 1, the default) and in node order (0) gives the same
-    ADMM iterates bit for bit: nodes split into several regions, ragged last
-    angle chunks, uneven node sizes in one call."""
+    (TOMO_OPT_PROJ_ORDER = 1), in node order (0) and in cost order with each
+    node's workgroups on one die (2, the default) gives the same ADMM iterates bit
+    for bit: nodes split into several regions, ragged last angle chunks, uneven
+    node sizes in one call (the reduction and backprojection keep table order
+    there: their dies would receive unequal counts)."""
     T, A = mods
     shapes = [(300, 150, 425, 3), (96, 70, 136, 5), (200, 90, 283, 2)]
     out = []
-    for order in (0, 1):
+    for order in (0, 1, 2):
         c = T.Context(0)
         T.tomo_set_option(c, T.TOMO_OPT_PROJ_ORDER, order)
         T.tomo_set_option(c, T.TOMO_OPT_PROJ_JOB_WGS, 48)
@@ -333,6 +350,29 @@ def test_dispatch_order_does_not_change_results(mods):
             run.step()
         out.append([t.cpu().numpy().copy() for s in slices for t in s.u + s.lam + [s.x]])
         log(f"  order {order}: |x| max {max(float(np.abs(a).max()) for a in out[-1]):.4g}")
+    for o in out[1:]:
+        for a, b in zip(out[0], o):
+            np.testing.assert_array_equal(a, b)
+    assert all(np.isfinite(a).all() for a in out[0])
+
+
+def test_node_die_order_does_not_change_results(mods):
+    """Eight equal nodes split into 2 x 2 regions: with TOMO_OPT_PROJ_ORDER = 2
+    each node's projector, reduction and backprojector workgroups run on one
+    die (every die gets the same count, so all three orders are built); the
+    ADMM iterates equal those of the cost order without it (1) bit for bit."""
+    T, A = mods
+    out = []
+    for order in (1, 2):
+        c = T.Context(0)
+        T.tomo_set_option(c, T.TOMO_OPT_PROJ_ORDER, order)
+        w = synthdata.Workload("die8", 3, 300, 160, 425, 8, "contiguous", 6, "gaussian", 0.01, 4)
+        s = A.make_slice(c, w)
+        s.eta1 = A.step_size(c, s, 1.0, 0.1)
+        run = A.DADMM(c, [s], quant=T.tomo_quant(T.TOMO_QUANT_KMEANS, 8, 30, 50))
+        for _ in range(2):
+            run.step()
+        out.append([t.cpu().numpy().copy() for t in s.u + s.lam + [s.x]])
     for a, b in zip(*out):
         np.testing.assert_array_equal(a, b)
-    assert all(np.isfinite(a).all() for a in out[0])
+    assert all(np.isfinite(a).all() for a in out[0]) and max(float(np.abs(a).max()) for a in out[0]) > 0

@@ -134,7 +134,7 @@ def test_projector_launch_options_match_oracle(T, kernel, band, job_wgs):
 def test_set_option_rejects_bad_values(T):
     c = T.Context(0)
     for opt, bad in ((T.TOMO_OPT_PROJ_BAND, 8), (T.TOMO_OPT_PROJ_BAND, 64), (T.TOMO_OPT_PROJ_JOB_WGS, 0),
-                     (T.TOMO_OPT_PROJ_KERNEL, 2), (T.TOMO_OPT_PROJ_MODEL, 2), (T.TOMO_OPT_PROJ_ORDER, 2),
+                     (T.TOMO_OPT_PROJ_KERNEL, 2), (T.TOMO_OPT_PROJ_MODEL, 2), (T.TOMO_OPT_PROJ_ORDER, 3),
                      (T.TOMO_OPT_PROJ_ORDER, -1), (2, 1), (99, 1)):
         with pytest.raises(T.TomoError):
             T.tomo_set_option(c, opt, bad)
