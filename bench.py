@@ -53,8 +53,11 @@ PEAK_FP32_SINGLE_ISSUE_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 PEAK_HBM_GBS = 8000.0
 PHASE_KERNELS = {"project": "projection phase: k_project + k_project_reduce",
                  "backproject": "backprojection phase: k_backproject"}
+# sources whose change invalidates a traffic record: the kernels, and the
+# plan code that sets their launch shapes and dispatch orders
 KERNEL_SOURCES = ("paper_2410_06106_amd/csrc/project.hip", "paper_2410_06106_amd/csrc/project_res.hip",
-                  "paper_2410_06106_amd/csrc/backproject.hip", "paper_2410_06106_amd/csrc/common.h")
+                  "paper_2410_06106_amd/csrc/backproject.hip", "paper_2410_06106_amd/csrc/common.h",
+                  "paper_2410_06106_amd/csrc/api.hip")
 DEFAULT_STEPS = {"single": 2000, "batch": 5, "large": 10, "diff": 4}
 # untimed warm-up steps; for the single workload one whole graph (see below)
 DEFAULT_WARMUP = {"single": 10, "batch": 3, "large": 3, "diff": 3}
