@@ -99,6 +99,25 @@ def test_projector_full_size_sampled_angles(T, ctx):
     assert rel_l2(got_b, joseph.backproject(sino, th_all[pick], n)) <= 1e-5
 
 
+def test_projector_maximum_image_side(T, ctx):
+    """The largest image the boundary accepts (4096 x 4096; the detector spans
+    the diagonal, 5794 bins): projection of 7 angles, three of them (0, 30 and
+    45 degrees, where the driving axis and the slope differ) checked against the
+    oracle, and the backprojection of those three."""
+    rng = np.random.default_rng(12)
+    n = 4096
+    nb = int(np.ceil(np.sqrt(2.0) * n)) + 1
+    th_all = np.array([0.0, 0.3, np.pi / 6, 1.1, np.pi / 4, 2.0, 2.9])
+    pick = np.array([0, 2, 4])
+    img = rng.random((n, n)).astype(np.float32)
+    got = T.tomo_project(ctx, to_dev(th_all, torch.float64), to_dev(img), nb).cpu().numpy()
+    ref = joseph.project(img, th_all[pick], nb)
+    assert rel_l2(got[pick], ref) <= 1e-5
+    sino = rng.standard_normal((pick.size, nb)).astype(np.float32)
+    got_b = T.tomo_backproject(ctx, to_dev(th_all[pick], torch.float64), to_dev(sino), n).cpu().numpy()
+    assert rel_l2(got_b, joseph.backproject(sino, th_all[pick], n)) <= 1e-5
+
+
 @pytest.mark.parametrize("kernel,band,job_wgs", [(0, 16, 1), (0, 16, 64), (0, 16, 4096), (0, 32, 1),
                                                   (0, 32, 64), (0, 32, 4096), (1, 32, 16)])
 def test_projector_launch_options_match_oracle(T, kernel, band, job_wgs):
@@ -173,6 +192,10 @@ KM_CASES = [  # (n, k, distribution)
     (1, 4, "normal"), (7, 3, "normal"), (1000, 16, "normal"), (1024, 16, "uniform"),
     (16384, 8, "normal"), (5000, 3, "three"), (4097, 1, "uniform"), (3000, 256, "normal"),
     (65536, 16, "mixture"), (100003, 8, "ties"), (64, 5, "const"),
+    # one value past the register-resident size (the workspace path), and a
+    # level count for each lane-group width of the one-wave Lloyd loop (64 / kp
+    # lanes per level, kp = k rounded up to a power of two: 2, 32, 64)
+    (16385, 8, "normal"), (2000, 2, "normal"), (6000, 20, "mixture"), (9000, 40, "normal"), (12000, 64, "uniform"),
 ]
 
 
