@@ -314,6 +314,32 @@ def test_local_update_matches_oracle(T, ctx):
         assert rel_l2(U[m].cpu().numpy(), ref) <= 1e-5
 
 
+def test_local_update_maximum_image_side(T, ctx):
+    """One Alg. 2 step of a single 4096 x 4096 node (6 angles, 5794 bins)
+    through the batched plan: 256 regions of 256 x 256 per angle chunk, the
+    projector's workgroups spread over every die while the region reduction
+    and backprojection keep table order (their dies would receive unequal
+    counts).  The increment u - u0 matches the oracle's to 1e-4 rel-L2."""
+    rng = np.random.default_rng(13)
+    n = 4096
+    nb = int(np.ceil(np.sqrt(2.0) * n)) + 1
+    th = np.sort(rng.uniform(0.0, np.pi, 6))
+    u0 = rng.random((n, n)).astype(np.float32)
+    x = rng.random((n, n)).astype(np.float32)
+    lam = (0.01 * rng.standard_normal((n, n))).astype(np.float32)
+    d = (1000.0 * rng.random((th.size, nb))).astype(np.float32)
+    rho, eta1 = 1.0, 1e-5
+    U = to_dev(u0)
+    nodes = T.make_nodes([dict(n=n, n_bins=nb, angles=to_dev(th, torch.float64), slice=0, d=to_dev(d), u=U,
+                               lam=to_dev(lam), x=to_dev(x), seg_row0=0, seg_rows=n, rho=rho, eta1=eta1,
+                               eta2=0.2)])
+    T.admm_local_update(ctx, nodes, 1)
+    got = U.cpu().numpy().astype(np.float64) - u0
+    ref = oadmm.local_update(u0, x, lam, d, th, rho, eta1, 1) - u0
+    assert np.abs(ref).max() > 1e-3
+    assert rel_l2(got, ref) <= 1e-4
+
+
 @pytest.mark.parametrize("mode", ["seg", "avg"])
 def test_consensus_without_quantizer_matches_oracle(T, ctx, mode):
     n, M = 48, 3
