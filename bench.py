@@ -28,7 +28,11 @@ of the batched graph and of the plain per-slice, per-node launch loop, and the
 RMSE of every slice after the same iterations in both forms (identical by
 construction: a node's work decomposes the same way alone or batched); the
 projector tiles picked by the autotuner; per-phase durations, the ALU roofline
-of the projection phase and its HBM traffic.
+of the projection phase and its HBM traffic; and, untimed, the reconstruction
+RMSE against the phantom after 50, 100 and 200 iterations with the segment and
+the averaging x-update (the timed configuration, segment-owned updates over
+contiguous angle blocks, does not reconstruct this phantom; the averaging form
+on the same data and kernels shows what the kernels reach).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload single|batch|large]
                     [--no-cpu-baseline] [--no-autotune] [--profile-kernels]
@@ -405,6 +409,8 @@ def main():
                          "(default: one per step)")
     ap.add_argument("--no-batch-line", action="store_true",
                     help="skip the batching workload's batched-vs-plain comparison of the default run")
+    ap.add_argument("--no-quality", action="store_true",
+                    help="skip the untimed reconstruction-quality trajectories of the single workload")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only launch the projector and backprojector of the workload a few times, and a "
                          "device copy of known size (for counter runs); prints their launch counts")
@@ -596,6 +602,26 @@ def main():
     rmse_final = [run.rmse(i) for i in range(n_slices)]
     log(f"batched graph: {ms_per_step:.3f} ms/iteration, {value:.4g} updates/s, rmse[0] {rmse_final[0]:.6g}")
 
+    # --- reconstruction quality on the same data (untimed): RMSE against the
+    # phantom after 50, 100 and 200 plain iterations from zero, with the timed
+    # form's segment x-update and with the averaging x-update of Eq. 9 (same
+    # kernels, same quantizer and step sizes)
+    quality = None
+    if args.workload == "single" and not args.no_quality:
+        quality = {"iterations": [50, 100, 200]}
+        for name, mode in (("segment", T.TOMO_XUPDATE_SEGMENT), ("average", T.TOMO_XUPDATE_AVERAGE)):
+            rq = A.DADMM(ctx, slices, rho=1.0, eta2=0.2, e1=5, e2=10, mode=mode, quant=q, msgs=None, reg=reg)
+            zero_all()
+            traj, k = [], 0
+            for target in quality["iterations"]:
+                while k < target:
+                    rq.step()
+                    k += 1
+                traj.append(rq.rmse(0))
+            quality[name] = traj
+        log(f"reconstruction RMSE after {quality['iterations']} iterations: segment {quality['segment']}, "
+            f"average {quality['average']}")
+
     # --- local-update phases: average duration with HIP events on the launch stream
     kern = {}
     for phase, name in ((0, "project"), (1, "backproject")):
@@ -691,6 +717,7 @@ def main():
         "equal_rmse": {"iterations": n_eq, "bit_identical": identical, "max_rel_rmse_diff": max(rel),
                        "plain_slice0": rmse_plain[0], "batched_slice0": rmse_batched[0]},
         "rmse_after_timed_steps": {"slice0": rmse_final[0], "mean": float(np.mean(rmse_final))},
+        "reconstruction": quality,
         "batching": batching,
         "kmeans_lloyd_iters_last_step": lloyd,
         "projector_tiles": tiles,
