@@ -111,10 +111,10 @@ int tomo_release(tomo_ctx* ctx);
  *                           (default), the same with all workgroups of a node
  *                           on one die, and, when every die then receives the
  *                           same number of them, the node's region-reduction
- *                           and backprojector workgroups on that die too (its
- *                           partial sums, residual and image stay in that
- *                           die's L2 cache); larger launches, and 0, keep node
- *                           order.  Results are bit-identical for all values.
+ *                           and backprojector workgroups on that die too (each
+ *                           die then reads the data of its own nodes only);
+ *                           larger launches, and 0, keep node order.  Results
+ *                           are bit-identical for all values.
  */
 enum {
   TOMO_OPT_PROJ_JOB_WGS = 1,

@@ -670,8 +670,8 @@ LocalPlan* get_local_plan(tomo_ctx* ctx, const tomo_node* nodes, int n_nodes, in
     }
     plan->ordered = true;
     if (ctx->proj_order == 2) {
-      // the node's partials, residual and image stay in its die's L2: its
-      // reduction and backprojection workgroups run on that die as well
+      // each die reads only its own nodes' partials, residuals and images:
+      // a node's reduction and backprojection workgroups run on its die too
       std::vector<int> rwgs, rdie, bwgs;
       for (int i = 0; i < n_nodes; ++i) {
         if (shapes[i].regions() > 1) {
