@@ -24,12 +24,13 @@
 // code sum at or below a threshold are then the prefix of the buckets left of
 // the threshold's bucket plus that one bucket's share: a Lloyd iteration costs
 // k - 1 bucket scans instead of a pass over every value, and "no label
-// changed" is "no boundary count changed".  For k <= 64 a Lloyd iteration
-// takes one workgroup barrier: the waves scan the buckets of different
-// thresholds in parallel, and each keeps all k centres in its lanes and
-// updates them from the shared counts.  Segments of up to 16384 values stay in
-// registers from the first pass to the last, where labels and quantized values
-// are written.  The optional Alg. 3 x-update of the segment is applied on load.
+// changed" is "no boundary count changed".  For k <= 64 the Lloyd iterations
+// run in one wave with no barrier: a group of lanes per threshold scans its
+// bucket, and neighbouring groups exchange totals and centres through DPP
+// shifts and lane swaps (lloyd_wave); larger k use every wave and a barrier per
+// step.  Segments of up to 16384 values stay in registers from the first pass
+// to the last, where labels and quantized values are written.  The optional
+// Alg. 3 x-update of the segment (its closed form) is applied on load.
 #include "consensus.h"
 
 namespace tomo {
