@@ -422,6 +422,38 @@ def test_argument_errors_are_reported(T, ctx):
                                   out=sino[8:16].view(1, 8))
 
 
+def test_empty_and_out_of_range_sizes(T, ctx):
+    """Sizes at and past the boundary's documented limits: an empty K-means
+    input and k outside [1, 256] are rejected, packing zero labels is a no-op
+    and bits outside [1, 8] are rejected, an image side above 4096 is refused,
+    and so is an empty node list; none of them launches a kernel, and the
+    context stays usable afterwards."""
+    with pytest.raises(T.TomoError):
+        T.quantize_kmeans(ctx, torch.zeros(0, dtype=torch.float32, device="cuda"), 4)
+    b = torch.rand(100, device="cuda")
+    for k in (0, 257):
+        with pytest.raises(T.TomoError):
+            T.quantize_kmeans(ctx, b, k)
+    out = T.tomo_pack_labels(ctx, torch.zeros(0, dtype=torch.uint8, device="cuda"), 3)
+    assert out.numel() == 0
+    for bits in (0, 9):
+        with pytest.raises(T.TomoError):
+            T.tomo_pack_labels(ctx, torch.zeros(10, dtype=torch.uint8, device="cuda"), bits)
+    with pytest.raises(T.TomoError):
+        T.tomo_project(ctx, to_dev(np.zeros(2), torch.float64),
+                       torch.zeros((4097, 4097), dtype=torch.float32, device="cuda"), 5800)
+    with pytest.raises(T.TomoError):
+        T.admm_local_update(ctx, T.make_nodes([]), 1)
+    with pytest.raises(T.TomoError):
+        T.admm_consensus(ctx, T.make_nodes([]), T.TOMO_XUPDATE_SEGMENT, 1)
+    labels, cents = T.quantize_kmeans(ctx, b, 4)
+    torch.cuda.synchronize()
+    assert int(labels.max()) < 4 and torch.isfinite(cents).all()
+    got = T.tomo_project(ctx, to_dev(np.array([0.3]), torch.float64), to_dev(np.ones((8, 8), np.float32)), 12)
+    torch.cuda.synchronize()
+    assert torch.isfinite(got).all() and float(got.sum()) > 0
+
+
 def test_node_list_errors_are_reported(T, ctx):
     """Segments of one slice that overlap, and distinct slice ids that share x,
     are rejected before anything is launched (the consensus writes all
