@@ -189,7 +189,15 @@ __device__ void bucket_scan(KMShared& sh, int B) {
   __syncthreads();
   int ec = ic - ct;
   long long es = is - st;
-  for (int q = 0; q < w; ++q) { ec += sh.wcnt[q]; es += sh.wsum[q]; }
+  // the totals of the waves below: all of them read at once, those at or
+  // above this wave masked (integer adds, exact in any order)
+#pragma unroll
+  for (int q = 0; q < KWAVES; ++q) {
+    const int cq = sh.wcnt[q];
+    const long long sq = sh.wsum[q];
+    ec += q < w ? cq : 0;
+    es += q < w ? sq : 0;
+  }
 #pragma unroll
   for (int r = 0; r < KPER; ++r) {
     const int b = tid * KPER + r;
