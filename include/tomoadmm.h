@@ -141,7 +141,9 @@ int tomo_project(tomo_ctx* ctx, tomo_geom g, const double* angles, int32_t n_ang
 /*
  * Matched backprojection, the exact transpose of tomo_project:
  *   image = alpha * P^T sino + beta * image
- * (image is not read when beta == 0).  Same layouts as tomo_project.
+ * (image is not read when beta == 0).  Same layouts as tomo_project.  With
+ * n_ang == 0 the sinogram is empty and P^T sino is zero: image = beta * image
+ * (zeros when beta == 0); angles and sino may then be null.
  */
 int tomo_backproject(tomo_ctx* ctx, tomo_geom g, const double* angles, int32_t n_ang,
                      const float* sino, float* image, float alpha, float beta, void* stream);

@@ -454,6 +454,22 @@ def test_empty_and_out_of_range_sizes(T, ctx):
     assert torch.isfinite(got).all() and float(got.sum()) > 0
 
 
+def test_zero_angles(T, ctx):
+    """No angles: projecting writes nothing, and backprojecting an empty
+    sinogram gives alpha * 0 + beta * image (zeros when beta is 0)."""
+    n, nb = 40, 57
+    empty_ang = torch.zeros(0, dtype=torch.float64, device="cuda")
+    sino = T.tomo_project(ctx, empty_ang, to_dev(np.ones((n, n), np.float32)), nb)
+    assert tuple(sino.shape) == (0, nb)
+    base = np.random.default_rng(3).standard_normal((n, n)).astype(np.float32)
+    empty_sino = torch.zeros((0, nb), dtype=torch.float32, device="cuda")
+    out = to_dev(base)
+    T.tomo_backproject(ctx, empty_ang, empty_sino, n, out=out, alpha=3.0, beta=0.5)
+    assert np.array_equal(out.cpu().numpy(), (np.float32(0.5) * base).astype(np.float32))
+    got = T.tomo_backproject(ctx, empty_ang, empty_sino, n)
+    assert not got.cpu().numpy().any()
+
+
 def test_node_list_errors_are_reported(T, ctx):
     """Segments of one slice that overlap, and distinct slice ids that share x,
     are rejected before anything is launched (the consensus writes all
