@@ -231,6 +231,25 @@ def test_kmeans_bit_exact(T, ctx, n, k, dist):
     assert int(iters.item()) == ref.iters
 
 
+@pytest.mark.parametrize("n,k,max_iter", [(16384, 8, 0), (16384, 8, 1), (16384, 8, 2), (70000, 16, 0),
+                                           (70000, 16, 3), (3000, 100, 1)])
+def test_kmeans_lloyd_caps_bit_exact(T, ctx, n, k, max_iter):
+    """Lloyd caps below convergence (0 = the uniform quantizer's cells, then
+    one to three updates), register-resident, workspace and all-wave paths:
+    labels, centres, values and the iteration count equal the oracle's."""
+    log(f"case kmeans cap n={n} k={k} max_iter={max_iter}")
+    rng = np.random.default_rng(n + 31 * k + max_iter)
+    a = _km_input(n, "mixture", rng)
+    ref = kmeans_quantize(a, k, max_iter)
+    a_hat = torch.empty(n, dtype=torch.float32, device="cuda")
+    iters = torch.zeros(1, dtype=torch.int32, device="cuda")
+    labels, cent = T.quantize_kmeans(ctx, to_dev(a), k, max_iter, a_hat=a_hat, iters=iters)
+    np.testing.assert_array_equal(labels.cpu().numpy(), ref.labels)
+    np.testing.assert_array_equal(cent.cpu().numpy().view(np.uint32), ref.centroids.view(np.uint32))
+    np.testing.assert_array_equal(a_hat.cpu().numpy(), ref.a_hat)
+    assert int(iters.item()) == ref.iters
+
+
 def test_kmeans_in_place_and_nonfinite(T, ctx):
     rng = np.random.default_rng(3)
     a = rng.standard_normal(2000).astype(np.float32)
