@@ -295,6 +295,39 @@ def test_dct_codec(T, ctx, rows, cols, q):
     assert rel_l2(a_hat[clean], ref.a_hat[clean]) <= 1e-5
 
 
+@pytest.mark.parametrize("kind", ["constant", "zeros", "quality1", "one_spike"])
+def test_dct_degenerate_segments(T, ctx, kind):
+    """Degenerate inputs of the codec: a constant segment (hi == lo) and an
+    all-zero one are sent as they are with all codes zero; quality 1 (the
+    coarsest table, steps clamped at 255) and a single spike in a zero field
+    (lo and hi from one value) match the oracle's codes and values."""
+    log(f"case dct degenerate {kind}")
+    rows, cols, q = 16, 24, 50
+    if kind == "constant":
+        a = np.full((rows, cols), -2.75, np.float32)
+    elif kind == "zeros":
+        a = np.zeros((rows, cols), np.float32)
+    elif kind == "quality1":
+        a = np.random.default_rng(5).standard_normal((rows, cols)).astype(np.float32)
+        q = 1
+    else:
+        a = np.zeros((rows, cols), np.float32)
+        a[5, 11] = 3.5
+    ref = odct.dct_quantize(a, q)
+    coeffs = torch.empty((rows, cols), dtype=torch.int16, device="cuda")
+    lohi = torch.empty(2, dtype=torch.float32, device="cuda")
+    a_hat = T.quantize_dct(ctx, to_dev(a), q, coeffs=coeffs, lohi=lohi).cpu().numpy()
+    np.testing.assert_array_equal(lohi.cpu().numpy(), [a.min(), a.max()])
+    got = coeffs.cpu().numpy()
+    if kind in ("constant", "zeros"):
+        assert not got.any()
+        np.testing.assert_array_equal(a_hat, a)
+        return
+    diff = got.astype(np.int64) != ref.coeffs.astype(np.int64)
+    assert not diff.any(), int(diff.sum())
+    assert rel_l2(a_hat, ref.a_hat) <= 1e-5
+
+
 def test_dct_rejects_bad_shapes(T, ctx):
     with pytest.raises(T.TomoError):
         T.quantize_dct(ctx, to_dev(np.zeros((12, 16), np.float32)), 50)
